@@ -1,0 +1,168 @@
+"""Plain FP64 CPU oracle for the multipolar-Ewald QM/MM coupling (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  It compiles ``ewald_oracle.c`` with gcc (no code shared
+with the HIP library) and exposes :func:`oracle_ewald`.
+
+Conventions (paper: SI "Multipolar Ewald"; main text, periodic QM/MM energy):
+  * positions in length units (Angstrom in the workloads), charges in e,
+    Coulomb constant 1, so energies come out in e^2/Angstrom;
+  * theta is the raw second moment, stored as (xx, xy, xz, yy, yz, zz);
+  * phi, dphi, hphi are the MM-generated Ewald potential, its gradient and
+    one half of its Hessian at each QM site;
+  * g_* are derivatives of the total energy E = E_QMMM + E_QQ; g_theta is the
+    derivative with respect to the six stored numbers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ewald_oracle.c")
+_LIB = os.path.join(_HERE, "libewald_oracle.so")
+
+ENERGY_NAMES = ("total", "qmmm_sr", "qmmm_lr", "qmmm_bg", "qq_sr", "qq_lr", "qq_self", "qq_bg")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double * 3),
+        ("alpha", ctypes.c_double),
+        ("rcut", ctypes.c_double),
+        ("kmax", ctypes.c_int * 3),
+        ("qmqm", ctypes.c_int),
+    ]
+
+
+def build(src: str = _SRC, out: str = _LIB, extra_flags: tuple = ()) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, generic x86-64)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-fno-fast-math",
+           "-ffp-contract=off", *extra_flags, "-o", out + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+_lib_cache: dict = {}
+
+
+def load(path: str = _LIB) -> ctypes.CDLL:
+    if path in _lib_cache:
+        return _lib_cache[path]
+    if not os.path.exists(path) or (path == _LIB and os.path.getmtime(path) < os.path.getmtime(_SRC)):
+        if path != _LIB:
+            raise FileNotFoundError(path)
+        build()
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_ewald.restype = ctypes.c_int
+    lib.oracle_ewald.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp,
+                                 dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp, dp]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib_cache[path] = lib
+    return lib
+
+
+def num_threads() -> int:
+    return int(load().oracle_num_threads())
+
+
+@dataclass
+class OracleResult:
+    energy: dict
+    phi: np.ndarray        # (nq,)
+    dphi: np.ndarray       # (nq,3)   grad phi
+    hphi: np.ndarray       # (nq,6)   1/2 grad grad phi
+    g_qm_pos: np.ndarray   # (nq,3)   dE/dR_qm
+    g_Q: np.ndarray        # (nq,)
+    g_mu: np.ndarray       # (nq,3)
+    g_theta: np.ndarray    # (nq,6)   w.r.t. stored numbers
+    g_mm_pos: np.ndarray   # (nsel,3) dE/dR_mm
+    g_mm_q: np.ndarray     # (nsel,)
+    mm_sel: np.ndarray | None
+
+    @property
+    def E(self) -> float:
+        return self.energy["total"]
+
+    @property
+    def efield(self) -> np.ndarray:
+        return -self.dphi
+
+    @property
+    def efgrad(self) -> np.ndarray:
+        """-grad grad phi in (xx,xy,xz,yy,yz,zz) order."""
+        return -2.0 * self.hphi
+
+
+def _c(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def oracle_ewald(box, alpha, rcut, kmax, qm_pos, Q, mu, theta, mm_pos, q, qmqm=True, mm_sel=None,
+                 lib_path: str | None = None) -> OracleResult:
+    """Evaluate the truncated Ewald sums for the given parameters.
+
+    box: (3,) orthorhombic edges; kmax: int or (3,) per-axis |n| limit;
+    qm_pos (nq,3), Q (nq,), mu (nq,3), theta (nq,6); mm_pos (nm,3), q (nm,).
+    mm_sel: optional indices of MM atoms whose gradients are wanted.
+    """
+    lib = load(lib_path) if lib_path else load()
+    qm_pos = _c(qm_pos).reshape(-1, 3)
+    nq = qm_pos.shape[0]
+    Q = _c(Q, (nq,))
+    mu = _c(mu, (nq, 3))
+    theta = _c(theta, (nq, 6))
+    mm_pos = _c(mm_pos).reshape(-1, 3)
+    nm = mm_pos.shape[0]
+    q = _c(q, (nm,))
+    if np.isscalar(kmax):
+        kmax = (int(kmax),) * 3
+    p = _Params()
+    p.box[:] = [float(b) for b in box]
+    p.alpha = float(alpha)
+    p.rcut = float(rcut)
+    p.kmax[:] = [int(k) for k in kmax]
+    p.qmqm = 1 if qmqm else 0
+    if mm_sel is None:
+        nsel = nm
+        sel_arg = None
+        sel_n = -1
+    else:
+        sel = np.ascontiguousarray(np.asarray(mm_sel, dtype=np.int32))
+        if sel.size and (sel.min() < 0 or sel.max() >= nm):
+            raise IndexError("mm_sel out of range")
+        nsel = sel.size
+        sel_arg = sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        sel_n = nsel
+    energy = np.zeros(len(ENERGY_NAMES))
+    phi = np.zeros(nq)
+    dphi = np.zeros((nq, 3))
+    hphi = np.zeros((nq, 6))
+    gq = np.zeros((nq, 3))
+    gQ = np.zeros(nq)
+    gmu = np.zeros((nq, 3))
+    gth = np.zeros((nq, 6))
+    gm = np.zeros((max(nsel, 0), 3))
+    gmq = np.zeros(max(nsel, 0))
+    rc = lib.oracle_ewald(ctypes.byref(p), nq, _ptr(qm_pos), _ptr(Q), _ptr(mu), _ptr(theta), nm, _ptr(mm_pos),
+                          _ptr(q), _ptr(energy), _ptr(phi), _ptr(dphi), _ptr(hphi), _ptr(gq), _ptr(gQ), _ptr(gmu),
+                          _ptr(gth), sel_n, sel_arg, _ptr(gm), _ptr(gmq))
+    if rc != 0:
+        raise ValueError(f"oracle_ewald rejected its arguments (status {rc})")
+    return OracleResult(energy=dict(zip(ENERGY_NAMES, energy.tolist())), phi=phi, dphi=dphi, hphi=hphi,
+                        g_qm_pos=gq, g_Q=gQ, g_mu=gmu, g_theta=gth, g_mm_pos=gm, g_mm_q=gmq,
+                        mm_sel=None if mm_sel is None else np.asarray(mm_sel))
