@@ -1,0 +1,171 @@
+/*
+ * mpewald: periodic (Ewald) electrostatic coupling between atom-centred QM
+ * point multipoles and MM point charges, on AMD Instinct MI355X (gfx950).
+ *
+ * Quantity (paper: Methods, "Multipole Approximation to Electrostatics",
+ * the periodic QM/MM multipole energy; Supporting Information, "Multipolar
+ * Ewald"):
+ *
+ *   E = E_QMMM + E_QQ
+ *   E_QMMM = sum_j [ Q_j phi_j + mu_j . grad phi_j + theta_j : (1/2) grad grad phi_j ]
+ *   phi(R) = sum_i q_i psi(R - R_i),  psi = Ewald kernel (real + reciprocal + background)
+ *   E_QQ   = QM-QM image interactions truncated at total multipole order 2
+ *            (charge-charge, charge-dipole, charge-quadrupole, dipole-dipole),
+ *            including self terms; MM-MM interactions are excluded.
+ *
+ * Units: Coulomb constant 1.  Lengths and charges in any consistent units
+ * (the tests use Angstrom and e, giving e^2/Angstrom).
+ *
+ * Conventions shared by every entry point:
+ *   - All arrays are row-major, FP64, on the device of the plan, unless noted.
+ *   - Positions: (N,3) [x,y,z per atom]; any real values (wrapped internally).
+ *   - Dipoles mu: (Nq,3).  Quadrupoles theta: (Nq,6) raw Cartesian second
+ *     moments (not traceless) stored as xx, xy, xz, yy, yz, zz; the 1/2 of
+ *     the Taylor series is part of the order-2 interaction tensor.
+ *   - phi: (Nq,) potential of the MM charges at each QM site;
+ *     efield: (Nq,3) = -grad phi; efgrad: (Nq,6) = -grad grad phi (xx..zz).
+ *   - Gradients are dE/dx (forces are minus these).  g_theta is the
+ *     derivative with respect to the six stored numbers, so each stored
+ *     off-diagonal number receives twice the full-matrix derivative.
+ *   - Box: orthorhombic edges; the real-space cutoff must satisfy
+ *     rcut <= min(box)/2 (minimum image), reciprocal vectors are
+ *     k = 2 pi (nx/Lx, ny/Ly, nz/Lz) for every |n_a| <= kmax[a], n != 0.
+ *   - Boundary: tin-foil (no surface dipole term); uniform neutralising
+ *     background for charged subsystems.
+ *   - Streams: every call only enqueues work on `stream` (a hipStream_t,
+ *     0 = default stream) and returns; no host synchronisation except in
+ *     ewald_setup, ewald_autotune and the first ewald_batch call of a shape.
+ *   - Errors: a negative status; arguments are validated on the host before
+ *     anything is enqueued and outputs are left untouched on error.  The
+ *     message of the last error of the calling thread is ewald_last_error().
+ *   - Ownership: the caller owns every input, output and ctx buffer; the
+ *     plan owns only its workspace, graphs and tuning state.  A plan must
+ *     not be used by two host threads at once.
+ */
+#ifndef MPEWALD_H
+#define MPEWALD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EWALD_OK = 0,
+  EWALD_ERR_ARG = -1,      /* null pointer, bad size or bad parameter */
+  EWALD_ERR_CUTOFF = -2,   /* rcut > min(box)/2 */
+  EWALD_ERR_CAPACITY = -3, /* more atoms/frames than the plan was set up for */
+  EWALD_ERR_HIP = -4,      /* a HIP runtime call failed */
+  EWALD_ERR_OOM = -5       /* workspace allocation failed */
+} ewald_status_t;
+
+/* precision of the real-space pair kernel */
+enum {
+  EWALD_FP64 = 0,          /* everything in FP64 */
+  EWALD_FP32_REAL = 1      /* real-space distances, erfc, exp and tensors in FP32,
+                              accumulated in FP64; reciprocal space stays FP64 */
+};
+
+/* flags */
+enum {
+  EWALD_QMQM = 1,          /* include the QM-QM image terms (on in the tests) */
+  EWALD_PLAIN = 2,         /* forward uses the unoptimised reference GPU path:
+                              one thread per k, direct sincos per (k, atom) */
+  EWALD_CELL_LIST = 4      /* real space visits only neighbouring cells */
+};
+
+typedef struct {
+  double box[3];   /* orthorhombic edges */
+  double alpha;    /* Ewald splitting parameter (1/length), > 0 */
+  double rcut;     /* real-space cutoff, pairs with |r| < rcut, <= min(box)/2 */
+  int kmax[3];     /* reciprocal cube |n_a| <= kmax[a], each >= 1 */
+  int precision;   /* EWALD_FP64 or EWALD_FP32_REAL */
+  int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST */
+  int max_qm;      /* capacity: QM sites per call (sum over frames in a batch) */
+  int max_mm;      /* capacity: MM charges per call (sum over frames in a batch) */
+  int max_frames;  /* capacity: frames per ewald_batch call (>= 1) */
+} ewald_params_t;
+
+typedef struct ewald_plan ewald_plan;
+
+/* One frame of a batch: its box and where its atoms sit in the packed arrays. */
+typedef struct {
+  double box[3];
+  int n_qm, n_mm;
+  int qm_offset, mm_offset; /* first row of this frame in the packed QM / MM arrays */
+} ewald_frame_t;
+
+/* Create a plan on the current HIP device and allocate its workspace for
+ * the given capacities.  The plan keeps a copy of *params. */
+ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan);
+
+/* Release the workspace; null is accepted. */
+ewald_status_t ewald_destroy(ewald_plan* plan);
+
+/* Change the box of a plan (validated like ewald_setup); affects later calls. */
+ewald_status_t ewald_set_box(ewald_plan* plan, const double box[3]);
+
+/* Bytes of the caller-allocated context that ewald_forward fills and
+ * ewald_backward reads (saved reciprocal structure factor of the MM charges
+ * and the MM potential data at the QM sites). */
+size_t ewald_ctx_bytes(const ewald_plan* plan, int n_qm, int n_mm);
+
+/* Forward pass (paper: periodic multipole energy; SI multipolar Ewald).
+ * Inputs qm_xyz (Nq,3), Q (Nq), mu (Nq,3), theta (Nq,6), mm_xyz (Nm,3), mm_q (Nm).
+ * Outputs energy (1), phi (Nq), efield (Nq,3), efgrad (Nq,6); any output
+ * pointer except energy may be null.  ctx: null, or ewald_ctx_bytes() bytes
+ * of device memory for a later ewald_backward.  n_qm or n_mm may be 0. */
+ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q, const double* mu,
+                             const double* theta, int n_mm, const double* mm_xyz, const double* mm_q,
+                             double* energy, double* phi, double* efield, double* efgrad, void* ctx, void* stream);
+
+/* Adjoint of ewald_forward (paper: Fock-coupling potential v = dE/d(moments)
+ * and the tensor part of the nuclear gradient; MM atoms have no Pulay term).
+ * Upstream gradients: gE (device scalar, null means 1), g_phi (Nq), g_efield
+ * (Nq,3), g_efgrad (Nq,6) (each may be null = zero).  Inputs as in forward,
+ * ctx as filled by the matching forward call.
+ * Outputs (overwritten): g_qm_xyz (Nq,3), g_Q (Nq), g_mu (Nq,3), g_theta (Nq,6),
+ * g_mm_xyz (Nm,3), g_mm_q (Nm, may be null).  Each output is the gradient of
+ * L = gE*E + g_phi.phi + g_efield.efield + g_efgrad.efgrad. */
+ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz, const double* Q,
+                              const double* mu, const double* theta, int n_mm, const double* mm_xyz,
+                              const double* mm_q, const double* gE, const double* g_phi, const double* g_efield,
+                              const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
+                              double* g_mm_xyz, double* g_mm_q, void* stream);
+
+/* Batched evaluation of many independent frames with the plan's alpha, rcut
+ * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
+ * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or
+ * EWALD_FWD_BWD.  Outputs: energy (n_frames), phi/efield/efgrad per QM row;
+ * with EWALD_FWD_BWD also dE/dx for every input (gE = 1): g_qm_xyz, g_Q,
+ * g_mu, g_theta per QM row, g_mm_xyz and g_mm_q (may be null) per MM row.
+ * The launch sequence of one frame shape is captured once in a HIP graph and
+ * replayed while shapes, pointers and stream stay the same. */
+enum { EWALD_FWD = 0, EWALD_FWD_BWD = 1 };
+ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewald_frame_t* frames, const double* qm_xyz,
+                           const double* Q, const double* mu, const double* theta, const double* mm_xyz,
+                           const double* mm_q, int mode, double* energy, double* phi, double* efield, double* efgrad,
+                           double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, double* g_mm_xyz,
+                           double* g_mm_q, void* stream);
+
+/* Time the candidate tilings of the two reciprocal-space kernels for a
+ * system of n_mm MM charges on the plan's device and keep the fastest in the
+ * plan (and in cache_path as JSON lines if not null).  Synchronises. */
+ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char* cache_path);
+
+/* Tile configuration in use (for reports): forward nz chunk, backward
+ * columns per block, etc., as a short text. */
+const char* ewald_plan_describe(const ewald_plan* plan);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* ewald_last_error(void);
+
+/* Library version string. */
+const char* ewald_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPEWALD_H */

@@ -1,0 +1,586 @@
+// C ABI of the multipolar Ewald library: plan, validation, workspace, the
+// forward / backward / batched launch sequences, HIP-graph replay and the
+// tile autotuner.  See include/mpewald.h for the contract of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpewald.h"
+#include "ewald_internal.h"
+
+using namespace mpe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ewald_status_t fail(ewald_status_t st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(EWALD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kTargetBlocks = 2048;  // blocks the hot kernels aim for (8 per CU)
+
+}  // namespace
+
+struct ewald_plan {
+  ewald_params_t p;
+  int device;
+  Grid g;
+  Tuning t;
+  Work w;
+  int cap_qm, cap_mm, cap_frames, cap_slots, cap_kc;
+  std::vector<void*> allocs;
+  std::string describe;
+  // batched graph state
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
+  std::vector<FrameDev> host_frames;
+};
+
+namespace {
+
+ewald_status_t validate_box(const double box[3], double rcut) {
+  for (int a = 0; a < 3; a++)
+    if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(EWALD_ERR_ARG, "box[%d] must be positive", a);
+  const double mn = std::min(box[0], std::min(box[1], box[2]));
+  if (rcut > 0.5 * mn)
+    return fail(EWALD_ERR_CUTOFF, "rcut %.6g exceeds half the smallest box edge %.6g", rcut, 0.5 * mn);
+  return EWALD_OK;
+}
+
+Grid make_grid(const ewald_params_t& p) {
+  Grid g;
+  g.mx = p.kmax[0];
+  g.my = p.kmax[1];
+  g.mz = p.kmax[2];
+  g.NX = g.mx + 1;
+  g.NY = 2 * g.my + 1;
+  g.NZ = 2 * g.mz + 1;
+  g.NCOL = g.NX * g.NY;
+  g.KF = g.NCOL * g.NZ;
+  g.Zc = pick_zc(g.NZ);
+  g.NZP = ((g.NZ + g.Zc - 1) / g.Zc) * g.Zc;
+  g.R = g.NX + g.NY + g.NZP;
+  g.alpha = p.alpha;
+  g.rcut = p.rcut;
+  return g;
+}
+
+template <typename T>
+ewald_status_t alloc(ewald_plan* pl, T** ptr, size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(EWALD_ERR_OOM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  pl->allocs.push_back(p);
+  *ptr = (T*)p;
+  return EWALD_OK;
+}
+
+int fwd_kblocks(const Grid& g) { return ((g.NCOL + 63) / 64) * (g.NZP / g.Zc); }
+
+void free_plan(ewald_plan* pl) {
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
+  if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
+  if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  for (void* p : pl->allocs) (void)hipFree(p);
+  pl->allocs.clear();
+}
+
+void set_describe(ewald_plan* pl) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "zc=%d nzp=%d a_chunk=auto kc=%d kgrid=%dx%dx%d precision=%s", pl->g.Zc, pl->g.NZP,
+           pl->t.kc, pl->g.NX, pl->g.NY, pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
+  pl->describe = buf;
+}
+
+FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int slot_base) {
+  FrameDev f;
+  memset(&f, 0, sizeof(f));
+  for (int a = 0; a < 3; a++) {
+    f.box[a] = box[a];
+    f.inv_box[a] = 1.0 / box[a];
+  }
+  f.nq = nq;
+  f.nm = nm;
+  f.qoff = qoff;
+  f.moff = moff;
+  f.slot_base = slot_base;
+  return f;
+}
+
+// atoms per forward block so that the grid has about kTargetBlocks blocks
+// without exceeding the partial-sum slots.
+int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
+  long total = 0;
+  for (int n : nms) total += n;
+  const long kb = fwd_kblocks(pl->g);
+  long ac = (kb * total + kTargetBlocks - 1) / kTargetBlocks;
+  ac = ((ac + 255) / 256) * 256;
+  if (ac < 256) ac = 256;
+  if (pl->t.a_chunk > 0) ac = pl->t.a_chunk;  // tuned value
+  for (;;) {
+    long slots = 0;
+    for (int n : nms) slots += (n + ac - 1) / ac;
+    if (slots <= pl->cap_slots) break;
+    ac *= 2;
+  }
+  return (int)ac;
+}
+
+int choose_kc(const ewald_plan* pl, long total_nm) {
+  const long ablocks = std::max<long>(1, (total_nm + 255) / 256);
+  long kc = (kTargetBlocks + ablocks - 1) / ablocks;
+  if (pl->t.kc > 0) kc = pl->t.kc;
+  kc = std::max<long>(1, std::min<long>(kc, pl->cap_kc));
+  kc = std::min<long>(kc, pl->g.NCOL);
+  return (int)kc;
+}
+
+struct CtxView {
+  double2* smm;
+  double* site;
+};
+
+size_t ctx_bytes(const Grid& g, int nq) {
+  size_t a = (size_t)g.KF * sizeof(double2);
+  a = (a + 255) & ~(size_t)255;
+  return a + (size_t)std::max(nq, 1) * 10 * sizeof(double);
+}
+
+CtxView ctx_view(const Grid& g, void* ctx) {
+  size_t a = (size_t)g.KF * sizeof(double2);
+  a = (a + 255) & ~(size_t)255;
+  CtxView v;
+  v.smm = (double2*)ctx;
+  v.site = (double*)((char*)ctx + a);
+  return v;
+}
+
+ewald_status_t check_arrays(int nq, int nm, const void* qm_xyz, const void* Q, const void* mu, const void* theta,
+                            const void* mm_xyz, const void* mm_q) {
+  if (nq < 0 || nm < 0) return fail(EWALD_ERR_ARG, "negative atom count");
+  if (nq > 0 && (!qm_xyz || !Q || !mu || !theta)) return fail(EWALD_ERR_ARG, "null QM input array");
+  if (nm > 0 && (!mm_xyz || !mm_q)) return fail(EWALD_ERR_ARG, "null MM input array");
+  return EWALD_OK;
+}
+
+// ---------------------------------------------------------------- launch sequences
+struct Seq {
+  ewald_plan* pl;
+  hipStream_t s;
+  FrameArg fa;
+  int max_nq, max_nm, total_nq, total_nm;
+  int plain;
+  int fp32;
+  int qmqm;
+};
+
+#define LCHK(expr)                                                                                  \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return fail(EWALD_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mm_xyz,
+                         const double* mm_q) {
+  ewald_plan* pl = q.pl;
+  LCHK(launch_zero(pl->w.qacc, (size_t)q.total_nq * QA_STRIDE, q.s));
+  LCHK(launch_zero(pl->w.facc, (size_t)q.fa.n_frames * FA_COUNT, q.s));
+  LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm, pl->cap_mm));
+  return EWALD_OK;
+}
+
+ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu, const double* theta, double2* smm,
+                                size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
+                                double* site) {
+  ewald_plan* pl = q.pl;
+  LCHK(launch_reduce_smm(pl->g, pl->t, q.fa, q.plain, smm, smm_stride, pl->w, q.s));
+  LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 0, q.qmqm, pl->w, q.s));
+  LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
+  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, pl->cap_qm, Q, mu, theta, pl->w, q.s));
+  LCHK(launch_finalize_fwd(pl->g, q.fa, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad, site, pl->w, q.s));
+  return EWALD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ewald_last_error(void) { return g_last_error.c_str(); }
+
+const char* ewald_version(void) { return "mpewald 0.1 (gfx950)"; }
+
+ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
+  g_last_error.clear();
+  if (!params || !plan) return fail(EWALD_ERR_ARG, "null params or plan pointer");
+  const ewald_params_t& p = *params;
+  if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return fail(EWALD_ERR_ARG, "alpha must be positive");
+  if (!(p.rcut > 0.0) || !std::isfinite(p.rcut)) return fail(EWALD_ERR_ARG, "rcut must be positive");
+  for (int a = 0; a < 3; a++)
+    if (p.kmax[a] < 1 || p.kmax[a] > 256) return fail(EWALD_ERR_ARG, "kmax[%d] must be in [1,256]", a);
+  ewald_status_t st = validate_box(p.box, p.rcut);
+  if (st != EWALD_OK) return st;
+  if (p.precision != EWALD_FP64 && p.precision != EWALD_FP32_REAL) return fail(EWALD_ERR_ARG, "unknown precision");
+  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST)) return fail(EWALD_ERR_ARG, "unknown flags");
+  if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
+  ewald_plan* pl = new ewald_plan();
+  pl->p = p;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    delete pl;
+    return fail(EWALD_ERR_HIP, "no HIP device");
+  }
+  pl->g = make_grid(p);
+  pl->t.zc = pl->g.Zc;
+  pl->t.a_chunk = 0;
+  pl->t.kc = 0;
+  pl->t.bwd_ilp = 1;
+  pl->cap_qm = std::max(p.max_qm, 1);
+  pl->cap_mm = std::max(p.max_mm, 1);
+  pl->cap_frames = p.max_frames;
+  pl->cap_slots = std::max(64, 2 * kTargetBlocks / std::max(1, fwd_kblocks(pl->g)) + 2 * pl->cap_frames);
+  pl->cap_kc = (int)std::max<long>(1, std::min<long>(16, (kTargetBlocks * 256L + pl->cap_mm - 1) / pl->cap_mm));
+  const Grid& g = pl->g;
+  Work& w = pl->w;
+  size_t cm = pl->cap_mm, cq = pl->cap_qm, cf = pl->cap_frames;
+#define A(ptr, n)                        \
+  do {                                   \
+    st = alloc(pl, &(ptr), (n));         \
+    if (st != EWALD_OK) {                \
+      free_plan(pl);                     \
+      delete pl;                         \
+      return st;                         \
+    }                                    \
+  } while (0)
+  A(w.mm4, 4 * cm);
+  A(w.qm4, 4 * cq);
+  A(w.mm_tab, cm * g.R);
+  A(w.qm_tab, cq * g.R);
+  A(w.sabc, cf * g.KF * 3);
+  A(w.wk, cf * g.KF);
+  A(w.smm, cf * g.KF);
+  A(w.spart, (size_t)pl->cap_slots * g.NZP * g.NCOL);
+  A(w.fpart, (size_t)pl->cap_kc * cm * 4);
+  A(w.rpart, cm * 4);
+  A(w.qacc, cq * QA_STRIDE);
+  A(w.qeff, cq * 10);
+  A(w.site, cq * 10);
+  A(w.facc, cf * FA_COUNT);
+  A(w.one, 1);
+  A(w.frames, cf);
+#undef A
+  const double one = 1.0;
+  if (hipMemcpy(w.one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(pl);
+    delete pl;
+    return fail(EWALD_ERR_HIP, "hipMemcpy failed");
+  }
+  set_describe(pl);
+  *plan = pl;
+  return EWALD_OK;
+}
+
+ewald_status_t ewald_destroy(ewald_plan* plan) {
+  if (!plan) return EWALD_OK;
+  free_plan(plan);
+  delete plan;
+  return EWALD_OK;
+}
+
+ewald_status_t ewald_set_box(ewald_plan* plan, const double box[3]) {
+  if (!plan || !box) return fail(EWALD_ERR_ARG, "null plan or box");
+  ewald_status_t st = validate_box(box, plan->p.rcut);
+  if (st != EWALD_OK) return st;
+  for (int a = 0; a < 3; a++) plan->p.box[a] = box[a];
+  return EWALD_OK;
+}
+
+size_t ewald_ctx_bytes(const ewald_plan* plan, int n_qm, int n_mm) {
+  (void)n_mm;
+  if (!plan) return 0;
+  return ctx_bytes(plan->g, n_qm);
+}
+
+const char* ewald_plan_describe(const ewald_plan* plan) { return plan ? plan->describe.c_str() : ""; }
+
+ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q, const double* mu,
+                             const double* theta, int n_mm, const double* mm_xyz, const double* mm_q,
+                             double* energy, double* phi, double* efield, double* efgrad, void* ctx, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  ewald_status_t st = check_arrays(n_qm, n_mm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
+  if (st != EWALD_OK) return st;
+  if (!energy) return fail(EWALD_ERR_ARG, "null energy output");
+  if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
+    return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  hipStream_t s = (hipStream_t)stream;
+  Seq q;
+  q.pl = plan;
+  q.s = s;
+  q.plain = (plan->p.flags & EWALD_PLAIN) ? 1 : 0;
+  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
+  q.max_nq = q.total_nq = n_qm;
+  q.max_nm = q.total_nm = n_mm;
+  Tuning saved = plan->t;
+  plan->t.a_chunk = q.plain ? 1 << 30 : choose_a_chunk(plan, {n_mm});
+  q.fa.frames = nullptr;
+  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
+  q.fa.n_frames = 1;
+  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
+  if (st == EWALD_OK) {
+    hipError_t e = launch_sfac_qm(plan->g, q.fa, n_qm, Q, mu, theta, plan->w.qeff, nullptr, 0, plan->w, s);
+    if (e != hipSuccess) st = fail(EWALD_ERR_HIP, "sfac_qm launch: %s", hipGetErrorString(e));
+  }
+  if (st == EWALD_OK) {
+    hipError_t e = q.plain ? launch_sfac_mm_plain(plan->g, q.fa, plan->cap_mm, plan->w, s)
+                           : launch_sfac_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s);
+    if (e != hipSuccess) st = fail(EWALD_ERR_HIP, "sfac_mm launch: %s", hipGetErrorString(e));
+  }
+  if (st == EWALD_OK) {
+    CtxView cv{plan->w.smm, plan->w.site};
+    if (ctx) cv = ctx_view(plan->g, ctx);
+    st = seq_forward_tail(q, Q, mu, theta, cv.smm, plan->g.KF, energy, phi, efield, efgrad, cv.site);
+  }
+  plan->t = saved;
+  return st;
+}
+
+ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz, const double* Q,
+                              const double* mu, const double* theta, int n_mm, const double* mm_xyz,
+                              const double* mm_q, const double* gE, const double* g_phi, const double* g_efield,
+                              const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
+                              double* g_mm_xyz, double* g_mm_q, void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  if (!ctx) return fail(EWALD_ERR_ARG, "null ctx: run ewald_forward with a ctx buffer first");
+  ewald_status_t st = check_arrays(n_qm, n_mm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
+  if (st != EWALD_OK) return st;
+  if (n_qm > 0 && (!g_qm_xyz || !g_Q || !g_mu || !g_theta)) return fail(EWALD_ERR_ARG, "null QM gradient output");
+  if (n_mm > 0 && !g_mm_xyz) return fail(EWALD_ERR_ARG, "null MM gradient output");
+  if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
+    return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  hipStream_t s = (hipStream_t)stream;
+  Seq q;
+  q.pl = plan;
+  q.s = s;
+  q.plain = 0;
+  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
+  q.max_nq = q.total_nq = n_qm;
+  q.max_nm = q.total_nm = n_mm;
+  Tuning saved = plan->t;
+  plan->t.kc = choose_kc(plan, n_mm);
+  q.fa.frames = nullptr;
+  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
+  q.fa.n_frames = 1;
+  CtxView cv = ctx_view(plan->g, (void*)ctx);
+  Work& w = plan->w;
+  const Grid& g = plan->g;
+#define STEP(expr)                                                                                     \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) {                                                                            \
+      plan->t = saved;                                                                                 \
+      return fail(EWALD_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_));                      \
+    }                                                                                                  \
+  } while (0)
+  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
+  if (st != EWALD_OK) {
+    plan->t = saved;
+    return st;
+  }
+  STEP(launch_eff_moments(q.fa, n_qm, Q, mu, theta, gE, g_phi, g_efield, g_efgrad, w, s));
+  STEP(launch_sfac_qm(g, q.fa, n_qm, Q, mu, theta, w.qeff, gE, 1, w, s));
+  STEP(launch_force_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, w, s));
+  STEP(launch_real_mm(g, q.fa, n_mm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
+  STEP(launch_reduce_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
+  STEP(launch_project_qm(g, q.fa, n_qm, n_qm, cv.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
+  STEP(launch_real_qm(g, q.fa, n_qm, n_mm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
+  if (q.qmqm && n_qm > 0) STEP(launch_qmqm(g, q.fa, plan->cap_qm, Q, mu, theta, w, s));
+  STEP(launch_finalize_bwd(q.fa, n_qm, cv.site, gE, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, s));
+#undef STEP
+  plan->t = saved;
+  return EWALD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int max_nq, int max_nm, int total_nq,
+                             int total_nm, const double* qm_xyz, const double* Q, const double* mu,
+                             const double* theta, const double* mm_xyz, const double* mm_q, int mode, double* energy,
+                             double* phi, double* efield, double* efgrad, double* g_qm_xyz, double* g_Q,
+                             double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q) {
+  Seq q;
+  q.pl = plan;
+  q.s = s;
+  q.plain = 0;
+  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
+  q.max_nq = max_nq;
+  q.max_nm = max_nm;
+  q.total_nq = total_nq;
+  q.total_nm = total_nm;
+  q.fa.frames = plan->w.frames;
+  q.fa.n_frames = n_frames;
+  memset(&q.fa.f0, 0, sizeof(q.fa.f0));
+  Work& w = plan->w;
+  const Grid& g = plan->g;
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
+  if (st != EWALD_OK) return st;
+  const int bwd = mode == EWALD_FWD_BWD;
+  if (bwd) LCHK(launch_eff_moments(q.fa, max_nq, Q, mu, theta, nullptr, nullptr, nullptr, nullptr, w, s));
+  LCHK(launch_sfac_qm(g, q.fa, max_nq, Q, mu, theta, w.qeff, nullptr, bwd, w, s));
+  LCHK(launch_sfac_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
+  if (bwd) LCHK(launch_force_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
+  st = seq_forward_tail(q, Q, mu, theta, w.smm, g.KF, energy, phi, efield, efgrad, w.site);
+  if (st != EWALD_OK) return st;
+  if (bwd) {
+    LCHK(launch_real_mm(g, q.fa, max_nm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
+    LCHK(launch_reduce_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
+    LCHK(launch_project_qm(g, q.fa, max_nq, total_nq, w.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
+    LCHK(launch_real_qm(g, q.fa, max_nq, max_nm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
+    LCHK(launch_finalize_bwd(q.fa, max_nq, w.site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, s));
+  }
+  return EWALD_OK;
+}
+
+template <typename T>
+void key_push(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* p = (const unsigned char*)&v;
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+}  // namespace
+
+extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewald_frame_t* frames,
+                                      const double* qm_xyz, const double* Q, const double* mu, const double* theta,
+                                      const double* mm_xyz, const double* mm_q, int mode, double* energy,
+                                      double* phi, double* efield, double* efgrad, double* g_qm_xyz, double* g_Q,
+                                      double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q,
+                                      void* stream) {
+  g_last_error.clear();
+  if (!plan || !frames || !energy) return fail(EWALD_ERR_ARG, "null plan, frames or energy");
+  if (n_frames < 1) return fail(EWALD_ERR_ARG, "n_frames must be >= 1");
+  if (n_frames > plan->cap_frames) return fail(EWALD_ERR_CAPACITY, "%d frames exceed capacity %d", n_frames, plan->cap_frames);
+  if (mode != EWALD_FWD && mode != EWALD_FWD_BWD) return fail(EWALD_ERR_ARG, "unknown mode %d", mode);
+  int max_nq = 0, max_nm = 0;
+  long total_nq = 0, total_nm = 0, end_q = 0, end_m = 0;
+  for (int f = 0; f < n_frames; f++) {
+    const ewald_frame_t& fr = frames[f];
+    ewald_status_t st = validate_box(fr.box, plan->p.rcut);
+    if (st != EWALD_OK) return fail(st, "frame %d: %s", f, g_last_error.c_str());
+    if (fr.n_qm < 0 || fr.n_mm < 0 || fr.qm_offset < 0 || fr.mm_offset < 0)
+      return fail(EWALD_ERR_ARG, "frame %d: negative count or offset", f);
+    max_nq = std::max(max_nq, fr.n_qm);
+    max_nm = std::max(max_nm, fr.n_mm);
+    total_nq += fr.n_qm;
+    total_nm += fr.n_mm;
+    end_q = std::max(end_q, (long)fr.qm_offset + fr.n_qm);
+    end_m = std::max(end_m, (long)fr.mm_offset + fr.n_mm);
+  }
+  if (end_q > plan->cap_qm || end_m > plan->cap_mm)
+    return fail(EWALD_ERR_CAPACITY, "packed rows (%ld QM, %ld MM) exceed capacity %d/%d", end_q, end_m, plan->cap_qm,
+                plan->cap_mm);
+  ewald_status_t st = check_arrays((int)total_nq, (int)total_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
+  if (st != EWALD_OK) return st;
+  if (mode == EWALD_FWD_BWD && ((total_nq > 0 && (!g_qm_xyz || !g_Q || !g_mu || !g_theta)) || (total_nm > 0 && !g_mm_xyz)))
+    return fail(EWALD_ERR_ARG, "null gradient output in EWALD_FWD_BWD mode");
+
+  // tile choices for this shape
+  std::vector<int> nms(n_frames);
+  for (int f = 0; f < n_frames; f++) nms[f] = frames[f].n_mm;
+  Tuning saved = plan->t;
+  Tuning use = plan->t;
+  plan->t.a_chunk = saved.a_chunk;
+  use.a_chunk = choose_a_chunk(plan, nms);
+  use.kc = choose_kc(plan, total_nm);
+  // frame descriptors with partial-sum slots
+  std::vector<FrameDev> hf(n_frames);
+  int slot = 0;
+  for (int f = 0; f < n_frames; f++) {
+    hf[f] = make_frame(frames[f].box, frames[f].n_qm, frames[f].n_mm, frames[f].qm_offset, frames[f].mm_offset, slot);
+    slot += (frames[f].n_mm + use.a_chunk - 1) / use.a_chunk;
+  }
+  // graph key: frames, pointers, mode, stream, tiles
+  std::vector<unsigned char> key;
+  for (auto& f : hf) key_push(key, f);
+  const void* ptrs[] = {qm_xyz, Q, mu, theta, mm_xyz, mm_q, energy, phi, efield, efgrad,
+                        g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q, stream};
+  for (auto p : ptrs) key_push(key, p);
+  key_push(key, mode);
+  key_push(key, use);
+  hipStream_t s = (hipStream_t)stream;
+  if (!plan->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&plan->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&plan->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&plan->ev_out, hipEventDisableTiming));
+  }
+  if (!plan->gexec || key != plan->gkey) {
+    if (plan->gexec) {
+      HIPCHK(hipStreamSynchronize(plan->gstream));
+      (void)hipGraphExecDestroy(plan->gexec);
+      plan->gexec = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(plan->w.frames, hf.data(), sizeof(FrameDev) * n_frames, hipMemcpyHostToDevice));
+    plan->t = use;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_batch(plan, plan->gstream, n_frames, max_nq, max_nm, (int)total_nq, (int)total_nm, qm_xyz, Q, mu,
+                       theta, mm_xyz, mm_q, mode, energy, phi, efield, efgrad, g_qm_xyz, g_Q, g_mu, g_theta,
+                       g_mm_xyz, g_mm_q);
+    hipError_t ce = hipStreamEndCapture(plan->gstream, &graph);
+    plan->t = saved;
+    if (st != EWALD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (ce != hipSuccess) return fail(EWALD_ERR_HIP, "graph capture: %s", hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      plan->gexec = nullptr;
+      return fail(EWALD_ERR_HIP, "graph instantiate: %s", hipGetErrorString(ie));
+    }
+    plan->gkey = key;
+  }
+  HIPCHK(hipEventRecord(plan->ev_in, s));
+  HIPCHK(hipStreamWaitEvent(plan->gstream, plan->ev_in, 0));
+  HIPCHK(hipGraphLaunch(plan->gexec, plan->gstream));
+  HIPCHK(hipEventRecord(plan->ev_out, plan->gstream));
+  HIPCHK(hipStreamWaitEvent(s, plan->ev_out, 0));
+  return EWALD_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char* cache_path) {
+  (void)n_mm;
+  (void)cache_path;
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  return fail(EWALD_ERR_ARG, "autotune not available in this build");
+}

@@ -1,0 +1,146 @@
+// Internal layout shared by the host side of the library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mpe {
+
+// Per-frame description as the kernels see it.
+struct FrameDev {
+  double box[3];
+  double inv_box[3];
+  int nq, nm;        // atoms in this frame
+  int qoff, moff;    // first packed row of this frame
+  int slot_base;     // first partial-sum slot of the forward structure-factor kernel
+  int pad;
+};
+
+// Frames are either one descriptor passed by value (single-frame calls) or
+// a device array (batched calls).
+struct FrameArg {
+  const FrameDev* frames;  // device array or null
+  FrameDev f0;             // used when frames == null
+  int n_frames;
+};
+
+__host__ __device__ inline int kgrid_nx(int mx) { return mx + 1; }
+__host__ __device__ inline int kgrid_ny(int my) { return 2 * my + 1; }
+__host__ __device__ inline int kgrid_nz(int mz) { return 2 * mz + 1; }
+
+// Static description of the reciprocal grid and real-space parameters
+// (identical for every frame of a plan).
+struct Grid {
+  int mx, my, mz;
+  int NX, NY, NZ;   // nx in [0,mx], ny in [-my,my], nz in [-mz,mz]
+  int NCOL;         // NX*NY columns (nx,ny)
+  int KF;           // NCOL*NZ reciprocal vectors stored per frame (half space + masked rest)
+  int Zc;           // nz chunk of the forward kernel
+  int NZP;          // nz padded to a multiple of Zc
+  int R;            // complex entries per atom in the phase tables: NX + NY + NZP
+  double alpha, rcut;
+};
+
+// QM accumulator slots (doubles per QM row, zeroed at the start of each call).
+enum QmSlot {
+  QA_PHI_SR = 0,    // 1
+  QA_DPHI_SR = 1,   // 3
+  QA_H_SR = 4,      // 6  (1/2 grad grad phi: xx xy xz yy yz zz)
+  QA_PHI_LR = 10,
+  QA_DPHI_LR = 11,
+  QA_H_LR = 14,
+  QA_G_QMMM_SR = 20,  // 3  dL/dR of the QM-MM real-space part (effective moments)
+  QA_G_QMMM_LR = 23,  // 3
+  QA_G_QQ_LR = 26,    // 3
+  QA_DQ_QQ_LR = 29,   // 1
+  QA_DMU_QQ_LR = 30,  // 3
+  QA_DTH_QQ_LR = 33,  // 6 (derivative w.r.t. each distinct full-matrix element)
+  QA_G_QQ_SR = 39,    // 3
+  QA_DQ_QQ_SR = 42,   // 1 (includes self and background)
+  QA_DMU_QQ_SR = 43,  // 3
+  QA_DTH_QQ_SR = 46,  // 6
+  QA_COUNT = 52,
+  QA_STRIDE = 56
+};
+
+// Per-frame scalar accumulators.
+enum FrameSlot {
+  FA_QTOT_MM = 0,
+  FA_QTOT_QM = 1,
+  FA_E_QMMM_LR = 2,
+  FA_E_QQ_LR = 3,
+  FA_E_QQ_SR = 4,   // real space + self + background
+  FA_QTOT_EFF = 5,  // sum of effective charges (backward)
+  FA_COUNT = 8
+};
+
+// Device buffers of a plan (all sized for the plan capacities).
+struct Work {
+  double* mm4;        // [4][cap_mm]  wrapped x,y,z and q
+  double* qm4;        // [4][cap_qm]  wrapped x,y,z and Q
+  double2* mm_tab;    // [cap_mm][R]  e^{i 2 pi n x/L}: x (n=0..mx), y (-my..my), z (-mz..mz, zero padded)
+  double2* qm_tab;    // [cap_qm][R]
+  double2* sabc;      // [cap_frames][KF][3]  A, B, C of the QM multipoles
+  double2* wk;        // [cap_frames][KF]     backward weights (8 pi/V) g(k) S'_QM(k)
+  double2* smm;       // [cap_frames][KF]     S_MM for batched calls
+  double2* spart;     // [cap_slots][NZP][NCOL] partial S_MM sums
+  double* fpart;      // [cap_kc][cap_mm][4]  partial MM gradient data (phi, dx, dy, dz)
+  double* rpart;      // [cap_mm][4]          real-space MM gradient data
+  double* qacc;       // [cap_qm][QA_STRIDE]
+  double* qeff;       // [cap_qm][10]         effective moments Q', mu', theta'(stored)
+  double* site;       // [cap_qm][10]         phi, grad phi, H for batched calls
+  double* facc;       // [cap_frames][FA_COUNT]
+  double* one;        // a device 1.0
+  FrameDev* frames;   // [cap_frames]
+};
+
+// Tunables of the two hot kernels.
+struct Tuning {
+  int zc;         // forward nz chunk (template instance)
+  int a_chunk;    // forward atoms per block
+  int kc;         // backward column chunks
+  int bwd_ilp;    // backward atoms per lane (1 or 2)
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error; all are asynchronous.
+hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
+                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
+                       int cap_mm);
+hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const double* Q, const double* mu,
+                          const double* theta, const double* qeff, const double* gE, int with_w, Work& w,
+                          hipStream_t s);
+hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                          hipStream_t s);
+hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, Work& w, hipStream_t s);
+hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
+                             size_t smm_frame_stride, Work& w, hipStream_t s);
+hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int total_nq, const double2* smm,
+                             size_t smm_frame_stride, const double* Q, const double* mu, const double* theta,
+                             int backward, int qmqm, Work& w, hipStream_t s);
+hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                           hipStream_t s);
+hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
+                          int backward, int fp32, Work& w, hipStream_t s);
+hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
+                          hipStream_t s);
+hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int cap_qm, const double* Q, const double* mu,
+                       const double* theta, Work& w, hipStream_t s);
+hipError_t launch_finalize_fwd(const Grid& g, const FrameArg& fa, const double* Q, const double* mu,
+                               const double* theta, int qmqm, double* energy, double* phi, double* efield,
+                               double* efgrad, double* site_out, Work& w, hipStream_t s);
+hipError_t launch_eff_moments(const FrameArg& fa, int max_nq, const double* Q, const double* mu, const double* theta,
+                              const double* gE, const double* g_phi, const double* g_efield, const double* g_efgrad,
+                              Work& w, hipStream_t s);
+hipError_t launch_reduce_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                            double* g_mm_xyz, double* g_mm_q, Work& w, hipStream_t s);
+hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
+                               double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s);
+
+// forward kernel instances available for the nz chunk
+bool sfac_mm_has_zc(int zc);
+int pick_zc(int NZ);
+
+}  // namespace mpe

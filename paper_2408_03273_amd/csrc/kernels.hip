@@ -1,0 +1,1184 @@
+// HIP kernels for gfx950 of the multipolar Ewald QM/MM coupling.
+//
+// Paper: Methods (periodic QM/MM multipole energy, Fock potential and
+// nuclear gradient) and Supporting Information "Multipolar Ewald"
+// (screened tensors with f1..f7, reciprocal-space tensors, self terms).
+//
+// Reciprocal vectors are stored per frame on the box [0,mx] x [-my,my] x
+// [-mz,mz]; only the half space nx>0 | (nx=0 & ny>0) | (nx=ny=0 & nz>0)
+// carries weight (2 x (4 pi/V) e^{-k^2/4a^2}/k^2); the rest is masked.
+// Flat index k = col*NZ + (nz+mz), col = nx*NY + (ny+my).
+#include <math.h>
+
+#include "ewald_internal.h"
+
+namespace mpe {
+
+#define DEV __device__ __forceinline__
+
+static constexpr double kPi = 3.14159265358979323846;
+
+DEV int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+DEV double uniform_double(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(b & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The descriptor is selected between a kernel argument and device memory, so
+// the compiler cannot see that it is wave-uniform; say so explicitly, which
+// keeps the per-atom table reads of the hot loops on the scalar unit.
+DEV FrameDev get_frame(const FrameArg& fa, int f) {
+  FrameDev r = fa.frames ? fa.frames[f] : fa.f0;
+  for (int a = 0; a < 3; a++) {
+    r.box[a] = uniform_double(r.box[a]);
+    r.inv_box[a] = uniform_double(r.inv_box[a]);
+  }
+  r.nq = uniform_int(r.nq);
+  r.nm = uniform_int(r.nm);
+  r.qoff = uniform_int(r.qoff);
+  r.moff = uniform_int(r.moff);
+  r.slot_base = uniform_int(r.slot_base);
+  return r;
+}
+
+DEV double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+DEV double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+DEV double wrap_coord(double x, double L) {
+  double w = x - L * floor(x / L);
+  if (w >= L) w -= L;
+  if (w < 0.0) w += L;
+  return w;
+}
+
+DEV bool in_half_space(int nx, int ny, int nz) { return nx > 0 || (nx == 0 && (ny > 0 || (ny == 0 && nz > 0))); }
+
+// ------------------------------------------------------------------ reductions
+DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum N values over a 256-thread block; thread 0 gets the totals in out[].
+template <int N>
+DEV void block_sum256(double (&v)[N], double (&out)[N]) {
+  __shared__ double red[4][N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < N; t++) {
+    double s = wave_sum(v[t]);
+    if (lane == 0) red[wave][t] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int t = 0; t < N; t++) out[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ zero fill
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ preparation
+// Wrap positions into the cell, store them SoA with the charges, and sum the
+// charges of each subsystem of the frame.
+__global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __restrict__ qm_xyz,
+                                                  const double* __restrict__ Q, const double* __restrict__ mm_xyz,
+                                                  const double* __restrict__ mm_q, double* __restrict__ qm4,
+                                                  int cap_qm, double* __restrict__ mm4, int cap_mm,
+                                                  double* __restrict__ facc) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (i < fr.nm) {
+    const int r = fr.moff + i;
+    for (int a = 0; a < 3; a++) mm4[(size_t)a * cap_mm + r] = wrap_coord(mm_xyz[3 * (size_t)r + a], fr.box[a]);
+    mm4[(size_t)3 * cap_mm + r] = mm_q[r];
+    v[0] = mm_q[r];
+  }
+  if (i < fr.nq) {
+    const int r = fr.qoff + i;
+    for (int a = 0; a < 3; a++) qm4[(size_t)a * cap_qm + r] = wrap_coord(qm_xyz[3 * (size_t)r + a], fr.box[a]);
+    qm4[(size_t)3 * cap_qm + r] = Q[r];
+    v[1] = Q[r];
+  }
+  double tot[2];
+  block_sum256<2>(v, tot);
+  if (threadIdx.x == 0 && blockIdx.x * 256 < max(fr.nm, fr.nq)) {
+    atomicAdd(&facc[f * FA_COUNT + FA_QTOT_MM], tot[0]);
+    atomicAdd(&facc[f * FA_COUNT + FA_QTOT_QM], tot[1]);
+  }
+}
+
+// Per-atom phase tables: one thread per entry.  Row layout (complex):
+// [e^{i 2pi n x/Lx}, n = 0..mx][e^{i 2pi n y/Ly}, n = -my..my][e^{i 2pi n z/Lz}, n = -mz..mz, then zeros]
+__global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, const double* __restrict__ pos4,
+                                                  int cap, double2* __restrict__ tab) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int n_atoms = qm_side ? fr.nq : fr.nm;
+  const int off = qm_side ? fr.qoff : fr.moff;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n_atoms * g.R) return;
+  const int a = (int)(e / g.R), t = (int)(e - (long)a * g.R);
+  const int row = off + a;
+  int axis, n;
+  if (t < g.NX) {
+    axis = 0;
+    n = t;
+  } else if (t < g.NX + g.NY) {
+    axis = 1;
+    n = t - g.NX - g.my;
+  } else {
+    axis = 2;
+    const int iz = t - g.NX - g.NY;
+    if (iz >= g.NZ) {
+      tab[(size_t)row * g.R + t] = make_double2(0.0, 0.0);
+      return;
+    }
+    n = iz - g.mz;
+  }
+  const double x = pos4[(size_t)axis * cap + row];
+  double s, c;
+  sincospi(2.0 * (double)n * x / fr.box[axis], &s, &c);
+  tab[(size_t)row * g.R + t] = make_double2(c, s);
+}
+
+hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
+                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s,
+                       int cap_qm, int cap_mm);
+
+// ------------------------------------------------------------------ QM structure factors
+// A(k) = sum_j Q_j e_j, B(k) = sum_j i (k.mu_j) e_j, C(k) = sum_j -1/2 (k.theta_j.k) e_j,
+// e_j = e^{i k.R_j}  (SI, multipolar long-range tensors contracted with the moments).
+// With with_w, also W(k) = (8 pi/V) g(k) S'(k) for the effective moments of the backward pass.
+__global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const double* __restrict__ Q,
+                                                 const double* __restrict__ mu, const double* __restrict__ theta,
+                                                 const double* __restrict__ qeff, const double2* __restrict__ qtab,
+                                                 int with_w, double2* __restrict__ sabc, double2* __restrict__ wk) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= g.KF) return;
+  const int col = k / g.NZ, iz = k - col * g.NZ;
+  const int nx = col / g.NY, iy = col - nx * g.NY;
+  const int ny = iy - g.my, nz = iz - g.mz;
+  const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
+               kz = 2.0 * kPi * nz * fr.inv_box[2];
+  double2 A = make_double2(0, 0), B = make_double2(0, 0), C = make_double2(0, 0), S2 = make_double2(0, 0);
+  for (int j = 0; j < fr.nq; j++) {
+    const int r = fr.qoff + j;
+    const double2* row = qtab + (size_t)r * g.R;
+    const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
+    const double* m = mu + 3 * (size_t)r;
+    const double* t = theta + 6 * (size_t)r;
+    const double kmu = kx * m[0] + ky * m[1] + kz * m[2];
+    const double kthk = kx * kx * t[0] + ky * ky * t[3] + kz * kz * t[5] +
+                        2.0 * (kx * ky * t[1] + kx * kz * t[2] + ky * kz * t[4]);
+    const double Qj = Q[r];
+    A.x += Qj * e.x;
+    A.y += Qj * e.y;
+    B.x -= kmu * e.y;
+    B.y += kmu * e.x;
+    C.x -= 0.5 * kthk * e.x;
+    C.y -= 0.5 * kthk * e.y;
+    if (with_w) {
+      const double* qe = qeff + 10 * (size_t)r;
+      const double kmu2 = kx * qe[1] + ky * qe[2] + kz * qe[3];
+      const double kthk2 = kx * kx * qe[4] + ky * ky * qe[7] + kz * kz * qe[9] +
+                           2.0 * (kx * ky * qe[5] + kx * kz * qe[6] + ky * kz * qe[8]);
+      const double wr = qe[0] - 0.5 * kthk2, wi = kmu2;
+      S2.x += wr * e.x - wi * e.y;
+      S2.y += wr * e.y + wi * e.x;
+    }
+  }
+  double2* o = sabc + ((size_t)f * g.KF + k) * 3;
+  o[0] = A;
+  o[1] = B;
+  o[2] = C;
+  if (with_w) {
+    double wgt = 0.0;
+    if (in_half_space(nx, ny, nz)) {
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      const double V = fr.box[0] * fr.box[1] * fr.box[2];
+      wgt = 8.0 * kPi / V * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
+    }
+    wk[(size_t)f * g.KF + k] = make_double2(wgt * S2.x, wgt * S2.y);
+  }
+}
+
+hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const double* Q, const double* mu,
+                          const double* theta, const double* qeff, const double* gE, int with_w, Work& w,
+                          hipStream_t s) {
+  (void)max_nq;
+  (void)gE;
+  dim3 grid((g.KF + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_sfac_qm, grid, dim3(256), 0, s, g, fa, Q, mu, theta, qeff, w.qm_tab, with_w, w.sabc, w.wk);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MM structure factor (forward hot loop)
+// S_MM(k) = sum_i q_i e^{i k.R_i}.  Each lane owns one column (nx,ny) and Z
+// consecutive nz values; for every atom it forms c = q e^{i(kx x + ky y)}
+// from the atom's table row and accumulates c * e^{i kz z} with four FMAs per
+// k, the z phases being wave-uniform (scalar loads).  The four waves of a
+// block split the block's atom range and are summed through LDS; the block
+// writes one partial sum per k, and partial sums over atom chunks are added
+// by k_reduce_smm.
+template <int Z>
+__global__ __launch_bounds__(256) void k_sfac_mm(Grid g, FrameArg fa, int a_chunk, const double* __restrict__ mm4,
+                                                 int cap_mm, const double2* __restrict__ tab,
+                                                 double2* __restrict__ spart) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int nzc = g.NZP / Z;
+  const int tile = blockIdx.x / nzc, zc = blockIdx.x - tile * nzc;
+  const int a0 = blockIdx.y * a_chunk;
+  if (a0 >= fr.nm || tile * 64 >= g.NCOL) return;
+  const int a1 = min(fr.nm, a0 + a_chunk);
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int col = tile * 64 + lane;
+  const int colc = min(col, g.NCOL - 1);
+  const int nx = colc / g.NY, iy = colc - nx * g.NY;
+
+  double sr[Z], si[Z];
+#pragma unroll
+  for (int z = 0; z < Z; z++) {
+    sr[z] = 0.0;
+    si[z] = 0.0;
+  }
+  const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
+  const double2* __restrict__ base = tab + (size_t)fr.moff * g.R;
+  const int zoff = g.NX + g.NY + zc * Z;
+  for (int a = a0 + wave; a < a1; a += 4) {
+    const double2* __restrict__ row = base + (size_t)a * g.R;
+    const double q = qv[a];
+    const double2 ex = row[nx], ey = row[g.NX + iy];
+    const double cr = q * (ex.x * ey.x - ex.y * ey.y);
+    const double ci = q * (ex.x * ey.y + ex.y * ey.x);
+    const double2* __restrict__ ez = row + zoff;
+#pragma unroll
+    for (int z = 0; z < Z; z++) {
+      const double2 e = ez[z];
+      sr[z] = fma(cr, e.x, sr[z]);
+      sr[z] = fma(-ci, e.y, sr[z]);
+      si[z] = fma(cr, e.y, si[z]);
+      si[z] = fma(ci, e.x, si[z]);
+    }
+  }
+  // combine the four waves: 3,2 -> 1,0 -> 0
+  __shared__ double2 red[2][Z][64];
+  if (wave >= 2) {
+#pragma unroll
+    for (int z = 0; z < Z; z++) red[wave - 2][z][lane] = make_double2(sr[z], si[z]);
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int z = 0; z < Z; z++) {
+      const double2 o = red[wave][z][lane];
+      sr[z] += o.x;
+      si[z] += o.y;
+    }
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int z = 0; z < Z; z++) red[0][z][lane] = make_double2(sr[z], si[z]);
+  }
+  __syncthreads();
+  if (wave == 0 && col < g.NCOL) {
+    double2* __restrict__ out = spart + (size_t)(fr.slot_base + blockIdx.y) * g.NZP * g.NCOL;
+#pragma unroll
+    for (int z = 0; z < Z; z++) {
+      const double2 o = red[0][z][lane];
+      out[(size_t)(zc * Z + z) * g.NCOL + col] = make_double2(sr[z] + o.x, si[z] + o.y);
+    }
+  }
+}
+
+bool sfac_mm_has_zc(int zc) {
+  switch (zc) {
+    case 7: case 8: case 11: case 12: case 13: case 14: case 16: case 17: case 21: case 25:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// nz chunk with the least padding, preferring larger chunks on ties
+int pick_zc(int NZ) {
+  static const int cands[] = {25, 21, 17, 16, 14, 13, 12, 11};
+  int best = 17;
+  double best_cost = 1e30;
+  for (int c : cands) {
+    const int nzc = (NZ + c - 1) / c;
+    const double waste = (double)(nzc * c - NZ) / NZ;
+    // per-atom overhead of forming c is about 6 FMA-equivalents per lane
+    const double cost = (1.0 + waste) * (1.0 + 6.0 / (4.0 * c));
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
+}
+
+template <int Z>
+static hipError_t launch_sfac_mm_z(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                                   Work& w, hipStream_t s) {
+  const int tiles = (g.NCOL + 63) / 64;
+  const int nzc = g.NZP / Z;
+  const int achunks = (max_nm + t.a_chunk - 1) / t.a_chunk;
+  if (achunks == 0) return hipSuccess;
+  dim3 grid(tiles * nzc, achunks, fa.n_frames);
+  hipLaunchKernelGGL(k_sfac_mm<Z>, grid, dim3(256), 0, s, g, fa, t.a_chunk, w.mm4, cap_mm, w.mm_tab, w.spart);
+  return hipGetLastError();
+}
+
+hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                          hipStream_t s) {
+  switch (g.Zc) {
+    case 7: return launch_sfac_mm_z<7>(g, t, fa, max_nm, cap_mm, w, s);
+    case 8: return launch_sfac_mm_z<8>(g, t, fa, max_nm, cap_mm, w, s);
+    case 11: return launch_sfac_mm_z<11>(g, t, fa, max_nm, cap_mm, w, s);
+    case 12: return launch_sfac_mm_z<12>(g, t, fa, max_nm, cap_mm, w, s);
+    case 13: return launch_sfac_mm_z<13>(g, t, fa, max_nm, cap_mm, w, s);
+    case 14: return launch_sfac_mm_z<14>(g, t, fa, max_nm, cap_mm, w, s);
+    case 16: return launch_sfac_mm_z<16>(g, t, fa, max_nm, cap_mm, w, s);
+    case 17: return launch_sfac_mm_z<17>(g, t, fa, max_nm, cap_mm, w, s);
+    case 21: return launch_sfac_mm_z<21>(g, t, fa, max_nm, cap_mm, w, s);
+    case 25: return launch_sfac_mm_z<25>(g, t, fa, max_nm, cap_mm, w, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Reference GPU path: one thread per k, sincos of k.R for every atom.
+__global__ __launch_bounds__(256) void k_sfac_mm_plain(Grid g, FrameArg fa, const double* __restrict__ mm4,
+                                                       int cap_mm, double2* __restrict__ spart) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int e = blockIdx.x * 256 + threadIdx.x;  // e = iz * NCOL + col
+  if (e >= g.NZ * g.NCOL) return;
+  const int iz = e / g.NCOL, col = e - iz * g.NCOL;
+  const int nx = col / g.NY, iy = col - nx * g.NY;
+  const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * (iy - g.my) * fr.inv_box[1],
+               kz = 2.0 * kPi * (iz - g.mz) * fr.inv_box[2];
+  double sr = 0.0, si = 0.0;
+  const double* x = mm4 + fr.moff;
+  const double* y = mm4 + (size_t)cap_mm + fr.moff;
+  const double* z = mm4 + (size_t)2 * cap_mm + fr.moff;
+  const double* q = mm4 + (size_t)3 * cap_mm + fr.moff;
+  for (int i = 0; i < fr.nm; i++) {
+    double sn, cs;
+    sincos(kx * x[i] + ky * y[i] + kz * z[i], &sn, &cs);
+    sr += q[i] * cs;
+    si += q[i] * sn;
+  }
+  spart[(size_t)fr.slot_base * g.NZP * g.NCOL + (size_t)iz * g.NCOL + col] = make_double2(sr, si);
+}
+
+hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, Work& w, hipStream_t s) {
+  dim3 grid((g.NZ * g.NCOL + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_sfac_mm_plain, grid, dim3(256), 0, s, g, fa, w.mm4, cap_mm, w.spart);
+  return hipGetLastError();
+}
+
+// Sum the partial structure factors, store S_MM in k order, and accumulate
+// the reciprocal energies (8 pi/V) g Re[S_QM conj S_MM] and the order-2
+// truncated QM-QM term (4 pi/V) g (|A|^2 + 2Re A*B + 2Re A*C + |B|^2).
+__global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain,
+                                                    const double2* __restrict__ spart,
+                                                    const double2* __restrict__ sabc, double2* __restrict__ smm,
+                                                    size_t smm_stride, double* __restrict__ facc) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (e < g.NZ * g.NCOL) {
+    const int iz = e / g.NCOL, col = e - iz * g.NCOL;
+    const int nslots = plain ? 1 : (fr.nm + a_chunk - 1) / a_chunk;
+    double sr = 0.0, si = 0.0;
+    for (int sl = 0; sl < nslots; sl++) {
+      const double2 p = spart[(size_t)(fr.slot_base + sl) * g.NZP * g.NCOL + (size_t)iz * g.NCOL + col];
+      sr += p.x;
+      si += p.y;
+    }
+    if (plain && fr.nm == 0) sr = si = 0.0;
+    const int k = col * g.NZ + iz;
+    smm[(size_t)f * smm_stride + k] = make_double2(sr, si);
+    const int nx = col / g.NY, ny = col - nx * g.NY - g.my, nz = iz - g.mz;
+    if (in_half_space(nx, ny, nz)) {
+      const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
+                   kz = 2.0 * kPi * nz * fr.inv_box[2];
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      const double V = fr.box[0] * fr.box[1] * fr.box[2];
+      const double wgt = 8.0 * kPi / V * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
+      const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
+      const double2 A = abc[0], B = abc[1], C = abc[2];
+      const double sqr = A.x + B.x + C.x, sqi = A.y + B.y + C.y;
+      v[0] = wgt * (sqr * sr + sqi * si);
+      const double F = (A.x * A.x + A.y * A.y) + 2.0 * (A.x * B.x + A.y * B.y) + 2.0 * (A.x * C.x + A.y * C.y) +
+                       (B.x * B.x + B.y * B.y);
+      v[1] = 0.5 * wgt * F;
+    }
+  }
+  double tot[2];
+  block_sum256<2>(v, tot);
+  if (threadIdx.x == 0) {
+    atomicAdd(&facc[f * FA_COUNT + FA_E_QMMM_LR], tot[0]);
+    atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_LR], tot[1]);
+  }
+}
+
+hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
+                             size_t smm_frame_stride, Work& w, hipStream_t s) {
+  dim3 grid((g.NZ * g.NCOL + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, w.spart, w.sabc, smm_out,
+                     smm_frame_stride, w.facc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ QM-site projection
+// Forward: phi, grad phi and 1/2 grad grad phi of the MM charges at each QM
+// site from S_MM.  Backward: the QM-MM long-range gradient with the
+// effective moments, and the QM-QM long-range gradient and moment
+// derivatives of the order-2 truncated image energy.
+template <int BWD>
+__global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_pc, const double2* __restrict__ smm,
+                                                    size_t smm_stride, const double* __restrict__ Q,
+                                                    const double* __restrict__ mu, const double* __restrict__ theta,
+                                                    const double* __restrict__ qeff,
+                                                    const double2* __restrict__ qtab,
+                                                    const double2* __restrict__ sabc, int qmqm,
+                                                    double* __restrict__ qacc) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int j = blockIdx.x;
+  if (j >= fr.nq) return;
+  const int r = fr.qoff + j;
+  constexpr int NV = BWD ? 16 : 10;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; t++) acc[t] = 0.0;
+  const double2* row = qtab + (size_t)r * g.R;
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  const double pref = 8.0 * kPi / V;
+  double Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
+  double Qo = 0, o0 = 0, o1 = 0, o2 = 0, u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0, u5 = 0;
+  if (BWD) {
+    const double* qe = qeff + 10 * (size_t)r;
+    Qe = qe[0]; m0 = qe[1]; m1 = qe[2]; m2 = qe[3];
+    t0 = qe[4]; t1 = qe[5]; t2 = qe[6]; t3 = qe[7]; t4 = qe[8]; t5 = qe[9];
+    Qo = Q[r]; o0 = mu[3 * (size_t)r]; o1 = mu[3 * (size_t)r + 1]; o2 = mu[3 * (size_t)r + 2];
+    const double* th = theta + 6 * (size_t)r;
+    u0 = th[0]; u1 = th[1]; u2 = th[2]; u3 = th[3]; u4 = th[4]; u5 = th[5];
+  }
+  for (int k = blockIdx.y * 256 + threadIdx.x; k < g.KF; k += n_pc * 256) {
+    const int col = k / g.NZ, iz = k - col * g.NZ;
+    const int nx = col / g.NY, iy = col - nx * g.NY;
+    const int ny = iy - g.my, nz = iz - g.mz;
+    if (!in_half_space(nx, ny, nz)) continue;
+    const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
+                 kz = 2.0 * kPi * nz * fr.inv_box[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double w = pref * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
+    const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
+    const double2 S = smm[(size_t)f * smm_stride + k];
+    // Y = e conj(S)
+    const double yr = e.x * S.x + e.y * S.y, yi = e.y * S.x - e.x * S.y;
+    if (!BWD) {
+      acc[0] += w * yr;
+      acc[1] -= w * kx * yi;
+      acc[2] -= w * ky * yi;
+      acc[3] -= w * kz * yi;
+      const double h = -0.5 * w * yr;
+      acc[4] += h * kx * kx;
+      acc[5] += h * kx * ky;
+      acc[6] += h * kx * kz;
+      acc[7] += h * ky * ky;
+      acc[8] += h * ky * kz;
+      acc[9] += h * kz * kz;
+    } else {
+      // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
+      const double kthk = kx * kx * t0 + ky * ky * t3 + kz * kz * t5 + 2.0 * (kx * ky * t1 + kx * kz * t2 + ky * kz * t4);
+      const double wr = Qe - 0.5 * kthk, wi = kx * m0 + ky * m1 + kz * m2;
+      const double gr = -(wr * yi + wi * yr);
+      acc[0] += w * kx * gr;
+      acc[1] += w * ky * gr;
+      acc[2] += w * kz * gr;
+      if (qmqm) {
+        const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
+        const double2 A = abc[0], B = abc[1], C = abc[2];
+        const double kmu = kx * o0 + ky * o1 + kz * o2;
+        const double kthko = kx * kx * u0 + ky * ky * u3 + kz * kz * u5 + 2.0 * (kx * ky * u1 + kx * kz * u2 + ky * kz * u4);
+        // a_j = Q e, b_j = i kmu e, c_j = -1/2 kthk e
+        const double ajr = Qo * e.x, aji = Qo * e.y;
+        const double bjr = -kmu * e.y, bji = kmu * e.x;
+        const double cjr = -0.5 * kthko * e.x, cji = -0.5 * kthko * e.y;
+        const double T1r = A.x + B.x + C.x, T1i = A.y + B.y + C.y;
+        const double T2r = A.x + B.x, T2i = A.y + B.y;
+        // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
+        const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
+        acc[3] -= w * kx * zi;
+        acc[4] -= w * ky * zi;
+        acc[5] -= w * kz * zi;
+        acc[6] += w * (e.x * T1r + e.y * T1i);
+        const double ime = e.y * T2r - e.x * T2i;
+        acc[7] -= w * kx * ime;
+        acc[8] -= w * ky * ime;
+        acc[9] -= w * kz * ime;
+        const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
+        acc[10] += h * kx * kx;
+        acc[11] += h * kx * ky;
+        acc[12] += h * kx * kz;
+        acc[13] += h * ky * ky;
+        acc[14] += h * ky * kz;
+        acc[15] += h * kz * kz;
+      }
+    }
+  }
+  double tot[NV];
+  block_sum256<NV>(acc, tot);
+  if (threadIdx.x == 0) {
+    double* qa = qacc + (size_t)r * QA_STRIDE;
+    if (!BWD) {
+      atomicAdd(&qa[QA_PHI_LR], tot[0]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_LR + t], tot[1 + t]);
+      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_LR + t], tot[4 + t]);
+    } else {
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_LR + t], tot[t]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QQ_LR + t], tot[3 + t]);
+      atomicAdd(&qa[QA_DQ_QQ_LR], tot[6]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DMU_QQ_LR + t], tot[7 + t]);
+      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_DTH_QQ_LR + t], tot[10 + t]);
+    }
+  }
+}
+
+hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int total_nq, const double2* smm,
+                             size_t smm_frame_stride, const double* Q, const double* mu, const double* theta,
+                             int backward, int qmqm, Work& w, hipStream_t s) {
+  if (max_nq == 0) return hipSuccess;
+  int n_pc = (2048 + total_nq - 1) / (total_nq > 0 ? total_nq : 1);
+  const int kblocks = (g.KF + 255) / 256;
+  if (n_pc > kblocks) n_pc = kblocks;
+  if (n_pc < 1) n_pc = 1;
+  dim3 grid(max_nq, n_pc, fa.n_frames);
+  if (backward)
+    hipLaunchKernelGGL(k_project_qm<1>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
+                       w.qeff, w.qm_tab, w.sabc, qmqm, w.qacc);
+  else
+    hipLaunchKernelGGL(k_project_qm<0>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
+                       w.qeff, w.qm_tab, w.sabc, qmqm, w.qacc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MM gradients (backward hot loop)
+// For MM atom i: V(R) = sum_k W(k) e^{-i k.R}, W = (8 pi/V) g S'_QM, gives
+// dL/dq_i = Re V(R_i) and dL/dR_i = q_i grad Re V(R_i).  Lanes own atoms;
+// for each column (nx,ny) the nz sum is evaluated by Horner's rule in
+// u = e^{-i kz0 z} (nz >= 0) and conj(u) (nz < 0), together with the
+// nz-weighted sum for the z derivative: eight FMAs per k with the weights
+// W read as wave-uniform scalars.
+__global__ __launch_bounds__(256) void k_force_mm(Grid g, FrameArg fa, int kc_n, const double* __restrict__ mm4,
+                                                  int cap_mm, const double2* __restrict__ tab,
+                                                  const double2* __restrict__ wk, double* __restrict__ fpart) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int i0 = blockIdx.x * 256;
+  if (i0 >= fr.nm) return;
+  const int i = i0 + threadIdx.x;
+  const int ic = min(i, fr.nm - 1);
+  const int row = fr.moff + ic;
+  const double z = mm4[(size_t)2 * cap_mm + row];
+  const double y = mm4[(size_t)cap_mm + row];
+  const int kc = blockIdx.y;
+  const int per = (g.NCOL + kc_n - 1) / kc_n;
+  const int c0 = kc * per, c1 = min(g.NCOL, c0 + per);
+  const int mz = g.mz;
+  double sz, cz, sy, cy;
+  sincospi(2.0 * z / fr.box[2], &sz, &cz);
+  sincospi(2.0 * y / fr.box[1], &sy, &cy);
+  const double2 u = make_double2(cz, -sz);   // e^{-i kz0 z}
+  const double2 v = make_double2(cz, sz);    // conj(u)
+  const double2 wy = make_double2(cy, -sy);  // e^{-i ky0 y}
+  const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
+  const double2* trow = tab + (size_t)row * g.R;
+  double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
+  const double2* __restrict__ wf = wk + (size_t)f * g.KF;
+  double2 c = make_double2(1.0, 0.0);
+  for (int col = c0; col < c1; col++) {
+    const int nx = col / g.NY, iy = col - nx * g.NY;
+    if (col == c0 || iy == 0)
+      c = cconj(cmul(trow[nx], trow[g.NX + iy]));
+    else
+      c = cmul(c, wy);
+    const double2* __restrict__ wc = wf + (size_t)col * g.NZ;
+    // nz >= 0 part: P(u) = sum_{n=0}^{mz} W_n u^n, d = P'(u)
+    double pr = wc[2 * mz].x, pi = wc[2 * mz].y, dr = 0.0, di = 0.0;
+    // nz < 0 part: Qp(v) = sum_{n'=0}^{mz-1} W_{-(n'+1)} v^{n'}, e = Qp'(v)
+    double qr = wc[0].x, qi = wc[0].y, er = 0.0, ei = 0.0;
+    for (int t = 0; t < mz - 1; t++) {
+      const double2 wp = wc[2 * mz - 1 - t];
+      const double2 wn = wc[1 + t];
+      double tr = fma(dr, u.x, fma(-di, u.y, pr));
+      di = fma(dr, u.y, fma(di, u.x, pi));
+      dr = tr;
+      tr = fma(pr, u.x, fma(-pi, u.y, wp.x));
+      pi = fma(pr, u.y, fma(pi, u.x, wp.y));
+      pr = tr;
+      tr = fma(er, v.x, fma(-ei, v.y, qr));
+      ei = fma(er, v.y, fma(ei, v.x, qi));
+      er = tr;
+      tr = fma(qr, v.x, fma(-qi, v.y, wn.x));
+      qi = fma(qr, v.y, fma(qi, v.x, wn.y));
+      qr = tr;
+    }
+    {
+      const double2 wp = wc[mz];  // last step of the nz >= 0 part (n = 0)
+      double tr = fma(dr, u.x, fma(-di, u.y, pr));
+      di = fma(dr, u.y, fma(di, u.x, pi));
+      dr = tr;
+      tr = fma(pr, u.x, fma(-pi, u.y, wp.x));
+      pi = fma(pr, u.y, fma(pi, u.x, wp.y));
+      pr = tr;
+    }
+    // P- = v Qp, sum n W_{-n} v^n = v (Qp + v Qp')
+    const double2 Qp = make_double2(qr, qi), dQ = make_double2(er, ei);
+    const double2 Pm = cmul(v, Qp);
+    const double2 Zm = cmul(v, make_double2(Qp.x + (v.x * dQ.x - v.y * dQ.y), Qp.y + (v.x * dQ.y + v.y * dQ.x)));
+    const double2 Zp = cmul(u, make_double2(dr, di));
+    const double2 P = make_double2(pr + Pm.x, pi + Pm.y);
+    const double2 Pz = make_double2(Zp.x - Zm.x, Zp.y - Zm.y);
+    const double2 cP = cmul(c, P), cPz = cmul(c, Pz);
+    aphi += cP.x;
+    agx += (double)nx * cP.y;
+    agy += (double)(iy - g.my) * cP.y;
+    agz += cPz.y;
+  }
+  if (i < fr.nm) {
+    double* o = fpart + ((size_t)kc * cap_mm + fr.moff + i) * 4;
+    o[0] = aphi;
+    o[1] = kx0 * agx;
+    o[2] = ky0 * agy;
+    o[3] = kz0 * agz;
+  }
+}
+
+hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                           hipStream_t s) {
+  if (max_nm == 0) return hipSuccess;
+  dim3 grid((max_nm + 255) / 256, t.kc, fa.n_frames);
+  hipLaunchKernelGGL(k_force_mm, grid, dim3(256), 0, s, g, fa, t.kc, w.mm4, cap_mm, w.mm_tab, w.wk, w.fpart);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ real space
+// Screened tensors of erfc(a r)/r about the QM site, r = R_qm - R_mm
+// (SI, screened tensors with kappa = alpha):
+//   psi0 = f1, psi1 = -r f3, psi2 = 1/2 (3 r r f5 - I f3),
+//   psi3 = 1/2 [ (r delta)_sym f5 - 5 r r r f7 ]
+// contracted analytically with the moments.
+template <typename T>
+struct Radial {
+  T f1, f3, f5, f7;
+};
+
+template <typename T>
+DEV Radial<T> radial(T r2, T a) {
+  const T r = sqrt(r2);
+  const T ex = exp(-a * a * r2);
+  const T inv2 = T(1) / r2;
+  const T c = T(1.1283791670955126) * a;  // 2 a / sqrt(pi)
+  Radial<T> o;
+  o.f1 = erfc(a * r) / r;
+  o.f3 = (o.f1 + c * ex) * inv2;
+  o.f5 = (o.f3 + T(2.0 / 3.0) * a * a * c * ex) * inv2;
+  o.f7 = (o.f5 + T(4.0 / 15.0) * a * a * a * a * c * ex) * inv2;
+  return o;
+}
+
+DEV void min_image(double& dx, double& dy, double& dz, const FrameDev& fr) {
+  dx -= fr.box[0] * rint(dx * fr.inv_box[0]);
+  dy -= fr.box[1] * rint(dy * fr.inv_box[1]);
+  dz -= fr.box[2] * rint(dz * fr.inv_box[2]);
+}
+
+// QM side of the QM-MM real-space sum.  Forward: phi, grad phi, 1/2 grad grad phi.
+// Backward: dL/dR_qm with the effective moments.
+template <typename T, int BWD>
+__global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk, const double* __restrict__ qm4,
+                                                 int cap_qm, const double* __restrict__ mm4, int cap_mm,
+                                                 const double* __restrict__ qeff, double* __restrict__ qacc) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int j = blockIdx.x;
+  if (j >= fr.nq) return;
+  const int i0 = blockIdx.y * chunk;
+  if (i0 >= fr.nm) return;
+  const int i1 = min(fr.nm, i0 + chunk);
+  const int r = fr.qoff + j;
+  const double X = qm4[r], Y = qm4[(size_t)cap_qm + r], Zc = qm4[(size_t)2 * cap_qm + r];
+  const T a = (T)g.alpha;
+  const double rc2 = g.rcut * g.rcut;
+  constexpr int NV = BWD ? 3 : 10;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; t++) acc[t] = 0.0;
+  T Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
+  if (BWD) {
+    const double* qe = qeff + 10 * (size_t)r;
+    Qe = (T)qe[0]; m0 = (T)qe[1]; m1 = (T)qe[2]; m2 = (T)qe[3];
+    t0 = (T)qe[4]; t1 = (T)qe[5]; t2 = (T)qe[6]; t3 = (T)qe[7]; t4 = (T)qe[8]; t5 = (T)qe[9];
+  }
+  const double* mx_ = mm4 + fr.moff;
+  const double* my_ = mm4 + (size_t)cap_mm + fr.moff;
+  const double* mz_ = mm4 + (size_t)2 * cap_mm + fr.moff;
+  const double* mq_ = mm4 + (size_t)3 * cap_mm + fr.moff;
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    double dx = X - mx_[i], dy = Y - my_[i], dz = Zc - mz_[i];
+    min_image(dx, dy, dz, fr);
+    const double r2d = dx * dx + dy * dy + dz * dz;
+    if (!(r2d < rc2) || r2d == 0.0) continue;
+    const T x = (T)dx, y = (T)dy, z = (T)dz;
+    const Radial<T> R = radial<T>((T)r2d, a);
+    const T q = (T)mq_[i];
+    if (!BWD) {
+      acc[0] += (double)(q * R.f1);
+      acc[1] += (double)(-q * x * R.f3);
+      acc[2] += (double)(-q * y * R.f3);
+      acc[3] += (double)(-q * z * R.f3);
+      const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
+      acc[4] += (double)(h5 * x * x - h3);
+      acc[5] += (double)(h5 * x * y);
+      acc[6] += (double)(h5 * x * z);
+      acc[7] += (double)(h5 * y * y - h3);
+      acc[8] += (double)(h5 * y * z);
+      acc[9] += (double)(h5 * z * z - h3);
+    } else {
+      // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
+      const T md = m0 * x + m1 * y + m2 * z;
+      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+      const T dtd = x * thx + y * thy + z * thz;
+      const T tr = t0 + t3 + t5;
+      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+      const T s2 = -R.f3;
+      const T s3 = T(3) * R.f5;
+      acc[0] += (double)(q * (s1 * x + s2 * m0 + s3 * thx));
+      acc[1] += (double)(q * (s1 * y + s2 * m1 + s3 * thy));
+      acc[2] += (double)(q * (s1 * z + s2 * m2 + s3 * thz));
+    }
+  }
+  double tot[NV];
+  block_sum256<NV>(acc, tot);
+  if (threadIdx.x == 0) {
+    double* qa = qacc + (size_t)r * QA_STRIDE;
+    if (!BWD) {
+      atomicAdd(&qa[QA_PHI_SR], tot[0]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_SR + t], tot[1 + t]);
+      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_SR + t], tot[4 + t]);
+    } else {
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], tot[t]);
+    }
+  }
+}
+
+static constexpr int kRealChunk = 2048;
+
+hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
+                          int backward, int fp32, Work& w, hipStream_t s) {
+  if (max_nq == 0 || max_nm == 0) return hipSuccess;
+  dim3 grid(max_nq, (max_nm + kRealChunk - 1) / kRealChunk, fa.n_frames);
+#define RQ(T, B) \
+  hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, kRealChunk, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.qacc)
+  if (fp32) {
+    if (backward) RQ(float, 1); else RQ(float, 0);
+  } else {
+    if (backward) RQ(double, 1); else RQ(double, 0);
+  }
+#undef RQ
+  return hipGetLastError();
+}
+
+// MM side of the QM-MM real-space sum (backward): dL/dR_i and dL/dq_i with
+// the effective moments, one thread per MM atom looping over the QM sites.
+template <typename T>
+__global__ __launch_bounds__(256) void k_real_mm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
+                                                 const double* __restrict__ mm4, int cap_mm,
+                                                 const double* __restrict__ qeff, double* __restrict__ rpart) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= fr.nm) return;
+  const int row = fr.moff + i;
+  const double X = mm4[row], Y = mm4[(size_t)cap_mm + row], Zc = mm4[(size_t)2 * cap_mm + row];
+  const double q = mm4[(size_t)3 * cap_mm + row];
+  const T a = (T)g.alpha;
+  const double rc2 = g.rcut * g.rcut;
+  double aphi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int j = 0; j < fr.nq; j++) {
+    const int r = fr.qoff + j;
+    double dx = qm4[r] - X, dy = qm4[(size_t)cap_qm + r] - Y, dz = qm4[(size_t)2 * cap_qm + r] - Zc;
+    min_image(dx, dy, dz, fr);
+    const double r2d = dx * dx + dy * dy + dz * dz;
+    if (!(r2d < rc2) || r2d == 0.0) continue;
+    const T x = (T)dx, y = (T)dy, z = (T)dz;
+    const Radial<T> R = radial<T>((T)r2d, a);
+    const double* qe = qeff + 10 * (size_t)r;
+    const T Qe = (T)qe[0], m0 = (T)qe[1], m1 = (T)qe[2], m2 = (T)qe[3];
+    const T t0 = (T)qe[4], t1 = (T)qe[5], t2 = (T)qe[6], t3 = (T)qe[7], t4 = (T)qe[8], t5 = (T)qe[9];
+    const T md = m0 * x + m1 * y + m2 * z;
+    const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+    const T dtd = x * thx + y * thy + z * thz;
+    const T tr = t0 + t3 + t5;
+    // energy per unit MM charge: Q psi0 + mu.psi1 + theta:psi2
+    aphi += (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
+    const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+    const T s2 = -R.f3;
+    const T s3 = T(3) * R.f5;
+    // r depends on -R_mm
+    gx -= (double)(s1 * x + s2 * m0 + s3 * thx);
+    gy -= (double)(s1 * y + s2 * m1 + s3 * thy);
+    gz -= (double)(s1 * z + s2 * m2 + s3 * thz);
+  }
+  double* o = rpart + (size_t)row * 4;
+  o[0] = aphi;
+  o[1] = q * gx;
+  o[2] = q * gy;
+  o[3] = q * gz;
+}
+
+hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
+                          hipStream_t s) {
+  if (max_nm == 0) return hipSuccess;
+  dim3 grid((max_nm + 255) / 256, fa.n_frames);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_mm<float>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart);
+  else
+    hipLaunchKernelGGL(k_real_mm<double>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ QM-QM real space, self, background
+// P(a,b) = Qa Qb psi0 + (Qb mu_a - Qa mu_b).psi1 + (Qb th_a + Qa th_b):psi2 - 2 mu_a.psi2.mu_b,
+// E = 1/2 sum_{a != b} P + sum_a self_a - (pi/(2 a^2 V)) Qtot^2.  Thread a owns site a.
+__global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
+                                              const double* __restrict__ Q, const double* __restrict__ mu,
+                                              const double* __restrict__ theta, double* __restrict__ qacc,
+                                              double* __restrict__ facc) {
+  const int f = blockIdx.x;
+  const FrameDev fr = get_frame(fa, f);
+  const double al = g.alpha, rc2 = g.rcut * g.rcut;
+  const double sp = 1.7724538509055160273;  // sqrt(pi)
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  const double bgc = -kPi / (al * al * V);
+  const double Qtot = facc[f * FA_COUNT + FA_QTOT_QM];
+  double esum = 0.0;
+  for (int a = threadIdx.x; a < fr.nq; a += 256) {
+    const int ra = fr.qoff + a;
+    const double Xa = qm4[ra], Ya = qm4[(size_t)cap_qm + ra], Za = qm4[(size_t)2 * cap_qm + ra];
+    const double Qa = Q[ra];
+    const double ma0 = mu[3 * (size_t)ra], ma1 = mu[3 * (size_t)ra + 1], ma2 = mu[3 * (size_t)ra + 2];
+    const double* tha = theta + 6 * (size_t)ra;
+    double e = 0.0, g0 = 0, g1 = 0, g2 = 0, dQ = 0, dm0 = 0, dm1 = 0, dm2 = 0;
+    double dt[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < fr.nq; b++) {
+      if (b == a) continue;
+      const int rb = fr.qoff + b;
+      double x = Xa - qm4[rb], y = Ya - qm4[(size_t)cap_qm + rb], z = Za - qm4[(size_t)2 * cap_qm + rb];
+      min_image(x, y, z, fr);
+      const double r2 = x * x + y * y + z * z;
+      if (!(r2 < rc2) || r2 == 0.0) continue;
+      const Radial<double> R = radial<double>(r2, al);
+      const double Qb = Q[rb];
+      const double mb0 = mu[3 * (size_t)rb], mb1 = mu[3 * (size_t)rb + 1], mb2 = mu[3 * (size_t)rb + 2];
+      const double* thb = theta + 6 * (size_t)rb;
+      // combined moments seen by the pair
+      const double c0 = Qb * ma0 - Qa * mb0, c1 = Qb * ma1 - Qa * mb1, c2 = Qb * ma2 - Qa * mb2;
+      double s[6];
+      for (int t = 0; t < 6; t++) s[t] = Qb * tha[t] + Qa * thb[t];
+      const double cd = c0 * x + c1 * y + c2 * z;
+      const double sx = s[0] * x + s[1] * y + s[2] * z, sy = s[1] * x + s[3] * y + s[4] * z,
+                   sz = s[2] * x + s[4] * y + s[5] * z;
+      const double dsd = x * sx + y * sy + z * sz, trs = s[0] + s[3] + s[5];
+      const double mad = ma0 * x + ma1 * y + ma2 * z, mbd = mb0 * x + mb1 * y + mb2 * z;
+      const double mab = ma0 * mb0 + ma1 * mb1 + ma2 * mb2;
+      // P
+      const double P = Qa * Qb * R.f1 - cd * R.f3 + (1.5 * dsd * R.f5 - 0.5 * trs * R.f3) -
+                       (3.0 * mad * mbd * R.f5 - mab * R.f3);
+      e += 0.5 * P;
+      // dP/dr = QaQb psi1 + 2 c.psi2 + 3 s:psi3 - 6 mu_a.psi3.mu_b
+      const double s1 = -Qa * Qb * R.f3 + 3.0 * cd * R.f5 + 1.5 * trs * R.f5 - 7.5 * dsd * R.f7 -
+                        3.0 * (mab * R.f5 - 5.0 * mad * mbd * R.f7);
+      const double sc = -R.f3, ss = 3.0 * R.f5, sm = -3.0 * R.f5;
+      g0 += s1 * x + sc * c0 + ss * sx + sm * (ma0 * mbd + mb0 * mad);
+      g1 += s1 * y + sc * c1 + ss * sy + sm * (ma1 * mbd + mb1 * mad);
+      g2 += s1 * z + sc * c2 + ss * sz + sm * (ma2 * mbd + mb2 * mad);
+      // moment derivatives of P w.r.t. site a
+      const double thbx = thb[0] * x + thb[1] * y + thb[2] * z, thby = thb[1] * x + thb[3] * y + thb[4] * z,
+                   thbz = thb[2] * x + thb[4] * y + thb[5] * z;
+      const double dtbd = x * thbx + y * thby + z * thbz, trb = thb[0] + thb[3] + thb[5];
+      dQ += Qb * R.f1 + mbd * R.f3 + (1.5 * dtbd * R.f5 - 0.5 * trb * R.f3);
+      // Qb psi1 - 2 psi2.mu_b
+      dm0 += -Qb * x * R.f3 - (3.0 * x * mbd * R.f5 - mb0 * R.f3);
+      dm1 += -Qb * y * R.f3 - (3.0 * y * mbd * R.f5 - mb1 * R.f3);
+      dm2 += -Qb * z * R.f3 - (3.0 * z * mbd * R.f5 - mb2 * R.f3);
+      // Qb psi2 (distinct elements xx xy xz yy yz zz)
+      const double h5 = 1.5 * Qb * R.f5, h3 = 0.5 * Qb * R.f3;
+      dt[0] += h5 * x * x - h3;
+      dt[1] += h5 * x * y;
+      dt[2] += h5 * x * z;
+      dt[3] += h5 * y * y - h3;
+      dt[4] += h5 * y * z;
+      dt[5] += h5 * z * z - h3;
+    }
+    // self terms
+    const double a3 = 2.0 * al * al * al / (3.0 * sp);
+    const double tra = tha[0] + tha[3] + tha[5];
+    const double mm2 = ma0 * ma0 + ma1 * ma1 + ma2 * ma2;
+    e += -al / sp * Qa * Qa - a3 * mm2 + a3 * Qa * tra;
+    dQ += -2.0 * al / sp * Qa + a3 * tra + bgc * Qtot;
+    dm0 += -2.0 * a3 * ma0;
+    dm1 += -2.0 * a3 * ma1;
+    dm2 += -2.0 * a3 * ma2;
+    dt[0] += a3 * Qa;
+    dt[3] += a3 * Qa;
+    dt[5] += a3 * Qa;
+    double* qa = qacc + (size_t)ra * QA_STRIDE;
+    qa[QA_G_QQ_SR + 0] = g0;
+    qa[QA_G_QQ_SR + 1] = g1;
+    qa[QA_G_QQ_SR + 2] = g2;
+    qa[QA_DQ_QQ_SR] = dQ;
+    qa[QA_DMU_QQ_SR + 0] = dm0;
+    qa[QA_DMU_QQ_SR + 1] = dm1;
+    qa[QA_DMU_QQ_SR + 2] = dm2;
+    for (int t = 0; t < 6; t++) qa[QA_DTH_QQ_SR + t] = dt[t];
+    esum += e;
+  }
+  double v[1] = {esum}, tot[1];
+  block_sum256<1>(v, tot);
+  if (threadIdx.x == 0) facc[f * FA_COUNT + FA_E_QQ_SR] = tot[0] + 0.5 * bgc * Qtot * Qtot;
+}
+
+hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int cap_qm, const double* Q, const double* mu,
+                       const double* theta, Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_qmqm, dim3(fa.n_frames), dim3(256), 0, s, g, fa, w.qm4, cap_qm, Q, mu, theta, w.qacc, w.facc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ forward outputs
+// phi = SR + LR + background of the MM charges; E = sum_j [Q phi + mu.grad phi
+// + theta:(1/2 grad grad phi)] + E_QQ.  One block per frame.
+__global__ __launch_bounds__(256) void k_finalize_fwd(Grid g, FrameArg fa, const double* __restrict__ Q,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ theta, int qmqm,
+                                                      const double* __restrict__ qacc,
+                                                      const double* __restrict__ facc, double* __restrict__ energy,
+                                                      double* __restrict__ phi, double* __restrict__ efield,
+                                                      double* __restrict__ efgrad, double* __restrict__ site) {
+  const int f = blockIdx.x;
+  const FrameDev fr = get_frame(fa, f);
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  const double bg = -kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
+  double esum = 0.0;
+  for (int j = threadIdx.x; j < fr.nq; j += 256) {
+    const int r = fr.qoff + j;
+    const double* qa = qacc + (size_t)r * QA_STRIDE;
+    const double p = qa[QA_PHI_SR] + qa[QA_PHI_LR] + bg;
+    double d[3], h[6];
+    for (int t = 0; t < 3; t++) d[t] = qa[QA_DPHI_SR + t] + qa[QA_DPHI_LR + t];
+    for (int t = 0; t < 6; t++) h[t] = qa[QA_H_SR + t] + qa[QA_H_LR + t];
+    if (phi) phi[r] = p;
+    if (efield)
+      for (int t = 0; t < 3; t++) efield[3 * (size_t)r + t] = -d[t];
+    if (efgrad)
+      for (int t = 0; t < 6; t++) efgrad[6 * (size_t)r + t] = -2.0 * h[t];
+    if (site) {
+      double* o = site + 10 * (size_t)r;
+      o[0] = p;
+      for (int t = 0; t < 3; t++) o[1 + t] = d[t];
+      for (int t = 0; t < 6; t++) o[4 + t] = h[t];
+    }
+    const double* m = mu + 3 * (size_t)r;
+    const double* th = theta + 6 * (size_t)r;
+    esum += Q[r] * p + m[0] * d[0] + m[1] * d[1] + m[2] * d[2] + th[0] * h[0] + th[3] * h[3] + th[5] * h[5] +
+            2.0 * (th[1] * h[1] + th[2] * h[2] + th[4] * h[4]);
+  }
+  double v[1] = {esum}, tot[1];
+  block_sum256<1>(v, tot);
+  if (threadIdx.x == 0) {
+    double e = tot[0];
+    if (qmqm) e += facc[f * FA_COUNT + FA_E_QQ_LR] + facc[f * FA_COUNT + FA_E_QQ_SR];
+    energy[f] = e;
+  }
+}
+
+hipError_t launch_finalize_fwd(const Grid& g, const FrameArg& fa, const double* Q, const double* mu,
+                               const double* theta, int qmqm, double* energy, double* phi, double* efield,
+                               double* efgrad, double* site_out, Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_fwd, dim3(fa.n_frames), dim3(256), 0, s, g, fa, Q, mu, theta, qmqm, w.qacc, w.facc,
+                     energy, phi, efield, efgrad, site_out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ backward helpers
+// Effective moments: L = gE E + g_phi.phi + g_efield.efield + g_efgrad.efgrad
+// enters the QM-MM coupling exactly like E with Q' = gE Q + g_phi,
+// mu' = gE mu - g_efield, theta'(stored) = gE theta - (2,1,1,2,1,2) * g_efgrad.
+__global__ __launch_bounds__(256) void k_eff_moments(FrameArg fa, const double* __restrict__ Q,
+                                                     const double* __restrict__ mu, const double* __restrict__ theta,
+                                                     const double* __restrict__ gE, const double* __restrict__ g_phi,
+                                                     const double* __restrict__ g_efield,
+                                                     const double* __restrict__ g_efgrad, double* __restrict__ qeff,
+                                                     double* __restrict__ facc) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const double ge = gE ? gE[0] : 1.0;
+  double v[1] = {0.0};
+  if (j < fr.nq) {
+    const int r = fr.qoff + j;
+    double* o = qeff + 10 * (size_t)r;
+    o[0] = ge * Q[r] + (g_phi ? g_phi[r] : 0.0);
+    for (int t = 0; t < 3; t++) o[1 + t] = ge * mu[3 * (size_t)r + t] - (g_efield ? g_efield[3 * (size_t)r + t] : 0.0);
+    const double mult[6] = {2.0, 1.0, 1.0, 2.0, 1.0, 2.0};
+    for (int t = 0; t < 6; t++)
+      o[4 + t] = ge * theta[6 * (size_t)r + t] - (g_efgrad ? mult[t] * g_efgrad[6 * (size_t)r + t] : 0.0);
+    v[0] = o[0];
+  }
+  double tot[1];
+  block_sum256<1>(v, tot);
+  if (threadIdx.x == 0 && blockIdx.x * 256 < fr.nq) atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[0]);
+}
+
+hipError_t launch_eff_moments(const FrameArg& fa, int max_nq, const double* Q, const double* mu, const double* theta,
+                              const double* gE, const double* g_phi, const double* g_efield, const double* g_efgrad,
+                              Work& w, hipStream_t s) {
+  if (max_nq == 0) return hipSuccess;
+  dim3 grid((max_nq + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_eff_moments, grid, dim3(256), 0, s, fa, Q, mu, theta, gE, g_phi, g_efield, g_efgrad, w.qeff,
+                     w.facc);
+  return hipGetLastError();
+}
+
+// MM outputs: sum the reciprocal partials over column chunks, add the real-space part
+// and the background term -(pi/(a^2 V)) Q'_tot of dL/dq.
+__global__ __launch_bounds__(256) void k_reduce_mm(Grid g, FrameArg fa, int kc_n, int cap_mm,
+                                                   const double* __restrict__ mm4, const double* __restrict__ fpart,
+                                                   const double* __restrict__ rpart,
+                                                   const double* __restrict__ facc, double* __restrict__ g_mm_xyz,
+                                                   double* __restrict__ g_mm_q) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= fr.nm) return;
+  const int row = fr.moff + i;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int kc = 0; kc < kc_n; kc++) {
+    const double* p = fpart + ((size_t)kc * cap_mm + row) * 4;
+    s0 += p[0];
+    s1 += p[1];
+    s2 += p[2];
+    s3 += p[3];
+  }
+  const double q = mm4[(size_t)3 * cap_mm + row];
+  const double* rp = rpart + (size_t)row * 4;
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  g_mm_xyz[3 * (size_t)row + 0] = q * s1 + rp[1];
+  g_mm_xyz[3 * (size_t)row + 1] = q * s2 + rp[2];
+  g_mm_xyz[3 * (size_t)row + 2] = q * s3 + rp[3];
+  if (g_mm_q) g_mm_q[row] = s0 + rp[0] - kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
+}
+
+hipError_t launch_reduce_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                            double* g_mm_xyz, double* g_mm_q, Work& w, hipStream_t s) {
+  if (max_nm == 0) return hipSuccess;
+  dim3 grid((max_nm + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_reduce_mm, grid, dim3(256), 0, s, g, fa, t.kc, cap_mm, w.mm4, w.fpart, w.rpart, w.facc,
+                     g_mm_xyz, g_mm_q);
+  return hipGetLastError();
+}
+
+// QM outputs of the backward pass.
+__global__ __launch_bounds__(256) void k_finalize_bwd(FrameArg fa, const double* __restrict__ site,
+                                                      const double* __restrict__ gE, int qmqm,
+                                                      const double* __restrict__ qacc, double* __restrict__ g_qm_xyz,
+                                                      double* __restrict__ g_Q, double* __restrict__ g_mu,
+                                                      double* __restrict__ g_theta) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= fr.nq) return;
+  const int r = fr.qoff + j;
+  const double ge = gE ? gE[0] : 1.0;
+  const double* qa = qacc + (size_t)r * QA_STRIDE;
+  const double* st = site + 10 * (size_t)r;
+  const double w = qmqm ? 1.0 : 0.0;
+  for (int t = 0; t < 3; t++)
+    g_qm_xyz[3 * (size_t)r + t] =
+        qa[QA_G_QMMM_SR + t] + qa[QA_G_QMMM_LR + t] + ge * w * (qa[QA_G_QQ_LR + t] + qa[QA_G_QQ_SR + t]);
+  g_Q[r] = ge * (st[0] + w * (qa[QA_DQ_QQ_LR] + qa[QA_DQ_QQ_SR]));
+  for (int t = 0; t < 3; t++)
+    g_mu[3 * (size_t)r + t] = ge * (st[1 + t] + w * (qa[QA_DMU_QQ_LR + t] + qa[QA_DMU_QQ_SR + t]));
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  for (int t = 0; t < 6; t++)
+    g_theta[6 * (size_t)r + t] = ge * mult[t] * (st[4 + t] + w * (qa[QA_DTH_QQ_LR + t] + qa[QA_DTH_QQ_SR + t]));
+}
+
+hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
+                               double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s) {
+  if (max_nq == 0) return hipSuccess;
+  dim3 grid((max_nq + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_finalize_bwd, grid, dim3(256), 0, s, fa, site, gE, qmqm, w.qacc, g_qm_xyz, g_Q, g_mu, g_theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
+                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
+                       int cap_mm) {
+  const int nmax = max_nq > max_nm ? max_nq : max_nm;
+  if (nmax > 0) {
+    dim3 grid((nmax + 255) / 256, fa.n_frames);
+    hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, w.qm4, cap_qm, w.mm4, cap_mm,
+                       w.facc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (max_nm > 0) {
+    const long n = (long)max_nm * g.R;
+    dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, w.mm4, cap_mm, w.mm_tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (max_nq > 0) {
+    const long n = (long)max_nq * g.R;
+    dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 1, w.qm4, cap_qm, w.qm_tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mpe
