@@ -1,0 +1,232 @@
+"""Benchmark: multipolar-Ewald QM/MM forward+backward frames/s on one MI355X.
+
+Workload (headline): 70x70x72 A box, 35,000 MM point charges (>= 1 A apart,
+neutral, U(-0.9,0.9)), 40 QM sites with charge, dipole and quadrupole, alpha
+0.22 /A, real cutoff 12 A, |n| <= 24 per axis, FP64.  One step = the
+differentiable forward pass (energy, potential, field and field gradient at
+the QM sites) plus the adjoint (gradients for every QM and MM input) through
+torch.autograd; inputs are resident in HBM when timing starts.
+
+Prints ONE JSON line.  Extra keys: per-kernel durations, the roofline of the
+dominant kernel (achieved algorithmic FP64 rate against the 78.6 TFLOP/s
+vector peak), the unoptimised plain forward path, a 64-frame batched run and
+the CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+METRIC = "QM/MM Ewald fwd+bwd frames/s at 35k MM charges; % FP64 roofline vs plain path"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def n_half_space(m):
+    mx, my, mz = m
+    return ((2 * mx + 1) * (2 * my + 1) * (2 * mz + 1) - 1) // 2
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ewald_internal.h"):
+        with open(os.path.join(ROOT, "paper_2408_03273_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, src_hash: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(PROFILES, "traffic_c3.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and batched measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one device-to-device copy of 256 MiB (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2408_03273_amd import workloads as wl
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan, ewald
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    s = wl.make_config(3)
+    nh = n_half_space(s.kmax)
+    # the plan records HIP events around every launch on the stream it runs on
+    pplan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                             profile=True))
+
+    def tens(a, grad=True):
+        return torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
+
+    inputs = [tens(a) for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+
+    def step(p):
+        for t in inputs:
+            t.grad = None
+        E, phi, efield, efgrad = ewald(p, *inputs)
+        E.backward()
+        return E
+
+    for _ in range(args.warmup):
+        step(pplan)
+    torch.cuda.synchronize()
+    pplan.profile_report()  # discard warm-up timings
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E = step(pplan)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    kern = pplan.profile_report()
+    assert np.isfinite(E.item())
+
+    # per-kernel averages and the roofline of the dominant hot kernel
+    per = {k: dict(count=v["count"], avg_us=1e3 * v["total_ms"] / max(v["count"], 1),
+                   ms_per_step=v["total_ms"] / args.steps) for k, v in kern.items()}
+    flops = {"sfac_mm": 8.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm}
+    hot = {k: per[k] for k in flops if k in per}
+    dom = max(hot, key=lambda k: hot[k]["ms_per_step"])
+    achieved = flops[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12
+    src_hash = kernel_source_hash()
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=traffic_from_profiles(dom, src_hash),
+                kernel=dom, flops_per_launch=flops[dom], avg_launch_us=round(per[dom]["avg_us"], 2))
+    hot_total_us = sum(per[k]["avg_us"] for k in hot)
+    path_flops = 14.0 * nh * s.nm
+    extra = dict(
+        hot_path=dict(kernels=sorted(hot), flops_per_step=path_flops, kernel_us=round(hot_total_us, 2),
+                      frac_of_fp64_peak=round(path_flops / (hot_total_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                      step_frac_of_fp64_peak=round(path_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
+        kernels={k: dict(avg_us=round(v["avg_us"], 2), per_step=round(v["count"] / args.steps, 2))
+                 for k, v in per.items()},
+        kernel_source_hash=src_hash, plan=pplan.describe())
+
+    if not args.no_extras:
+        extra["plain_path"] = _plain_path(s, dev, nh)
+        extra["batch_c4"] = _batch_c4(dev)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(s)
+
+    line = {
+        "metric": METRIC, "value": round(1e3 / ms, 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c3: box 70x70x72 A, 35000 MM charges, 40 QM multipole sites, alpha 0.22, rcut 12 A, "
+                               "|n|<=24, fwd+bwd via autograd, FP64",
+                   "n_mm": s.nm, "n_qm": s.nq, "kmax": list(s.kmax), "n_kvec_half_space": nh,
+                   "alpha": s.alpha, "rcut": s.rcut, "box": list(map(float, s.box)), "input_sha256": s.sha256()[:16]},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def _plain_path(s, dev, nh, steps=5):
+    """Unoptimised forward path (one thread per k, sincos per (k, atom))."""
+    import torch
+
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan
+    plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                            plain=True))
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa: E731
+    x = [t(a) for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+    plan.forward(*x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(*x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fl = 8.0 * nh * s.nm
+    plan.close()
+    return dict(ms_per_frame_fwd=round(ms, 3), frames_per_s_fwd=round(1e3 / ms, 2),
+                frac_of_fp64_peak=round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4))
+
+
+def _batch_c4(dev, steps=5):
+    """64 independent frames of uneven size through one graph-replayed batch call."""
+    import numpy as np
+    import torch
+
+    from paper_2408_03273_amd import workloads as wl
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan
+    frames = [wl.make_config(4, f) for f in range(64)]
+    qoff = np.cumsum([0] + [f.nq for f in frames])
+    moff = np.cumsum([0] + [f.nm for f in frames])
+    desc = [dict(box=f.box, n_qm=f.nq, n_mm=f.nm, qm_offset=int(qoff[i]), mm_offset=int(moff[i]))
+            for i, f in enumerate(frames)]
+    cat = lambda k: torch.tensor(np.concatenate([getattr(f, k) for f in frames]), dtype=torch.float64,  # noqa: E731
+                                 device=dev)
+    x = [cat("qm_pos"), cat("Q"), cat("mu"), cat("theta"), cat("mm_pos"), cat("q")]
+    f0 = frames[0]
+    plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
+                            max_mm=int(moff[-1]), max_frames=64))
+    out = plan.batch(desc, *x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.batch(desc, *x, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    nh = n_half_space(f0.kmax)
+    fl = 14.0 * nh * float(moff[-1])
+    plan.close()
+    return dict(frames=64, total_mm=int(moff[-1]), ms_per_batch=round(ms, 3), frames_per_s=round(64e3 / ms, 1),
+                frac_of_fp64_peak=round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4))
+
+
+def _cpu_baseline(s):
+    """The FP64 CPU oracle, as it stands, on one full c3 frame (forward and all gradients)."""
+    from oracle.oracle import num_threads, oracle_ewald
+    t0 = time.perf_counter()
+    r = oracle_ewald(s.box, s.alpha, s.rcut, s.kmax, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)
+    dt = time.perf_counter() - t0
+    assert r.E == r.E
+    return dict(value=round(1.0 / dt, 5), unit="frames/s", cores=num_threads(), kind="oracle",
+                sample="one full c3 frame (35000 MM, 40 QM, |n|<=24): energy, fields and every gradient",
+                seconds=round(dt, 2))
+
+
+if __name__ == "__main__":
+    main()

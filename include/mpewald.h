@@ -72,7 +72,9 @@ enum {
   EWALD_QMQM = 1,          /* include the QM-QM image terms (on in the tests) */
   EWALD_PLAIN = 2,         /* forward uses the unoptimised reference GPU path:
                               one thread per k, direct sincos per (k, atom) */
-  EWALD_CELL_LIST = 4      /* real space visits only neighbouring cells */
+  EWALD_CELL_LIST = 4,     /* real space visits only neighbouring cells */
+  EWALD_PROFILE = 8        /* time every kernel launch with events on its stream
+                              (single-frame calls only; read with ewald_profile_report) */
 };
 
 typedef struct {
@@ -153,6 +155,12 @@ ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewald_frame_t* 
  * system of n_mm MM charges on the plan's device and keep the fastest in the
  * plan (and in cache_path as JSON lines if not null).  Synchronises. */
 ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char* cache_path);
+
+/* Per-kernel launch counts and summed durations (ms) since the last report,
+ * as a JSON object, for plans created with EWALD_PROFILE (for benchmark
+ * reports).  Synchronises on the recorded events.  Returns EWALD_ERR_ARG if
+ * len is too small. */
+ewald_status_t ewald_profile_report(ewald_plan* plan, char* buf, size_t len);
 
 /* Tile configuration in use (for reports): forward nz chunk, backward
  * columns per block, etc., as a short text. */

@@ -20,6 +20,7 @@ EWALD_FP32_REAL = 1
 EWALD_QMQM = 1
 EWALD_PLAIN = 2
 EWALD_CELL_LIST = 4
+EWALD_PROFILE = 8
 
 EWALD_FWD = 0
 EWALD_FWD_BWD = 1
@@ -29,7 +30,8 @@ STATUS_NAMES = {0: "EWALD_OK", -1: "EWALD_ERR_ARG", -2: "EWALD_ERR_CUTOFF", -3: 
 
 # every symbol the public header declares
 EXPORTED = ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_ctx_bytes", "ewald_forward", "ewald_backward",
-            "ewald_batch", "ewald_autotune", "ewald_plan_describe", "ewald_last_error", "ewald_version")
+            "ewald_batch", "ewald_autotune", "ewald_profile_report", "ewald_plan_describe", "ewald_last_error",
+            "ewald_version")
 
 
 class EwaldParams(ctypes.Structure):
@@ -71,6 +73,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_batch.argtypes = [vp, ip, ctypes.POINTER(EwaldFrame), vp, vp, vp, vp, vp, vp, ip, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     lib.ewald_autotune.argtypes = [vp, ip, ctypes.c_char_p]
+    lib.ewald_profile_report.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.ewald_plan_describe.argtypes = [vp]
     lib.ewald_plan_describe.restype = ctypes.c_char_p
     lib.ewald_last_error.argtypes = []
@@ -78,7 +81,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_version.argtypes = []
     lib.ewald_version.restype = ctypes.c_char_p
     for name in ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_forward", "ewald_backward", "ewald_batch",
-                 "ewald_autotune"):
+                 "ewald_autotune", "ewald_profile_report"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

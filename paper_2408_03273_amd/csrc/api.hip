@@ -56,9 +56,47 @@ struct ewald_plan {
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
   std::vector<FrameDev> host_frames;
+  // kernel timing (EWALD_PROFILE)
+  struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<std::string, std::pair<long, double>>> prof_acc;
+  bool capturing = false;
 };
 
 namespace {
+
+bool profiling(const ewald_plan* pl) { return (pl->p.flags & EWALD_PROFILE) && !pl->capturing; }
+
+hipEvent_t pool_event(ewald_plan* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Bracket one launch with events on its own stream.
+struct ProfScope {
+  ewald_plan* pl;
+  hipStream_t s;
+  bool on;
+  ProfScope(ewald_plan* p, const char* name, hipStream_t st) : pl(p), s(st), on(profiling(p)) {
+    if (!on) return;
+    ewald_plan::ProfRec r{name, pool_event(pl), pool_event(pl)};
+    (void)hipEventRecord(r.a, s);
+    pl->prof_pending.push_back(r);
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(pl->prof_pending.back().b, s);
+  }
+};
 
 ewald_status_t validate_box(const double box[3], double rcut) {
   for (int a = 0; a < 3; a++)
@@ -105,6 +143,13 @@ void free_plan(ewald_plan* pl) {
   if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
   if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  for (auto& r : pl->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pl->ev_pool) (void)hipEventDestroy(e);
+  pl->prof_pending.clear();
+  pl->ev_pool.clear();
   for (void* p : pl->allocs) (void)hipFree(p);
   pl->allocs.clear();
 }
@@ -198,11 +243,16 @@ struct Seq {
   int qmqm;
 };
 
-#define LCHK(expr)                                                                                  \
+#define LCHK_P(pl_, s_, name, expr)                                                                 \
   do {                                                                                              \
-    hipError_t e_ = (expr);                                                                         \
+    hipError_t e_;                                                                                  \
+    {                                                                                               \
+      ProfScope ps_(pl_, name, s_);                                                                 \
+      e_ = (expr);                                                                                  \
+    }                                                                                               \
     if (e_ != hipSuccess) return fail(EWALD_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+#define LCHK(expr) LCHK_P(pl, q.s, #expr, expr)
 
 ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mm_xyz,
                          const double* mm_q) {
@@ -244,7 +294,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   ewald_status_t st = validate_box(p.box, p.rcut);
   if (st != EWALD_OK) return st;
   if (p.precision != EWALD_FP64 && p.precision != EWALD_FP32_REAL) return fail(EWALD_ERR_ARG, "unknown precision");
-  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST)) return fail(EWALD_ERR_ARG, "unknown flags");
+  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE)) return fail(EWALD_ERR_ARG, "unknown flags");
   if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
   ewald_plan* pl = new ewald_plan();
   pl->p = p;
@@ -351,12 +401,22 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.fa.n_frames = 1;
   st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
   if (st == EWALD_OK) {
-    hipError_t e = launch_sfac_qm(plan->g, q.fa, n_qm, Q, mu, theta, plan->w.qeff, nullptr, 0, plan->w, s);
+    hipError_t e;
+    {
+      ProfScope ps(plan, "launch_sfac_qm", s);
+      e = launch_sfac_qm(plan->g, q.fa, n_qm, Q, mu, theta, plan->w.qeff, nullptr, 0, plan->w, s);
+    }
     if (e != hipSuccess) st = fail(EWALD_ERR_HIP, "sfac_qm launch: %s", hipGetErrorString(e));
   }
   if (st == EWALD_OK) {
-    hipError_t e = q.plain ? launch_sfac_mm_plain(plan->g, q.fa, plan->cap_mm, plan->w, s)
-                           : launch_sfac_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s);
+    hipError_t e;
+    if (q.plain) {
+      ProfScope ps(plan, "launch_sfac_mm_plain", s);
+      e = launch_sfac_mm_plain(plan->g, q.fa, plan->cap_mm, plan->w, s);
+    } else {
+      ProfScope ps(plan, "launch_sfac_mm", s);
+      e = launch_sfac_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s);
+    }
     if (e != hipSuccess) st = fail(EWALD_ERR_HIP, "sfac_mm launch: %s", hipGetErrorString(e));
   }
   if (st == EWALD_OK) {
@@ -401,7 +461,11 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   const Grid& g = plan->g;
 #define STEP(expr)                                                                                     \
   do {                                                                                                 \
-    hipError_t e_ = (expr);                                                                            \
+    hipError_t e_;                                                                                     \
+    {                                                                                                  \
+      ProfScope ps_(plan, #expr, s);                                                                   \
+      e_ = (expr);                                                                                     \
+    }                                                                                                  \
     if (e_ != hipSuccess) {                                                                            \
       plan->t = saved;                                                                                 \
       return fail(EWALD_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_));                      \
@@ -435,6 +499,7 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
                              const double* theta, const double* mm_xyz, const double* mm_q, int mode, double* energy,
                              double* phi, double* efield, double* efgrad, double* g_qm_xyz, double* g_Q,
                              double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q) {
+  ewald_plan* pl = plan;
   Seq q;
   q.pl = plan;
   q.s = s;
@@ -551,10 +616,13 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     plan->t = use;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal));
-    st = enqueue_batch(plan, plan->gstream, n_frames, max_nq, max_nm, (int)total_nq, (int)total_nm, qm_xyz, Q, mu,
+    plan->capturing = true;
+    // QM accumulators are indexed by packed row, so clear every row up to the last one used
+    st = enqueue_batch(plan, plan->gstream, n_frames, max_nq, max_nm, (int)end_q, (int)total_nm, qm_xyz, Q, mu,
                        theta, mm_xyz, mm_q, mode, energy, phi, efield, efgrad, g_qm_xyz, g_Q, g_mu, g_theta,
                        g_mm_xyz, g_mm_q);
     hipError_t ce = hipStreamEndCapture(plan->gstream, &graph);
+    plan->capturing = false;
     plan->t = saved;
     if (st != EWALD_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -574,6 +642,44 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   HIPCHK(hipGraphLaunch(plan->gexec, plan->gstream));
   HIPCHK(hipEventRecord(plan->ev_out, plan->gstream));
   HIPCHK(hipStreamWaitEvent(s, plan->ev_out, 0));
+  return EWALD_OK;
+}
+
+// ---------------------------------------------------------------- kernel timing report
+extern "C" ewald_status_t ewald_profile_report(ewald_plan* plan, char* buf, size_t len) {
+  if (!plan || !buf || len == 0) return fail(EWALD_ERR_ARG, "null plan or buffer");
+  for (auto& r : plan->prof_pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return fail(EWALD_ERR_HIP, "profile event: %s", hipGetErrorString(e));
+    std::string name(r.name);
+    const size_t cut = name.find('(');
+    if (cut != std::string::npos) name = name.substr(0, cut);
+    if (name.rfind("launch_", 0) == 0) name = name.substr(7);
+    bool found = false;
+    for (auto& a : plan->prof_acc)
+      if (a.first == name) {
+        a.second.first += 1;
+        a.second.second += ms;
+        found = true;
+      }
+    if (!found) plan->prof_acc.push_back({name, {1, (double)ms}});
+    plan->ev_pool.push_back(r.a);
+    plan->ev_pool.push_back(r.b);
+  }
+  plan->prof_pending.clear();
+  std::string out = "{";
+  for (size_t i = 0; i < plan->prof_acc.size(); i++) {
+    char item[160];
+    snprintf(item, sizeof(item), "%s\"%s\": {\"count\": %ld, \"total_ms\": %.6f}", i ? ", " : "",
+             plan->prof_acc[i].first.c_str(), plan->prof_acc[i].second.first, plan->prof_acc[i].second.second);
+    out += item;
+  }
+  out += "}";
+  plan->prof_acc.clear();
+  if (out.size() + 1 > len) return fail(EWALD_ERR_ARG, "report needs %zu bytes", out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
   return EWALD_OK;
 }
 

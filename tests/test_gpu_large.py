@@ -1,0 +1,90 @@
+"""Full-size workloads against stored oracle values (tests/golden/oracle_*.json,
+written by tests/golden/make_golden.py from the CPU oracle only): c3 as one
+frame through autograd, c4 and c5 through the batched path exactly as the
+benchmark runs them; QM outputs compared in full, MM gradients on the stored
+sample of rows."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2408_03273_amd import workloads as wl
+from paper_2408_03273_amd.ewald import EwaldConfig, Plan, ewald
+from tests import _harness as H
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-10
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"oracle_{name}.json")) as f:
+        return json.load(f)
+
+
+def _check(got, g, name):
+    sel = np.array(g["mm_sel"])
+    errs = {}
+    for k in H.FWD_KEYS + H.BWD_KEYS:
+        ref = np.asarray(g[k])
+        a = np.asarray(got[k])
+        if k in ("g_mm_pos", "g_mm_q"):
+            a = a[sel]
+        errs[k] = H.relerr(a, ref)
+    print(f"[large] {name}: worst {max(errs.values()):.2e}", flush=True)
+    assert max(errs.values()) <= TOL, (name, errs)
+
+
+def test_c3_autograd_full_size():
+    s = wl.make_config(3)
+    g = _golden("c3_f0")
+    assert s.sha256() == g["input_sha256"], "generator output changed"
+    dev = torch.device("cuda", 0)
+    x = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)
+         for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+    plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm))
+    E, phi, efield, efgrad = ewald(plan, *x)
+    E.backward()
+    got = dict(energy=E.item(), phi=phi.detach().cpu().numpy(), efield=efield.detach().cpu().numpy(),
+               efgrad=efgrad.detach().cpu().numpy(), g_qm_pos=x[0].grad.cpu().numpy(), g_Q=x[1].grad.cpu().numpy(),
+               g_mu=x[2].grad.cpu().numpy(), g_theta=x[3].grad.cpu().numpy(), g_mm_pos=x[4].grad.cpu().numpy(),
+               g_mm_q=x[5].grad.cpu().numpy())
+    _check(got, g, "c3")
+
+
+def _batch_config(cfg, nframes, check):
+    frames = [wl.make_config(cfg, f) for f in range(nframes)]
+    qoff = np.cumsum([0] + [f.nq for f in frames])
+    moff = np.cumsum([0] + [f.nm for f in frames])
+    desc = [dict(box=f.box, n_qm=f.nq, n_mm=f.nm, qm_offset=int(qoff[i]), mm_offset=int(moff[i]))
+            for i, f in enumerate(frames)]
+    dev = torch.device("cuda", 0)
+    cat = lambda k: torch.tensor(np.concatenate([getattr(f, k) for f in frames]), dtype=torch.float64,  # noqa: E731
+                                 device=dev)
+    x = [cat("qm_pos"), cat("Q"), cat("mu"), cat("theta"), cat("mm_pos"), cat("q")]
+    f0 = frames[0]
+    plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
+                            max_mm=int(moff[-1]), max_frames=nframes))
+    print(f"[large] c{cfg}: {nframes} frames, {int(moff[-1])} MM rows", flush=True)
+    out = plan.batch(desc, *x)
+    out = plan.batch(desc, *x, out=out)   # second call replays the graph
+    torch.cuda.synchronize()
+    o = {k: v.cpu().numpy() for k, v in out.items()}
+    for i in check:
+        g = _golden(f"c{cfg}_f{i}")
+        assert frames[i].sha256() == g["input_sha256"], "generator output changed"
+        sq, sm = slice(qoff[i], qoff[i + 1]), slice(moff[i], moff[i + 1])
+        got = dict(energy=o["energy"][i], phi=o["phi"][sq], efield=o["efield"][sq], efgrad=o["efgrad"][sq],
+                   g_qm_pos=o["g_qm_pos"][sq], g_Q=o["g_Q"][sq], g_mu=o["g_mu"][sq], g_theta=o["g_theta"][sq],
+                   g_mm_pos=o["g_mm_pos"][sm], g_mm_q=o["g_mm_q"][sm])
+        _check(got, g, f"c{cfg}_f{i}")
+
+
+def test_c4_batch_64_frames():
+    _batch_config(4, 64, check=(0, 1, 2))
+
+
+def test_c5_batch_16_replicas():
+    _batch_config(5, 16, check=(0,))
