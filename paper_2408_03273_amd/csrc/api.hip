@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -53,6 +54,9 @@ struct ewald_plan {
   // batched graph state
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // second stream for the adjoint chain that runs beside the forward chain
+  hipStream_t aux = nullptr, gaux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
   std::vector<FrameDev> host_frames;
@@ -120,6 +124,8 @@ Grid make_grid(const ewald_params_t& p) {
   g.Zc = pick_zc(g.NZ);
   g.NZP = ((g.NZ + g.Zc - 1) / g.Zc) * g.Zc;
   g.R = g.NX + g.NY + g.NZP;
+  g.NG = (g.NCOL + 15) / 16;
+  g.NKS = (g.NZ + 3) / 4;
   g.alpha = p.alpha;
   g.rcut = p.rcut;
   return g;
@@ -138,11 +144,16 @@ ewald_status_t alloc(ewald_plan* pl, T** ptr, size_t count) {
 
 int fwd_kblocks(const Grid& g) { return ((g.NCOL + 63) / 64) * (g.NZP / g.Zc); }
 
+
 void free_plan(ewald_plan* pl) {
   if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
   if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
   if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  if (pl->aux) (void)hipStreamDestroy(pl->aux);
+  if (pl->gaux) (void)hipStreamDestroy(pl->gaux);
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
   for (auto& r : pl->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -156,8 +167,10 @@ void free_plan(ewald_plan* pl) {
 
 void set_describe(ewald_plan* pl) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "zc=%d nzp=%d a_chunk=auto kc=%d kgrid=%dx%dx%d precision=%s", pl->g.Zc, pl->g.NZP,
-           pl->t.kc, pl->g.NX, pl->g.NY, pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
+  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-16col", "mfma-16col"};
+  snprintf(buf, sizeof(buf), "fwd=valu zc=%d nzp=%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", pl->g.Zc, pl->g.NZP,
+           bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY,
+           pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
   pl->describe = buf;
 }
 
@@ -182,7 +195,7 @@ int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
   long total = 0;
   for (int n : nms) total += n;
   const long kb = fwd_kblocks(pl->g);
-  long ac = (kb * total + kTargetBlocks - 1) / kTargetBlocks;
+  long ac = (kb * total + pl->t.fwd_target - 1) / pl->t.fwd_target;
   ac = ((ac + 255) / 256) * 256;
   if (ac < 256) ac = 256;
   if (pl->t.a_chunk > 0) ac = pl->t.a_chunk;  // tuned value
@@ -196,7 +209,8 @@ int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
 }
 
 int choose_kc(const ewald_plan* pl, long total_nm) {
-  const long ablocks = std::max<long>(1, (total_nm + 255) / 256);
+  const long per_block = pl->t.bwd_ilp >= 3 ? 64L : 256L * (pl->t.bwd_ilp == 1 ? 1 : 2);
+  const long ablocks = std::max<long>(1, (total_nm + per_block - 1) / per_block);
   long kc = (kTargetBlocks + ablocks - 1) / ablocks;
   if (pl->t.kc > 0) kc = pl->t.kc;
   kc = std::max<long>(1, std::min<long>(kc, pl->cap_kc));
@@ -204,23 +218,47 @@ int choose_kc(const ewald_plan* pl, long total_nm) {
   return (int)kc;
 }
 
+// Caller-owned context of one forward call:
+//   S_MM(k) | MM potential data at the QM sites (10 per site) |
+//   gradients of E for unit upstream gradient: QM (3+1+3+6 per site), MM (3+1 per atom)
 struct CtxView {
   double2* smm;
   double* site;
+  double* gq;   // [nq][3]
+  double* gQ;   // [nq]
+  double* gmu;  // [nq][3]
+  double* gth;  // [nq][6]
+  double* gm;   // [nm][3]
+  double* gmq;  // [nm]
 };
 
-size_t ctx_bytes(const Grid& g, int nq) {
-  size_t a = (size_t)g.KF * sizeof(double2);
-  a = (a + 255) & ~(size_t)255;
-  return a + (size_t)std::max(nq, 1) * 10 * sizeof(double);
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t ctx_bytes(const Grid& g, int nq, int nm) {
+  const size_t q = (size_t)std::max(nq, 1), m = (size_t)std::max(nm, 1);
+  return align256((size_t)g.KF * sizeof(double2)) + align256(q * 10 * 8) + 4 * align256(q * 6 * 8) +
+         2 * align256(m * 3 * 8);
 }
 
-CtxView ctx_view(const Grid& g, void* ctx) {
-  size_t a = (size_t)g.KF * sizeof(double2);
-  a = (a + 255) & ~(size_t)255;
+CtxView ctx_view(const Grid& g, void* ctx, int nq, int nm) {
+  const size_t q = (size_t)std::max(nq, 1), m = (size_t)std::max(nm, 1);
+  char* p = (char*)ctx;
   CtxView v;
-  v.smm = (double2*)ctx;
-  v.site = (double*)((char*)ctx + a);
+  v.smm = (double2*)p;
+  p += align256((size_t)g.KF * sizeof(double2));
+  v.site = (double*)p;
+  p += align256(q * 10 * 8);
+  v.gq = (double*)p;
+  p += align256(q * 6 * 8);
+  v.gQ = (double*)p;
+  p += align256(q * 6 * 8);
+  v.gmu = (double*)p;
+  p += align256(q * 6 * 8);
+  v.gth = (double*)p;
+  p += align256(q * 6 * 8);
+  v.gm = (double*)p;
+  p += align256(m * 3 * 8);
+  v.gmq = (double*)p;
   return v;
 }
 
@@ -255,11 +293,12 @@ struct Seq {
 #define LCHK(expr) LCHK_P(pl, q.s, #expr, expr)
 
 ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mm_xyz,
-                         const double* mm_q) {
+                         const double* mm_q, int mm_tables) {
   ewald_plan* pl = q.pl;
   LCHK(launch_zero(pl->w.qacc, (size_t)q.total_nq * QA_STRIDE, q.s));
   LCHK(launch_zero(pl->w.facc, (size_t)q.fa.n_frames * FA_COUNT, q.s));
-  LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm, pl->cap_mm));
+  LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm, pl->cap_mm,
+                   mm_tables));
   return EWALD_OK;
 }
 
@@ -270,8 +309,60 @@ ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu,
   LCHK(launch_reduce_smm(pl->g, pl->t, q.fa, q.plain, smm, smm_stride, pl->w, q.s));
   LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 0, q.qmqm, pl->w, q.s));
   LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
-  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, pl->cap_qm, Q, mu, theta, pl->w, q.s));
+  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
   LCHK(launch_finalize_fwd(pl->g, q.fa, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad, site, pl->w, q.s));
+  return EWALD_OK;
+}
+
+ewald_status_t fork_to(ewald_plan* pl, hipStream_t from, hipStream_t to) {
+  HIPCHK(hipEventRecord(pl->ev_fork, from));
+  HIPCHK(hipStreamWaitEvent(to, pl->ev_fork, 0));
+  return EWALD_OK;
+}
+
+ewald_status_t join_to(ewald_plan* pl, hipStream_t from, hipStream_t to) {
+  HIPCHK(hipEventRecord(pl->ev_join, from));
+  HIPCHK(hipStreamWaitEvent(to, pl->ev_join, 0));
+  return EWALD_OK;
+}
+
+// Forward pass and the gradients of E (upstream gradient 1) in one sequence.
+// The reciprocal MM adjoint (matrix cores) runs on a second stream beside the
+// forward structure factor (vector units); both need only the phase tables
+// and the QM structure factors.
+ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, const double* Q, const double* mu,
+                           const double* theta, const double* mm_xyz, const double* mm_q, double2* smm,
+                           size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
+                           double* site, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
+                           double* g_mm_xyz, double* g_mm_q) {
+  ewald_plan* pl = q.pl;
+  Work& w = pl->w;
+  const Grid& g = pl->g;
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, 1);
+  if (st != EWALD_OK) return st;
+  LCHK(launch_eff_moments(q.fa, q.max_nq, Q, mu, theta, nullptr, nullptr, nullptr, nullptr, w, q.s));
+  LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
+  st = fork_to(pl, q.s, aux);
+  if (st != EWALD_OK) return st;
+  {
+    Seq qa = q;
+    qa.s = aux;
+    const Seq& q_ = qa;
+    {
+      const Seq& q = q_;
+      LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
+      LCHK(launch_real_mm(g, q.fa, q.max_nm, pl->cap_qm, pl->cap_mm, q.fp32, w, q.s));
+      LCHK(launch_reduce_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, g_mm_xyz, g_mm_q, w, q.s));
+    }
+  }
+  LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
+  st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site);
+  if (st != EWALD_OK) return st;
+  st = join_to(pl, aux, q.s);
+  if (st != EWALD_OK) return st;
+  LCHK(launch_project_qm(g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 1, q.qmqm, w, q.s));
+  LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
+  LCHK(launch_finalize_bwd(q.fa, q.max_nq, site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
   return EWALD_OK;
 }
 
@@ -306,11 +397,25 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->t.zc = pl->g.Zc;
   pl->t.a_chunk = 0;
   pl->t.kc = 0;
-  pl->t.bwd_ilp = 1;
+  pl->t.bwd_ilp = 3;
+  pl->t.fwd_pf = 0;
+  pl->t.fwd_target = 8192;
+  // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
+  // atoms per lane) or 3 (matrix cores); MPEWALD_FWD_PF = 0|1 (prefetch);
+  // MPEWALD_FWD_TARGET = forward block count target
+  if (const char* e = getenv("MPEWALD_BWD")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 3) pl->t.bwd_ilp = v;
+  }
+  if (const char* e = getenv("MPEWALD_FWD_PF")) pl->t.fwd_pf = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_FWD_TARGET")) {
+    const int v = atoi(e);
+    if (v >= 64 && v <= 65536) pl->t.fwd_target = v;
+  }
   pl->cap_qm = std::max(p.max_qm, 1);
   pl->cap_mm = std::max(p.max_mm, 1);
   pl->cap_frames = p.max_frames;
-  pl->cap_slots = std::max(64, 2 * kTargetBlocks / std::max(1, fwd_kblocks(pl->g)) + 2 * pl->cap_frames);
+  pl->cap_slots = std::max(64, 4 * kTargetBlocks / std::max(1, fwd_kblocks(pl->g)) + 2 * pl->cap_frames);
   pl->cap_kc = (int)std::max<long>(1, std::min<long>(16, (kTargetBlocks * 256L + pl->cap_mm - 1) / pl->cap_mm));
   const Grid& g = pl->g;
   Work& w = pl->w;
@@ -331,6 +436,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.sabc, cf * g.KF * 3);
   A(w.wk, cf * g.KF);
   A(w.smm, cf * g.KF);
+  A(w.kw, cf * g.KF);
+  A(w.wfrag, cf * (size_t)g.NG * g.NKS * 64 * 2);
   A(w.spart, (size_t)pl->cap_slots * g.NZP * g.NCOL);
   A(w.fpart, (size_t)pl->cap_kc * cm * 4);
   A(w.rpart, cm * 4);
@@ -342,10 +449,18 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.frames, cf);
 #undef A
   const double one = 1.0;
-  if (hipMemcpy(w.one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemset(w.wfrag, 0, sizeof(double2) * cf * (size_t)g.NG * g.NKS * 64 * 2) != hipSuccess ||
+      hipMemcpy(w.one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     free_plan(pl);
     delete pl;
     return fail(EWALD_ERR_HIP, "hipMemcpy failed");
+  }
+  if (hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
+    free_plan(pl);
+    delete pl;
+    return fail(EWALD_ERR_HIP, "stream or event creation failed");
   }
   set_describe(pl);
   *plan = pl;
@@ -370,7 +485,7 @@ ewald_status_t ewald_set_box(ewald_plan* plan, const double box[3]) {
 size_t ewald_ctx_bytes(const ewald_plan* plan, int n_qm, int n_mm) {
   (void)n_mm;
   if (!plan) return 0;
-  return ctx_bytes(plan->g, n_qm);
+  return ctx_bytes(plan->g, n_qm, n_mm);
 }
 
 const char* ewald_plan_describe(const ewald_plan* plan) { return plan ? plan->describe.c_str() : ""; }
@@ -399,7 +514,15 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.fa.frames = nullptr;
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
   q.fa.n_frames = 1;
-  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
+  if (ctx && !q.plain) {
+    plan->t.kc = choose_kc(plan, n_mm);
+    CtxView cv = ctx_view(plan->g, ctx, n_qm, n_mm);
+    st = seq_fwd_bwd(q, plan->aux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, cv.smm, plan->g.KF, energy, phi, efield,
+                     efgrad, cv.site, cv.gq, cv.gQ, cv.gmu, cv.gth, cv.gm, cv.gmq);
+    plan->t = saved;
+    return st;
+  }
+  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, q.plain ? 0 : 1);
   if (st == EWALD_OK) {
     hipError_t e;
     {
@@ -420,8 +543,10 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
     if (e != hipSuccess) st = fail(EWALD_ERR_HIP, "sfac_mm launch: %s", hipGetErrorString(e));
   }
   if (st == EWALD_OK) {
-    CtxView cv{plan->w.smm, plan->w.site};
-    if (ctx) cv = ctx_view(plan->g, ctx);
+    CtxView cv{};
+    cv.smm = plan->w.smm;
+    cv.site = plan->w.site;
+    if (ctx) cv = ctx_view(plan->g, ctx, n_qm, n_mm);
     st = seq_forward_tail(q, Q, mu, theta, cv.smm, plan->g.KF, energy, phi, efield, efgrad, cv.site);
   }
   plan->t = saved;
@@ -456,8 +581,20 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   q.fa.frames = nullptr;
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
   q.fa.n_frames = 1;
-  CtxView cv = ctx_view(plan->g, (void*)ctx);
+  CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
   Work& w = plan->w;
+  if (!g_phi && !g_efield && !g_efgrad && !(plan->p.flags & EWALD_PLAIN)) {
+    // the forward call stored the gradients of E; L = gE E scales them
+    hipError_t e;
+    {
+      ProfScope ps(plan, "launch_scale_grads", s);
+      e = launch_scale_grads(gE, n_qm, n_mm, cv.gq, cv.gQ, cv.gmu, cv.gth, cv.gm, cv.gmq, g_qm_xyz, g_Q, g_mu,
+                             g_theta, g_mm_xyz, g_mm_q, s);
+    }
+    plan->t = saved;
+    if (e != hipSuccess) return fail(EWALD_ERR_HIP, "scale launch: %s", hipGetErrorString(e));
+    return EWALD_OK;
+  }
   const Grid& g = plan->g;
 #define STEP(expr)                                                                                     \
   do {                                                                                                 \
@@ -471,7 +608,8 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
       return fail(EWALD_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_));                      \
     }                                                                                                  \
   } while (0)
-  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
+  // the matrix-core backward kernel reads the MM phase tables in its epilogue
+  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, plan->t.bwd_ilp >= 3 ? 1 : 0);
   if (st != EWALD_OK) {
     plan->t = saved;
     return st;
@@ -483,7 +621,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   STEP(launch_reduce_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
   STEP(launch_project_qm(g, q.fa, n_qm, n_qm, cv.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
   STEP(launch_real_qm(g, q.fa, n_qm, n_mm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
-  if (q.qmqm && n_qm > 0) STEP(launch_qmqm(g, q.fa, plan->cap_qm, Q, mu, theta, w, s));
+  if (q.qmqm && n_qm > 0) STEP(launch_qmqm(g, q.fa, n_qm, plan->cap_qm, Q, mu, theta, w, s));
   STEP(launch_finalize_bwd(q.fa, n_qm, cv.site, gE, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, s));
 #undef STEP
   plan->t = saved;
@@ -515,23 +653,15 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   memset(&q.fa.f0, 0, sizeof(q.fa.f0));
   Work& w = plan->w;
   const Grid& g = plan->g;
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q);
-  if (st != EWALD_OK) return st;
-  const int bwd = mode == EWALD_FWD_BWD;
-  if (bwd) LCHK(launch_eff_moments(q.fa, max_nq, Q, mu, theta, nullptr, nullptr, nullptr, nullptr, w, s));
-  LCHK(launch_sfac_qm(g, q.fa, max_nq, Q, mu, theta, w.qeff, nullptr, bwd, w, s));
-  LCHK(launch_sfac_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
-  if (bwd) LCHK(launch_force_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
-  st = seq_forward_tail(q, Q, mu, theta, w.smm, g.KF, energy, phi, efield, efgrad, w.site);
-  if (st != EWALD_OK) return st;
-  if (bwd) {
-    LCHK(launch_real_mm(g, q.fa, max_nm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
-    LCHK(launch_reduce_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
-    LCHK(launch_project_qm(g, q.fa, max_nq, total_nq, w.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
-    LCHK(launch_real_qm(g, q.fa, max_nq, max_nm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
-    LCHK(launch_finalize_bwd(q.fa, max_nq, w.site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, s));
+  if (mode == EWALD_FWD_BWD) {
+    return seq_fwd_bwd(q, plan->gaux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
+                       w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
   }
-  return EWALD_OK;
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, 1);
+  if (st != EWALD_OK) return st;
+  LCHK(launch_sfac_qm(g, q.fa, max_nq, Q, mu, theta, w.qeff, nullptr, 0, w, s));
+  LCHK(launch_sfac_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
+  return seq_forward_tail(q, Q, mu, theta, w.smm, g.KF, energy, phi, efield, efgrad, w.site);
 }
 
 template <typename T>
@@ -602,6 +732,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   hipStream_t s = (hipStream_t)stream;
   if (!plan->gstream) {
     HIPCHK(hipStreamCreateWithFlags(&plan->gstream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&plan->gaux, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&plan->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&plan->ev_out, hipEventDisableTiming));
   }

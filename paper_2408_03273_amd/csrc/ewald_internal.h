@@ -39,6 +39,8 @@ struct Grid {
   int Zc;           // nz chunk of the forward kernel
   int NZP;          // nz padded to a multiple of Zc
   int R;            // complex entries per atom in the phase tables: NX + NY + NZP
+  int NG;           // 16-column groups of the matrix-core backward kernel
+  int NKS;          // nz steps of 4 of the matrix-core backward kernel
   double alpha, rcut;
 };
 
@@ -84,6 +86,8 @@ struct Work {
   double2* sabc;      // [cap_frames][KF][3]  A, B, C of the QM multipoles
   double2* wk;        // [cap_frames][KF]     backward weights (8 pi/V) g(k) S'_QM(k)
   double2* smm;       // [cap_frames][KF]     S_MM for batched calls
+  double* kw;         // [cap_frames][KF]     (8 pi/V) e^{-k^2/4a^2}/k^2 on the half space, else 0
+  double2* wfrag;     // [cap_frames][NG][NKS][64][2] W and nz*W in matrix-core fragment order (zero padded)
   double2* spart;     // [cap_slots][NZP][NCOL] partial S_MM sums
   double* fpart;      // [cap_kc][cap_mm][4]  partial MM gradient data (phi, dx, dy, dz)
   double* rpart;      // [cap_mm][4]          real-space MM gradient data
@@ -100,7 +104,9 @@ struct Tuning {
   int zc;         // forward nz chunk (template instance)
   int a_chunk;    // forward atoms per block
   int kc;         // backward column chunks
-  int bwd_ilp;    // backward atoms per lane (1 or 2)
+  int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3 matrix cores
+  int fwd_pf;     // forward kernel prefetches the next atom's factors
+  int fwd_target; // forward blocks the atom chunking aims for
 };
 
 // ---------------------------------------------------------------- launchers
@@ -108,7 +114,7 @@ struct Tuning {
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
-                       int cap_mm);
+                       int cap_mm, int mm_tables);
 hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const double* Q, const double* mu,
                           const double* theta, const double* qeff, const double* gE, int with_w, Work& w,
                           hipStream_t s);
@@ -126,7 +132,7 @@ hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max
                           int backward, int fp32, Work& w, hipStream_t s);
 hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
                           hipStream_t s);
-hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int cap_qm, const double* Q, const double* mu,
+hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, const double* Q, const double* mu,
                        const double* theta, Work& w, hipStream_t s);
 hipError_t launch_finalize_fwd(const Grid& g, const FrameArg& fa, const double* Q, const double* mu,
                                const double* theta, int qmqm, double* energy, double* phi, double* efield,
@@ -139,6 +145,10 @@ hipError_t launch_reduce_mm(const Grid& g, const Tuning& t, const FrameArg& fa, 
 hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
                                double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s);
 
+hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq, const double* gQ, const double* gmu,
+                              const double* gth, const double* gm, const double* gmq, double* o_q, double* o_Q,
+                              double* o_mu, double* o_th, double* o_m, double* o_mq, hipStream_t s);
+bool force_mm_mfma_has_nks(int nks);
 // forward kernel instances available for the nz chunk
 bool sfac_mm_has_zc(int zc);
 int pick_zc(int NZ);

@@ -162,9 +162,6 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
   tab[(size_t)row * g.R + t] = make_double2(c, s);
 }
 
-hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
-                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s,
-                       int cap_qm, int cap_mm);
 
 // ------------------------------------------------------------------ QM structure factors
 // A(k) = sum_j Q_j e_j, B(k) = sum_j i (k.mu_j) e_j, C(k) = sum_j -1/2 (k.theta_j.k) e_j,
@@ -173,18 +170,21 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
 __global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const double* __restrict__ Q,
                                                  const double* __restrict__ mu, const double* __restrict__ theta,
                                                  const double* __restrict__ qeff, const double2* __restrict__ qtab,
-                                                 int with_w, double2* __restrict__ sabc, double2* __restrict__ wk) {
+                                                 int with_w, double2* __restrict__ sabc, double2* __restrict__ wk,
+                                                 double* __restrict__ kw, double2* __restrict__ wfrag) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= g.KF) return;
-  const int col = k / g.NZ, iz = k - col * g.NZ;
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int k = blockIdx.x * 64 + lane;
+  const int kc = min(k, g.KF - 1);
+  const int col = kc / g.NZ, iz = kc - col * g.NZ;
   const int nx = col / g.NY, iy = col - nx * g.NY;
   const int ny = iy - g.my, nz = iz - g.mz;
   const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
                kz = 2.0 * kPi * nz * fr.inv_box[2];
-  double2 A = make_double2(0, 0), B = make_double2(0, 0), C = make_double2(0, 0), S2 = make_double2(0, 0);
-  for (int j = 0; j < fr.nq; j++) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // A, B, C, S' (re, im)
+  for (int j = wave; j < fr.nq; j += 4) {
     const int r = fr.qoff + j;
     const double2* row = qtab + (size_t)r * g.R;
     const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
@@ -194,34 +194,51 @@ __global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const doub
     const double kthk = kx * kx * t[0] + ky * ky * t[3] + kz * kz * t[5] +
                         2.0 * (kx * ky * t[1] + kx * kz * t[2] + ky * kz * t[4]);
     const double Qj = Q[r];
-    A.x += Qj * e.x;
-    A.y += Qj * e.y;
-    B.x -= kmu * e.y;
-    B.y += kmu * e.x;
-    C.x -= 0.5 * kthk * e.x;
-    C.y -= 0.5 * kthk * e.y;
+    v[0] += Qj * e.x;
+    v[1] += Qj * e.y;
+    v[2] -= kmu * e.y;
+    v[3] += kmu * e.x;
+    v[4] -= 0.5 * kthk * e.x;
+    v[5] -= 0.5 * kthk * e.y;
     if (with_w) {
       const double* qe = qeff + 10 * (size_t)r;
       const double kmu2 = kx * qe[1] + ky * qe[2] + kz * qe[3];
       const double kthk2 = kx * kx * qe[4] + ky * ky * qe[7] + kz * kz * qe[9] +
                            2.0 * (kx * ky * qe[5] + kx * kz * qe[6] + ky * kz * qe[8]);
       const double wr = qe[0] - 0.5 * kthk2, wi = kmu2;
-      S2.x += wr * e.x - wi * e.y;
-      S2.y += wr * e.y + wi * e.x;
+      v[6] += wr * e.x - wi * e.y;
+      v[7] += wr * e.y + wi * e.x;
     }
   }
-  double2* o = sabc + ((size_t)f * g.KF + k) * 3;
-  o[0] = A;
-  o[1] = B;
-  o[2] = C;
-  if (with_w) {
+  __shared__ double red[3][8][64];
+  if (wave > 0)
+    for (int t = 0; t < 8; t++) red[wave - 1][t][lane] = v[t];
+  __syncthreads();
+  if (wave == 0 && k < g.KF) {
+    for (int t = 0; t < 8; t++) v[t] += red[0][t][lane] + red[1][t][lane] + red[2][t][lane];
+    double2* o = sabc + ((size_t)f * g.KF + k) * 3;
+    o[0] = make_double2(v[0], v[1]);
+    o[1] = make_double2(v[2], v[3]);
+    o[2] = make_double2(v[4], v[5]);
     double wgt = 0.0;
     if (in_half_space(nx, ny, nz)) {
       const double k2 = kx * kx + ky * ky + kz * kz;
       const double V = fr.box[0] * fr.box[1] * fr.box[2];
       wgt = 8.0 * kPi / V * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
     }
-    wk[(size_t)f * g.KF + k] = make_double2(wgt * S2.x, wgt * S2.y);
+    kw[(size_t)f * g.KF + k] = wgt;
+    if (with_w) {
+      const double2 W = make_double2(wgt * v[6], wgt * v[7]);
+      wk[(size_t)f * g.KF + k] = W;
+      if (wfrag) {
+        // fragment-major copy: [group][step][lane], lane = column%16 + 16 (nz%4)
+        const int grp = col >> 4, s4 = iz >> 2;
+        const size_t fi = (((size_t)f * g.NG + grp) * g.NKS + s4) * 64 + (col & 15) + 16 * (iz & 3);
+        const double fz = (double)nz;
+        wfrag[2 * fi] = W;
+        wfrag[2 * fi + 1] = make_double2(fz * W.x, fz * W.y);
+      }
+    }
   }
 }
 
@@ -230,8 +247,9 @@ hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const d
                           hipStream_t s) {
   (void)max_nq;
   (void)gE;
-  dim3 grid((g.KF + 255) / 256, fa.n_frames);
-  hipLaunchKernelGGL(k_sfac_qm, grid, dim3(256), 0, s, g, fa, Q, mu, theta, qeff, w.qm_tab, with_w, w.sabc, w.wk);
+  dim3 grid((g.KF + 63) / 64, fa.n_frames);
+  hipLaunchKernelGGL(k_sfac_qm, grid, dim3(256), 0, s, g, fa, Q, mu, theta, qeff, w.qm_tab, with_w, w.sabc, w.wk,
+                     w.kw, w.wfrag);
   return hipGetLastError();
 }
 
@@ -243,15 +261,17 @@ hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const d
 // block split the block's atom range and are summed through LDS; the block
 // writes one partial sum per k, and partial sums over atom chunks are added
 // by k_reduce_smm.
-template <int Z>
-__global__ __launch_bounds__(256) void k_sfac_mm(Grid g, FrameArg fa, int a_chunk, const double* __restrict__ mm4,
-                                                 int cap_mm, const double2* __restrict__ tab,
-                                                 double2* __restrict__ spart) {
+template <int Z, bool PF>
+__global__ __launch_bounds__(256) void k_sfac_mm(Grid g, FrameArg fa, int a_chunk, int nkb, int nac,
+                                                 const double* __restrict__ mm4, int cap_mm,
+                                                 const double2* __restrict__ tab, double2* __restrict__ spart) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
+  const int kb = blockIdx.x % nkb, ac = blockIdx.x / nkb;
+  if (ac >= nac) return;
   const int nzc = g.NZP / Z;
-  const int tile = blockIdx.x / nzc, zc = blockIdx.x - tile * nzc;
-  const int a0 = blockIdx.y * a_chunk;
+  const int tile = kb / nzc, zc = kb - tile * nzc;
+  const int a0 = ac * a_chunk;
   if (a0 >= fr.nm || tile * 64 >= g.NCOL) return;
   const int a1 = min(fr.nm, a0 + a_chunk);
   const int lane = threadIdx.x & 63;
@@ -269,13 +289,40 @@ __global__ __launch_bounds__(256) void k_sfac_mm(Grid g, FrameArg fa, int a_chun
   const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
   const double2* __restrict__ base = tab + (size_t)fr.moff * g.R;
   const int zoff = g.NX + g.NY + zc * Z;
-  for (int a = a0 + wave; a < a1; a += 4) {
+  int a = a0 + wave;
+  // optional software pipeline: the lane-specific factors of the next atom are
+  // in flight while the current atom is accumulated
+  double qn = 0.0;
+  double2 exn = make_double2(0, 0), eyn = make_double2(0, 0);
+  if (PF && a < a1) {
     const double2* __restrict__ row = base + (size_t)a * g.R;
-    const double q = qv[a];
-    const double2 ex = row[nx], ey = row[g.NX + iy];
+    qn = qv[a];
+    exn = row[nx];
+    eyn = row[g.NX + iy];
+  }
+  for (; a < a1; a += 4) {
+    double q;
+    double2 ex, ey;
+    if (PF) {
+      q = qn;
+      ex = exn;
+      ey = eyn;
+      const int an = a + 4;
+      if (an < a1) {
+        const double2* __restrict__ rown = base + (size_t)an * g.R;
+        qn = qv[an];
+        exn = rown[nx];
+        eyn = rown[g.NX + iy];
+      }
+    } else {
+      const double2* __restrict__ rowc = base + (size_t)a * g.R;
+      q = qv[a];
+      ex = rowc[nx];
+      ey = rowc[g.NX + iy];
+    }
     const double cr = q * (ex.x * ey.x - ex.y * ey.y);
     const double ci = q * (ex.x * ey.y + ex.y * ey.x);
-    const double2* __restrict__ ez = row + zoff;
+    const double2* __restrict__ ez = base + (size_t)a * g.R + zoff;
 #pragma unroll
     for (int z = 0; z < Z; z++) {
       const double2 e = ez[z];
@@ -307,7 +354,7 @@ __global__ __launch_bounds__(256) void k_sfac_mm(Grid g, FrameArg fa, int a_chun
   }
   __syncthreads();
   if (wave == 0 && col < g.NCOL) {
-    double2* __restrict__ out = spart + (size_t)(fr.slot_base + blockIdx.y) * g.NZP * g.NCOL;
+    double2* __restrict__ out = spart + (size_t)(fr.slot_base + ac) * g.NZP * g.NCOL;
 #pragma unroll
     for (int z = 0; z < Z; z++) {
       const double2 o = red[0][z][lane];
@@ -347,11 +394,16 @@ template <int Z>
 static hipError_t launch_sfac_mm_z(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
                                    Work& w, hipStream_t s) {
   const int tiles = (g.NCOL + 63) / 64;
-  const int nzc = g.NZP / Z;
-  const int achunks = (max_nm + t.a_chunk - 1) / t.a_chunk;
-  if (achunks == 0) return hipSuccess;
-  dim3 grid(tiles * nzc, achunks, fa.n_frames);
-  hipLaunchKernelGGL(k_sfac_mm<Z>, grid, dim3(256), 0, s, g, fa, t.a_chunk, w.mm4, cap_mm, w.mm_tab, w.spart);
+  const int nkb = tiles * (g.NZP / Z);
+  const int nac = (max_nm + t.a_chunk - 1) / t.a_chunk;
+  if (nac == 0) return hipSuccess;
+  dim3 grid(nkb * nac, 1, fa.n_frames);
+  if (t.fwd_pf)
+    hipLaunchKernelGGL((k_sfac_mm<Z, true>), grid, dim3(256), 0, s, g, fa, t.a_chunk, nkb, nac, w.mm4, cap_mm, w.mm_tab,
+                       w.spart);
+  else
+    hipLaunchKernelGGL((k_sfac_mm<Z, false>), grid, dim3(256), 0, s, g, fa, t.a_chunk, nkb, nac, w.mm4, cap_mm,
+                       w.mm_tab, w.spart);
   return hipGetLastError();
 }
 
@@ -408,7 +460,8 @@ hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, W
 // truncated QM-QM term (4 pi/V) g (|A|^2 + 2Re A*B + 2Re A*C + |B|^2).
 __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain,
                                                     const double2* __restrict__ spart,
-                                                    const double2* __restrict__ sabc, double2* __restrict__ smm,
+                                                    const double2* __restrict__ sabc,
+                                                    const double* __restrict__ kw, double2* __restrict__ smm,
                                                     size_t smm_stride, double* __restrict__ facc) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
@@ -426,13 +479,8 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
     if (plain && fr.nm == 0) sr = si = 0.0;
     const int k = col * g.NZ + iz;
     smm[(size_t)f * smm_stride + k] = make_double2(sr, si);
-    const int nx = col / g.NY, ny = col - nx * g.NY - g.my, nz = iz - g.mz;
-    if (in_half_space(nx, ny, nz)) {
-      const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
-                   kz = 2.0 * kPi * nz * fr.inv_box[2];
-      const double k2 = kx * kx + ky * ky + kz * kz;
-      const double V = fr.box[0] * fr.box[1] * fr.box[2];
-      const double wgt = 8.0 * kPi / V * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
+    const double wgt = kw[(size_t)f * g.KF + k];
+    if (wgt != 0.0) {
       const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
       const double2 A = abc[0], B = abc[1], C = abc[2];
       const double sqr = A.x + B.x + C.x, sqi = A.y + B.y + C.y;
@@ -453,7 +501,7 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
 hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
                              size_t smm_frame_stride, Work& w, hipStream_t s) {
   dim3 grid((g.NZ * g.NCOL + 255) / 256, fa.n_frames);
-  hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, w.spart, w.sabc, smm_out,
+  hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, w.spart, w.sabc, w.kw, smm_out,
                      smm_frame_stride, w.facc);
   return hipGetLastError();
 }
@@ -469,7 +517,8 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
                                                     const double* __restrict__ mu, const double* __restrict__ theta,
                                                     const double* __restrict__ qeff,
                                                     const double2* __restrict__ qtab,
-                                                    const double2* __restrict__ sabc, int qmqm,
+                                                    const double2* __restrict__ sabc,
+                                                    const double* __restrict__ kw, int qmqm,
                                                     double* __restrict__ qacc) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
@@ -481,8 +530,6 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
 #pragma unroll
   for (int t = 0; t < NV; t++) acc[t] = 0.0;
   const double2* row = qtab + (size_t)r * g.R;
-  const double V = fr.box[0] * fr.box[1] * fr.box[2];
-  const double pref = 8.0 * kPi / V;
   double Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
   double Qo = 0, o0 = 0, o1 = 0, o2 = 0, u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0, u5 = 0;
   if (BWD) {
@@ -497,11 +544,10 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
     const int col = k / g.NZ, iz = k - col * g.NZ;
     const int nx = col / g.NY, iy = col - nx * g.NY;
     const int ny = iy - g.my, nz = iz - g.mz;
-    if (!in_half_space(nx, ny, nz)) continue;
+    const double w = kw[(size_t)f * g.KF + k];
+    if (w == 0.0) continue;
     const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
                  kz = 2.0 * kPi * nz * fr.inv_box[2];
-    const double k2 = kx * kx + ky * ky + kz * kz;
-    const double w = pref * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
     const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
     const double2 S = smm[(size_t)f * smm_stride + k];
     // Y = e conj(S)
@@ -586,110 +632,327 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
   dim3 grid(max_nq, n_pc, fa.n_frames);
   if (backward)
     hipLaunchKernelGGL(k_project_qm<1>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
-                       w.qeff, w.qm_tab, w.sabc, qmqm, w.qacc);
+                       w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc);
   else
     hipLaunchKernelGGL(k_project_qm<0>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
-                       w.qeff, w.qm_tab, w.sabc, qmqm, w.qacc);
+                       w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ MM gradients (backward hot loop)
 // For MM atom i: V(R) = sum_k W(k) e^{-i k.R}, W = (8 pi/V) g S'_QM, gives
-// dL/dq_i = Re V(R_i) and dL/dR_i = q_i grad Re V(R_i).  Lanes own atoms;
-// for each column (nx,ny) the nz sum is evaluated by Horner's rule in
-// u = e^{-i kz0 z} (nz >= 0) and conj(u) (nz < 0), together with the
-// nz-weighted sum for the z derivative: eight FMAs per k with the weights
-// W read as wave-uniform scalars.
+// dL/dq_i = Re V(R_i) and dL/dR_i = q_i grad Re V(R_i).  Lanes own atoms
+// (A per lane for instruction-level parallelism).  For each column (nx,ny)
+// the nz sum is one Horner chain in u = e^{-i kz0 z} over n' = nz + mz =
+// 0..2mz, together with its derivative for the nz-weighted sum of the z
+// gradient: eight FMAs per k, the weights W being wave-uniform scalar loads.
+// The column factor c = e^{-i(kx x + ky y)} e^{i mz kz0 z} follows the
+// columns by complex recurrences in ny and nx, so no per-atom table is read.
+template <int MZ>
+DEV void horner_column(const double2* __restrict__ wc, int mz, double2 u, double& pr, double& pi, double& dr,
+                       double& di) {
+  const int top = MZ > 0 ? 2 * MZ : 2 * mz;
+  pr = wc[top].x;
+  pi = wc[top].y;
+  dr = 0.0;
+  di = 0.0;
+  if (MZ > 0) {
+#pragma unroll
+    for (int n = 2 * MZ - 1; n >= 0; n--) {
+      const double2 w = wc[n];
+      const double tr = fma(dr, u.x, fma(-di, u.y, pr));
+      di = fma(dr, u.y, fma(di, u.x, pi));
+      dr = tr;
+      const double t2 = fma(pr, u.x, fma(-pi, u.y, w.x));
+      pi = fma(pr, u.y, fma(pi, u.x, w.y));
+      pr = t2;
+    }
+  } else {
+#pragma unroll 4
+    for (int n = top - 1; n >= 0; n--) {
+      const double2 w = wc[n];
+      const double tr = fma(dr, u.x, fma(-di, u.y, pr));
+      di = fma(dr, u.y, fma(di, u.x, pi));
+      dr = tr;
+      const double t2 = fma(pr, u.x, fma(-pi, u.y, w.x));
+      pi = fma(pr, u.y, fma(pi, u.x, w.y));
+      pr = t2;
+    }
+  }
+}
+
+template <int MZ, int A>
 __global__ __launch_bounds__(256) void k_force_mm(Grid g, FrameArg fa, int kc_n, const double* __restrict__ mm4,
-                                                  int cap_mm, const double2* __restrict__ tab,
-                                                  const double2* __restrict__ wk, double* __restrict__ fpart) {
+                                                  int cap_mm, const double2* __restrict__ wk,
+                                                  double* __restrict__ fpart) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
-  const int i0 = blockIdx.x * 256;
+  const int i0 = blockIdx.x * 256 * A;
   if (i0 >= fr.nm) return;
-  const int i = i0 + threadIdx.x;
-  const int ic = min(i, fr.nm - 1);
-  const int row = fr.moff + ic;
-  const double z = mm4[(size_t)2 * cap_mm + row];
-  const double y = mm4[(size_t)cap_mm + row];
   const int kc = blockIdx.y;
   const int per = (g.NCOL + kc_n - 1) / kc_n;
   const int c0 = kc * per, c1 = min(g.NCOL, c0 + per);
-  const int mz = g.mz;
-  double sz, cz, sy, cy;
-  sincospi(2.0 * z / fr.box[2], &sz, &cz);
-  sincospi(2.0 * y / fr.box[1], &sy, &cy);
-  const double2 u = make_double2(cz, -sz);   // e^{-i kz0 z}
-  const double2 v = make_double2(cz, sz);    // conj(u)
-  const double2 wy = make_double2(cy, -sy);  // e^{-i ky0 y}
-  const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
-  const double2* trow = tab + (size_t)row * g.R;
-  double aphi = 0.0, agx = 0.0, agy = 0.0, agz = 0.0;
+  const int mz = MZ > 0 ? MZ : g.mz;
+  double2 u[A], c[A], crow[A], wy[A], wx[A];
+  double aphi[A], agx[A], agy[A], agz[A];
+  const int nx0 = c0 / g.NY, iy0 = c0 - nx0 * g.NY;
+#pragma unroll
+  for (int a = 0; a < A; a++) {
+    const int i = min(i0 + threadIdx.x + 256 * a, fr.nm - 1);
+    const int row = fr.moff + i;
+    const double x = mm4[row] * fr.inv_box[0];
+    const double y = mm4[(size_t)cap_mm + row] * fr.inv_box[1];
+    const double z = mm4[(size_t)2 * cap_mm + row] * fr.inv_box[2];
+    double s, co;
+    sincospi(2.0 * z, &s, &co);
+    u[a] = make_double2(co, -s);
+    sincospi(2.0 * y, &s, &co);
+    wy[a] = make_double2(co, -s);
+    sincospi(2.0 * x, &s, &co);
+    wx[a] = make_double2(co, -s);
+    // row start (nx0, ny=-my) and column start (nx0, ny0), both times e^{+i mz kz0 z}
+    sincospi(2.0 * ((double)mz * z - (double)nx0 * x + (double)g.my * y), &s, &co);
+    crow[a] = make_double2(co, s);
+    sincospi(2.0 * ((double)mz * z - (double)nx0 * x - (double)(iy0 - g.my) * y), &s, &co);
+    c[a] = make_double2(co, s);
+    aphi[a] = agx[a] = agy[a] = agz[a] = 0.0;
+  }
   const double2* __restrict__ wf = wk + (size_t)f * g.KF;
-  double2 c = make_double2(1.0, 0.0);
+  int nx = nx0, iy = iy0;
   for (int col = c0; col < c1; col++) {
-    const int nx = col / g.NY, iy = col - nx * g.NY;
-    if (col == c0 || iy == 0)
-      c = cconj(cmul(trow[nx], trow[g.NX + iy]));
-    else
-      c = cmul(c, wy);
+    if (col != c0) {
+      if (iy == g.NY) {  // next row
+        iy = 0;
+        nx++;
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+          crow[a] = cmul(crow[a], wx[a]);
+          c[a] = crow[a];
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < A; a++) c[a] = cmul(c[a], wy[a]);
+      }
+    }
     const double2* __restrict__ wc = wf + (size_t)col * g.NZ;
-    // nz >= 0 part: P(u) = sum_{n=0}^{mz} W_n u^n, d = P'(u)
-    double pr = wc[2 * mz].x, pi = wc[2 * mz].y, dr = 0.0, di = 0.0;
-    // nz < 0 part: Qp(v) = sum_{n'=0}^{mz-1} W_{-(n'+1)} v^{n'}, e = Qp'(v)
-    double qr = wc[0].x, qi = wc[0].y, er = 0.0, ei = 0.0;
-    for (int t = 0; t < mz - 1; t++) {
-      const double2 wp = wc[2 * mz - 1 - t];
-      const double2 wn = wc[1 + t];
-      double tr = fma(dr, u.x, fma(-di, u.y, pr));
-      di = fma(dr, u.y, fma(di, u.x, pi));
-      dr = tr;
-      tr = fma(pr, u.x, fma(-pi, u.y, wp.x));
-      pi = fma(pr, u.y, fma(pi, u.x, wp.y));
-      pr = tr;
-      tr = fma(er, v.x, fma(-ei, v.y, qr));
-      ei = fma(er, v.y, fma(ei, v.x, qi));
-      er = tr;
-      tr = fma(qr, v.x, fma(-qi, v.y, wn.x));
-      qi = fma(qr, v.y, fma(qi, v.x, wn.y));
-      qr = tr;
+    double pr[A], pi[A], dr[A], di[A];
+    if (A == 1) {
+      horner_column<MZ>(wc, mz, u[0], pr[0], pi[0], dr[0], di[0]);
+    } else {
+      // two atoms share every scalar load of W
+      const int top = 2 * mz;
+#pragma unroll
+      for (int a = 0; a < A; a++) {
+        pr[a] = wc[top].x;
+        pi[a] = wc[top].y;
+        dr[a] = di[a] = 0.0;
+      }
+#pragma unroll 8
+      for (int n = top - 1; n >= 0; n--) {
+        const double2 w = wc[n];
+#pragma unroll
+        for (int a = 0; a < A; a++) {
+          const double tr = fma(dr[a], u[a].x, fma(-di[a], u[a].y, pr[a]));
+          di[a] = fma(dr[a], u[a].y, fma(di[a], u[a].x, pi[a]));
+          dr[a] = tr;
+          const double t2 = fma(pr[a], u[a].x, fma(-pi[a], u[a].y, w.x));
+          pi[a] = fma(pr[a], u[a].y, fma(pi[a], u[a].x, w.y));
+          pr[a] = t2;
+        }
+      }
     }
-    {
-      const double2 wp = wc[mz];  // last step of the nz >= 0 part (n = 0)
-      double tr = fma(dr, u.x, fma(-di, u.y, pr));
-      di = fma(dr, u.y, fma(di, u.x, pi));
-      dr = tr;
-      tr = fma(pr, u.x, fma(-pi, u.y, wp.x));
-      pi = fma(pr, u.y, fma(pi, u.x, wp.y));
-      pr = tr;
+    const double fny = (double)(iy - g.my), fnx = (double)nx;
+#pragma unroll
+    for (int a = 0; a < A; a++) {
+      // V_col = c P~,  sum_n n W_n u^n (times the folded phase) = u D~ - mz P~
+      const double2 cP = cmul(c[a], make_double2(pr[a], pi[a]));
+      const double2 uD = cmul(u[a], make_double2(dr[a], di[a]));
+      const double zr = uD.x - mz * pr[a], zi = uD.y - mz * pi[a];
+      const double imz = c[a].x * zi + c[a].y * zr;
+      aphi[a] += cP.x;
+      agx[a] += fnx * cP.y;
+      agy[a] += fny * cP.y;
+      agz[a] += imz;
     }
-    // P- = v Qp, sum n W_{-n} v^n = v (Qp + v Qp')
-    const double2 Qp = make_double2(qr, qi), dQ = make_double2(er, ei);
-    const double2 Pm = cmul(v, Qp);
-    const double2 Zm = cmul(v, make_double2(Qp.x + (v.x * dQ.x - v.y * dQ.y), Qp.y + (v.x * dQ.y + v.y * dQ.x)));
-    const double2 Zp = cmul(u, make_double2(dr, di));
-    const double2 P = make_double2(pr + Pm.x, pi + Pm.y);
-    const double2 Pz = make_double2(Zp.x - Zm.x, Zp.y - Zm.y);
-    const double2 cP = cmul(c, P), cPz = cmul(c, Pz);
-    aphi += cP.x;
-    agx += (double)nx * cP.y;
-    agy += (double)(iy - g.my) * cP.y;
-    agz += cPz.y;
+    iy++;
   }
-  if (i < fr.nm) {
-    double* o = fpart + ((size_t)kc * cap_mm + fr.moff + i) * 4;
-    o[0] = aphi;
-    o[1] = kx0 * agx;
-    o[2] = ky0 * agy;
-    o[3] = kz0 * agz;
+  const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
+#pragma unroll
+  for (int a = 0; a < A; a++) {
+    const int i = i0 + threadIdx.x + 256 * a;
+    if (i < fr.nm) {
+      double* o = fpart + ((size_t)kc * cap_mm + fr.moff + i) * 4;
+      o[0] = aphi[a];
+      o[1] = kx0 * agx[a];
+      o[2] = ky0 * agy[a];
+      o[3] = kz0 * agz[a];
+    }
   }
+}
+
+// Matrix-core form of the same sums.  For a tile of 16 atoms and 16 columns
+//   P[a][c]  = sum_nz E[a][nz] W[nz][c],   Pz[a][c] = sum_nz E[a][nz] nz W[nz][c],
+//   E[a][nz] = e^{-i nz kz0 z_a},
+// are complex products with the contraction over nz, four nz per
+// v_mfma_f64_16x16x4f64 (A = E: lane l holds atom l%16, nz 4s + l/16;
+// B = W: lane l holds column l%16, nz 4s + l/16; D: lane l, element r holds
+// atom l/16 + 4r, column l%16).  E advances by e^{-4 i kz0 z} per step in
+// registers.  The epilogue multiplies by e^{-i(kx x + ky y)} from the phase
+// tables and accumulates the four outputs per atom across the wave's columns.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+DEV v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+template <int NKS>
+__global__ __launch_bounds__(256) void k_force_mm_mfma(Grid g, FrameArg fa, int kc_n, const double* __restrict__ mm4,
+                                                       int cap_mm, const double2* __restrict__ tab,
+                                                       const double2* __restrict__ wfrag, double* __restrict__ fpart) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int a0 = (blockIdx.x * 4 + wave) * 16;
+  if (a0 >= fr.nm) return;
+  const int kc = blockIdx.y;
+  const int per = (g.NG + kc_n - 1) / kc_n;
+  const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
+  const int li = lane & 15, lk = lane >> 4;
+  const int mz = g.mz;
+  // A operands for every step, once per wave: E[s] = e^{-i (4s + lk - mz) kz0 z}, atom a0 + li
+  const int aA = min(a0 + li, fr.nm - 1);
+  const double zA = mm4[(size_t)2 * cap_mm + fr.moff + aA] * fr.inv_box[2];
+  double er[NKS], ei[NKS];
+  {
+    double s_, c_;
+    sincospi(-2.0 * (double)(lk - mz) * zA, &s_, &c_);
+    double2 E = make_double2(c_, s_);
+    sincospi(-8.0 * zA, &s_, &c_);
+    const double2 u4 = make_double2(c_, s_);
+#pragma unroll
+    for (int st = 0; st < NKS; st++) {
+      er[st] = E.x;
+      ei[st] = E.y;
+      E = cmul(E, u4);
+    }
+  }
+  double acc0[4], acc1[4], acc2[4], acc3[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
+  int arow[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) arow[r] = fr.moff + min(a0 + lk + 4 * r, fr.nm - 1);
+  for (int grp = gbeg; grp < gend; grp++) {
+    const int col = grp * 16 + li;
+    const bool cok = col < g.NCOL;
+    const int colc = cok ? col : g.NCOL - 1;
+    const int nx = colc / g.NY, iy = colc - nx * g.NY;
+    // column phases of the epilogue, loaded ahead of the contraction
+    double2 ex[4], ey[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const double2* __restrict__ row = tab + (size_t)arow[r] * g.R;
+      ex[r] = row[nx];
+      ey[r] = row[g.NX + iy];
+    }
+    const double2* __restrict__ wg = wfrag + (((size_t)f * g.NG + grp) * NKS * 64 + lane) * 2;
+    v4d Pr = {0, 0, 0, 0}, Pi = {0, 0, 0, 0}, Zr = {0, 0, 0, 0}, Zi = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < NKS; st++) {
+      const double2 w = wg[st * 128];
+      const double2 wz = wg[st * 128 + 1];
+      Pr = mfma4(er[st], w.x, Pr);
+      Pi = mfma4(er[st], w.y, Pi);
+      Zr = mfma4(er[st], wz.x, Zr);
+      Zi = mfma4(er[st], wz.y, Zi);
+      Pr = mfma4(-ei[st], w.y, Pr);
+      Pi = mfma4(ei[st], w.x, Pi);
+      Zr = mfma4(-ei[st], wz.y, Zr);
+      Zi = mfma4(ei[st], wz.x, Zi);
+    }
+    const double fnx = (double)nx, fny = (double)(iy - g.my);
+    if (cok) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
+        const double2 c = cconj(cmul(ex[r], ey[r]));
+        const double cpr = c.x * Pr[r] - c.y * Pi[r];
+        const double cpi = c.x * Pi[r] + c.y * Pr[r];
+        const double czi = c.x * Zi[r] + c.y * Zr[r];
+        acc0[r] += cpr;
+        acc1[r] += fnx * cpi;
+        acc2[r] += fny * cpi;
+        acc3[r] += czi;
+      }
+    }
+  }
+  // sum over the 16 columns held by lanes with the same lk
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      acc0[r] += __shfl_xor(acc0[r], o, 64);
+      acc1[r] += __shfl_xor(acc1[r], o, 64);
+      acc2[r] += __shfl_xor(acc2[r], o, 64);
+      acc3[r] += __shfl_xor(acc3[r], o, 64);
+    }
+  }
+  if (li == 0) {
+    const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int a = a0 + lk + 4 * r;
+      if (a < fr.nm) {
+        double* o = fpart + ((size_t)kc * cap_mm + fr.moff + a) * 4;
+        o[0] = acc0[r];
+        o[1] = kx0 * acc1[r];
+        o[2] = ky0 * acc2[r];
+        o[3] = kz0 * acc3[r];
+      }
+    }
+  }
+}
+
+bool force_mm_mfma_has_nks(int nks) {
+  switch (nks) {
+    case 3: case 5: case 7: case 9: case 11: case 13: case 15: case 17: return true;
+    default: return false;
+  }
+}
+
+template <int MZ, int A>
+static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int kc, int cap_mm,
+                              Work& w) {
+  hipLaunchKernelGGL((k_force_mm<MZ, A>), grid, dim3(256), 0, s, g, fa, kc, w.mm4, cap_mm, w.wk, w.fpart);
 }
 
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
-  dim3 grid((max_nm + 255) / 256, t.kc, fa.n_frames);
-  hipLaunchKernelGGL(k_force_mm, grid, dim3(256), 0, s, g, fa, t.kc, w.mm4, cap_mm, w.mm_tab, w.wk, w.fpart);
+  if (t.bwd_ilp >= 3 && force_mm_mfma_has_nks(g.NKS)) {  // matrix-core path: 64 atoms per block
+    dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
+#define FM(N)                                                                                                   \
+  case N:                                                                                                       \
+    hipLaunchKernelGGL(k_force_mm_mfma<N>, grid, dim3(256), 0, s, g, fa, t.kc, w.mm4, cap_mm, w.mm_tab, w.wfrag, \
+                       w.fpart);                                                                                \
+    break;
+    switch (g.NKS) { FM(3) FM(5) FM(7) FM(9) FM(11) FM(13) FM(15) FM(17) default: break; }
+#undef FM
+    return hipGetLastError();
+  }
+  const int A = t.bwd_ilp == 1 ? 1 : 2;
+  dim3 grid((max_nm + 256 * A - 1) / (256 * A), t.kc, fa.n_frames);
+  if (A == 2) {
+    launch_force_mm_t<0, 2>(grid, s, g, fa, t.kc, cap_mm, w);
+  } else {
+    switch (g.mz) {
+      case 8: launch_force_mm_t<8, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+      case 16: launch_force_mm_t<16, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+      case 20: launch_force_mm_t<20, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+      case 24: launch_force_mm_t<24, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+      case 32: launch_force_mm_t<32, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+      default: launch_force_mm_t<0, 1>(grid, s, g, fa, t.kc, cap_mm, w); break;
+    }
+  }
   return hipGetLastError();
 }
 
@@ -881,108 +1144,98 @@ hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap
 
 // ------------------------------------------------------------------ QM-QM real space, self, background
 // P(a,b) = Qa Qb psi0 + (Qb mu_a - Qa mu_b).psi1 + (Qb th_a + Qa th_b):psi2 - 2 mu_a.psi2.mu_b,
-// E = 1/2 sum_{a != b} P + sum_a self_a - (pi/(2 a^2 V)) Qtot^2.  Thread a owns site a.
+// E = 1/2 sum_{a != b} P + sum_a self_a - (pi/(2 a^2 V)) Qtot^2.  One block per
+// site a; its threads take the partners b and the block sums the site's
+// energy share, position gradient and moment derivatives.
 __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
                                               const double* __restrict__ Q, const double* __restrict__ mu,
                                               const double* __restrict__ theta, double* __restrict__ qacc,
                                               double* __restrict__ facc) {
-  const int f = blockIdx.x;
+  const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
+  const int a = blockIdx.x;
+  if (a >= fr.nq) return;
   const double al = g.alpha, rc2 = g.rcut * g.rcut;
   const double sp = 1.7724538509055160273;  // sqrt(pi)
   const double V = fr.box[0] * fr.box[1] * fr.box[2];
   const double bgc = -kPi / (al * al * V);
   const double Qtot = facc[f * FA_COUNT + FA_QTOT_QM];
-  double esum = 0.0;
-  for (int a = threadIdx.x; a < fr.nq; a += 256) {
-    const int ra = fr.qoff + a;
-    const double Xa = qm4[ra], Ya = qm4[(size_t)cap_qm + ra], Za = qm4[(size_t)2 * cap_qm + ra];
-    const double Qa = Q[ra];
-    const double ma0 = mu[3 * (size_t)ra], ma1 = mu[3 * (size_t)ra + 1], ma2 = mu[3 * (size_t)ra + 2];
-    const double* tha = theta + 6 * (size_t)ra;
-    double e = 0.0, g0 = 0, g1 = 0, g2 = 0, dQ = 0, dm0 = 0, dm1 = 0, dm2 = 0;
-    double dt[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = 0; b < fr.nq; b++) {
-      if (b == a) continue;
-      const int rb = fr.qoff + b;
-      double x = Xa - qm4[rb], y = Ya - qm4[(size_t)cap_qm + rb], z = Za - qm4[(size_t)2 * cap_qm + rb];
-      min_image(x, y, z, fr);
-      const double r2 = x * x + y * y + z * z;
-      if (!(r2 < rc2) || r2 == 0.0) continue;
-      const Radial<double> R = radial<double>(r2, al);
-      const double Qb = Q[rb];
-      const double mb0 = mu[3 * (size_t)rb], mb1 = mu[3 * (size_t)rb + 1], mb2 = mu[3 * (size_t)rb + 2];
-      const double* thb = theta + 6 * (size_t)rb;
-      // combined moments seen by the pair
-      const double c0 = Qb * ma0 - Qa * mb0, c1 = Qb * ma1 - Qa * mb1, c2 = Qb * ma2 - Qa * mb2;
-      double s[6];
-      for (int t = 0; t < 6; t++) s[t] = Qb * tha[t] + Qa * thb[t];
-      const double cd = c0 * x + c1 * y + c2 * z;
-      const double sx = s[0] * x + s[1] * y + s[2] * z, sy = s[1] * x + s[3] * y + s[4] * z,
-                   sz = s[2] * x + s[4] * y + s[5] * z;
-      const double dsd = x * sx + y * sy + z * sz, trs = s[0] + s[3] + s[5];
-      const double mad = ma0 * x + ma1 * y + ma2 * z, mbd = mb0 * x + mb1 * y + mb2 * z;
-      const double mab = ma0 * mb0 + ma1 * mb1 + ma2 * mb2;
-      // P
-      const double P = Qa * Qb * R.f1 - cd * R.f3 + (1.5 * dsd * R.f5 - 0.5 * trs * R.f3) -
-                       (3.0 * mad * mbd * R.f5 - mab * R.f3);
-      e += 0.5 * P;
-      // dP/dr = QaQb psi1 + 2 c.psi2 + 3 s:psi3 - 6 mu_a.psi3.mu_b
-      const double s1 = -Qa * Qb * R.f3 + 3.0 * cd * R.f5 + 1.5 * trs * R.f5 - 7.5 * dsd * R.f7 -
-                        3.0 * (mab * R.f5 - 5.0 * mad * mbd * R.f7);
-      const double sc = -R.f3, ss = 3.0 * R.f5, sm = -3.0 * R.f5;
-      g0 += s1 * x + sc * c0 + ss * sx + sm * (ma0 * mbd + mb0 * mad);
-      g1 += s1 * y + sc * c1 + ss * sy + sm * (ma1 * mbd + mb1 * mad);
-      g2 += s1 * z + sc * c2 + ss * sz + sm * (ma2 * mbd + mb2 * mad);
-      // moment derivatives of P w.r.t. site a
-      const double thbx = thb[0] * x + thb[1] * y + thb[2] * z, thby = thb[1] * x + thb[3] * y + thb[4] * z,
-                   thbz = thb[2] * x + thb[4] * y + thb[5] * z;
-      const double dtbd = x * thbx + y * thby + z * thbz, trb = thb[0] + thb[3] + thb[5];
-      dQ += Qb * R.f1 + mbd * R.f3 + (1.5 * dtbd * R.f5 - 0.5 * trb * R.f3);
-      // Qb psi1 - 2 psi2.mu_b
-      dm0 += -Qb * x * R.f3 - (3.0 * x * mbd * R.f5 - mb0 * R.f3);
-      dm1 += -Qb * y * R.f3 - (3.0 * y * mbd * R.f5 - mb1 * R.f3);
-      dm2 += -Qb * z * R.f3 - (3.0 * z * mbd * R.f5 - mb2 * R.f3);
-      // Qb psi2 (distinct elements xx xy xz yy yz zz)
-      const double h5 = 1.5 * Qb * R.f5, h3 = 0.5 * Qb * R.f3;
-      dt[0] += h5 * x * x - h3;
-      dt[1] += h5 * x * y;
-      dt[2] += h5 * x * z;
-      dt[3] += h5 * y * y - h3;
-      dt[4] += h5 * y * z;
-      dt[5] += h5 * z * z - h3;
-    }
-    // self terms
+  const int ra = fr.qoff + a;
+  const double Xa = qm4[ra], Ya = qm4[(size_t)cap_qm + ra], Za = qm4[(size_t)2 * cap_qm + ra];
+  const double Qa = Q[ra];
+  const double ma0 = mu[3 * (size_t)ra], ma1 = mu[3 * (size_t)ra + 1], ma2 = mu[3 * (size_t)ra + 2];
+  const double* tha = theta + 6 * (size_t)ra;
+  // e, g0..2, dQ, dm0..2, dt0..5
+  double v[14];
+  for (int t = 0; t < 14; t++) v[t] = 0.0;
+  for (int b = threadIdx.x; b < fr.nq; b += 256) {
+    if (b == a) continue;
+    const int rb = fr.qoff + b;
+    double x = Xa - qm4[rb], y = Ya - qm4[(size_t)cap_qm + rb], z = Za - qm4[(size_t)2 * cap_qm + rb];
+    min_image(x, y, z, fr);
+    const double r2 = x * x + y * y + z * z;
+    if (!(r2 < rc2) || r2 == 0.0) continue;
+    const Radial<double> R = radial<double>(r2, al);
+    const double Qb = Q[rb];
+    const double mb0 = mu[3 * (size_t)rb], mb1 = mu[3 * (size_t)rb + 1], mb2 = mu[3 * (size_t)rb + 2];
+    const double* thb = theta + 6 * (size_t)rb;
+    const double c0 = Qb * ma0 - Qa * mb0, c1 = Qb * ma1 - Qa * mb1, c2 = Qb * ma2 - Qa * mb2;
+    double sm[6];
+    for (int t = 0; t < 6; t++) sm[t] = Qb * tha[t] + Qa * thb[t];
+    const double cd = c0 * x + c1 * y + c2 * z;
+    const double sx = sm[0] * x + sm[1] * y + sm[2] * z, sy = sm[1] * x + sm[3] * y + sm[4] * z,
+                 sz = sm[2] * x + sm[4] * y + sm[5] * z;
+    const double dsd = x * sx + y * sy + z * sz, trs = sm[0] + sm[3] + sm[5];
+    const double mad = ma0 * x + ma1 * y + ma2 * z, mbd = mb0 * x + mb1 * y + mb2 * z;
+    const double mab = ma0 * mb0 + ma1 * mb1 + ma2 * mb2;
+    const double P = Qa * Qb * R.f1 - cd * R.f3 + (1.5 * dsd * R.f5 - 0.5 * trs * R.f3) -
+                     (3.0 * mad * mbd * R.f5 - mab * R.f3);
+    v[0] += 0.5 * P;
+    // dP/dr = QaQb psi1 + 2 c.psi2 + 3 s:psi3 - 6 mu_a.psi3.mu_b
+    const double s1 = -Qa * Qb * R.f3 + 3.0 * cd * R.f5 + 1.5 * trs * R.f5 - 7.5 * dsd * R.f7 -
+                      3.0 * (mab * R.f5 - 5.0 * mad * mbd * R.f7);
+    const double sc = -R.f3, ss = 3.0 * R.f5, smu = -3.0 * R.f5;
+    v[1] += s1 * x + sc * c0 + ss * sx + smu * (ma0 * mbd + mb0 * mad);
+    v[2] += s1 * y + sc * c1 + ss * sy + smu * (ma1 * mbd + mb1 * mad);
+    v[3] += s1 * z + sc * c2 + ss * sz + smu * (ma2 * mbd + mb2 * mad);
+    const double thbx = thb[0] * x + thb[1] * y + thb[2] * z, thby = thb[1] * x + thb[3] * y + thb[4] * z,
+                 thbz = thb[2] * x + thb[4] * y + thb[5] * z;
+    const double dtbd = x * thbx + y * thby + z * thbz, trb = thb[0] + thb[3] + thb[5];
+    v[4] += Qb * R.f1 + mbd * R.f3 + (1.5 * dtbd * R.f5 - 0.5 * trb * R.f3);
+    v[5] += -Qb * x * R.f3 - (3.0 * x * mbd * R.f5 - mb0 * R.f3);
+    v[6] += -Qb * y * R.f3 - (3.0 * y * mbd * R.f5 - mb1 * R.f3);
+    v[7] += -Qb * z * R.f3 - (3.0 * z * mbd * R.f5 - mb2 * R.f3);
+    const double h5 = 1.5 * Qb * R.f5, h3 = 0.5 * Qb * R.f3;
+    v[8] += h5 * x * x - h3;
+    v[9] += h5 * x * y;
+    v[10] += h5 * x * z;
+    v[11] += h5 * y * y - h3;
+    v[12] += h5 * y * z;
+    v[13] += h5 * z * z - h3;
+  }
+  double tot[14];
+  block_sum256<14>(v, tot);
+  if (threadIdx.x == 0) {
+    // self terms of site a
     const double a3 = 2.0 * al * al * al / (3.0 * sp);
     const double tra = tha[0] + tha[3] + tha[5];
     const double mm2 = ma0 * ma0 + ma1 * ma1 + ma2 * ma2;
-    e += -al / sp * Qa * Qa - a3 * mm2 + a3 * Qa * tra;
-    dQ += -2.0 * al / sp * Qa + a3 * tra + bgc * Qtot;
-    dm0 += -2.0 * a3 * ma0;
-    dm1 += -2.0 * a3 * ma1;
-    dm2 += -2.0 * a3 * ma2;
-    dt[0] += a3 * Qa;
-    dt[3] += a3 * Qa;
-    dt[5] += a3 * Qa;
+    double e = tot[0] - al / sp * Qa * Qa - a3 * mm2 + a3 * Qa * tra;
+    if (a == 0) e += 0.5 * bgc * Qtot * Qtot;
     double* qa = qacc + (size_t)ra * QA_STRIDE;
-    qa[QA_G_QQ_SR + 0] = g0;
-    qa[QA_G_QQ_SR + 1] = g1;
-    qa[QA_G_QQ_SR + 2] = g2;
-    qa[QA_DQ_QQ_SR] = dQ;
-    qa[QA_DMU_QQ_SR + 0] = dm0;
-    qa[QA_DMU_QQ_SR + 1] = dm1;
-    qa[QA_DMU_QQ_SR + 2] = dm2;
-    for (int t = 0; t < 6; t++) qa[QA_DTH_QQ_SR + t] = dt[t];
-    esum += e;
+    for (int t = 0; t < 3; t++) qa[QA_G_QQ_SR + t] = tot[1 + t];
+    qa[QA_DQ_QQ_SR] = tot[4] - 2.0 * al / sp * Qa + a3 * tra + bgc * Qtot;
+    for (int t = 0; t < 3; t++) qa[QA_DMU_QQ_SR + t] = tot[5 + t] - 2.0 * a3 * (t == 0 ? ma0 : t == 1 ? ma1 : ma2);
+    for (int t = 0; t < 6; t++) qa[QA_DTH_QQ_SR + t] = tot[8 + t] + ((t == 0 || t == 3 || t == 5) ? a3 * Qa : 0.0);
+    atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_SR], e);
   }
-  double v[1] = {esum}, tot[1];
-  block_sum256<1>(v, tot);
-  if (threadIdx.x == 0) facc[f * FA_COUNT + FA_E_QQ_SR] = tot[0] + 0.5 * bgc * Qtot * Qtot;
 }
 
-hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int cap_qm, const double* Q, const double* mu,
+hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, const double* Q, const double* mu,
                        const double* theta, Work& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_qmqm, dim3(fa.n_frames), dim3(256), 0, s, g, fa, w.qm4, cap_qm, Q, mu, theta, w.qacc, w.facc);
+  if (max_nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qmqm, dim3(max_nq, fa.n_frames), dim3(256), 0, s, g, fa, w.qm4, cap_qm, Q, mu, theta, w.qacc,
+                     w.facc);
   return hipGetLastError();
 }
 
@@ -1153,9 +1406,41 @@ hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* sit
   return hipGetLastError();
 }
 
+// gradients for upstream gE from the stored gradients of E
+__global__ __launch_bounds__(256) void k_scale_grads(const double* __restrict__ gE, int nq, int nm,
+                                                     const double* __restrict__ gq, const double* __restrict__ gQ,
+                                                     const double* __restrict__ gmu, const double* __restrict__ gth,
+                                                     const double* __restrict__ gm, const double* __restrict__ gmq,
+                                                     double* __restrict__ o_q, double* __restrict__ o_Q,
+                                                     double* __restrict__ o_mu, double* __restrict__ o_th,
+                                                     double* __restrict__ o_m, double* __restrict__ o_mq) {
+  const double ge = gE ? gE[0] : 1.0;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < nq) {
+    for (int t = 0; t < 3; t++) o_q[3 * i + t] = ge * gq[3 * i + t];
+    o_Q[i] = ge * gQ[i];
+    for (int t = 0; t < 3; t++) o_mu[3 * i + t] = ge * gmu[3 * i + t];
+    for (int t = 0; t < 6; t++) o_th[6 * i + t] = ge * gth[6 * i + t];
+  }
+  if (i < nm) {
+    for (int t = 0; t < 3; t++) o_m[3 * i + t] = ge * gm[3 * i + t];
+    if (o_mq) o_mq[i] = ge * gmq[i];
+  }
+}
+
+hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq, const double* gQ, const double* gmu,
+                              const double* gth, const double* gm, const double* gmq, double* o_q, double* o_Q,
+                              double* o_mu, double* o_th, double* o_m, double* o_mq, hipStream_t s) {
+  const int n = nq > nm ? nq : nm;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_grads, dim3((n + 255) / 256), dim3(256), 0, s, gE, nq, nm, gq, gQ, gmu, gth, gm, gmq, o_q,
+                     o_Q, o_mu, o_th, o_m, o_mq);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
-                       int cap_mm) {
+                       int cap_mm, int mm_tables) {
   const int nmax = max_nq > max_nm ? max_nq : max_nm;
   if (nmax > 0) {
     dim3 grid((nmax + 255) / 256, fa.n_frames);
@@ -1164,7 +1449,7 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (max_nm > 0) {
+  if (max_nm > 0 && mm_tables) {
     const long n = (long)max_nm * g.R;
     dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
     hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, w.mm4, cap_mm, w.mm_tab);

@@ -209,14 +209,21 @@ class Plan:
 class EwaldFunction(torch.autograd.Function):
     """E, phi, efield, efgrad = EwaldFunction.apply(plan, qm_pos, Q, mu, theta, mm_pos, mm_q).
 
-    The backward pass is the library's adjoint (once differentiable); the
-    saved context holds the MM structure factor and the MM field data at the
-    QM sites, and the phases e^{i k.r} are recomputed rather than stored.
+    The backward pass is the library's adjoint (once differentiable).  The
+    forward call already evaluates the gradients of E (its adjoint kernel runs
+    beside the forward kernel on a second stream) and keeps them with the MM
+    structure factor and the MM field data in the saved context; a backward
+    with upstream gradients only on E scales them, one with upstream gradients
+    on phi/efield/efgrad re-runs the adjoint.  Phases e^{i k.r} are recomputed,
+    never stored.
     """
 
     @staticmethod
     def forward(ctx, plan, qm_pos, Q, mu, theta, mm_pos, mm_q):
         energy, phi, efield, efgrad, cbuf = plan.forward(qm_pos, Q, mu, theta, mm_pos, mm_q, want_ctx=True)
+        # unused outputs get no upstream gradient (None) instead of zeros, so the
+        # library can take its energy-only adjoint
+        ctx.set_materialize_grads(False)
         ctx.plan = plan
         ctx.save_for_backward(qm_pos, Q, mu, theta, mm_pos, mm_q, cbuf)
         return energy, phi, efield, efgrad

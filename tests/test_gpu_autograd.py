@@ -99,3 +99,21 @@ def test_double_backward_raises():
     (g,) = torch.autograd.grad(E, x[0], create_graph=True)
     with pytest.raises(RuntimeError):
         g.sum().backward()
+
+
+def test_recompute_adjoint_matches_stored_gradients():
+    """ewald_backward with explicit zero field gradients re-runs the adjoint;
+    it must agree with the gradients the forward call stored."""
+    s = wl.random_system(25, 8, 2222, alpha=0.3, rcut=8.5, kmax=(8, 9, 7), neutral=False)
+    plan = H.make_plan(s)
+    d = H.to_dev(s)
+    args = (d["qm_pos"], d["Q"], d["mu"], d["theta"], d["mm_pos"], d["mm_q"])
+    E, phi, ef, eg, ctx = plan.forward(*args, want_ctx=True)
+    gE = torch.tensor(1.7, dtype=torch.float64, device=E.device)
+    fast = plan.backward(ctx, *args, gE=gE)
+    slow = plan.backward(ctx, *args, gE=gE, g_phi=torch.zeros_like(phi), g_efield=torch.zeros_like(ef),
+                         g_efgrad=torch.zeros_like(eg))
+    torch.cuda.synchronize()
+    for a, b, name in zip(fast, slow, H.BWD_KEYS):
+        err = H.relerr(a.cpu().numpy(), b.cpu().numpy())
+        assert err <= 1e-12, (name, err)

@@ -75,3 +75,12 @@ def test_fp32_real_space_error_report():
     print("[fp32-real] errors vs FP64 oracle:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     # not a parity gate: FP32 real space is reported; it must still be sane
     assert max(errs.values()) < 1e-3
+
+
+@pytest.mark.parametrize("variant", ["1", "2", "3"])
+def test_backward_kernel_variants(variant, monkeypatch):
+    """Every backward kernel variant (VALU Horner with 1 or 2 atoms per lane,
+    matrix cores) meets the parity bar."""
+    monkeypatch.setenv("MPEWALD_BWD", variant)
+    _check(wl.random_system(41, 11, 3333, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11)))
+    _check(wl.random_system(42, 3, 700, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=5))
