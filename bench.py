@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and batched measurements")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles instead of timing candidates")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device-to-device copy of 256 MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -93,6 +94,8 @@ def main():
     # the plan records HIP events around every launch on the stream it runs on
     pplan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
                              profile=True))
+    if not args.no_autotune:
+        pplan.autotune(s.nm)   # times candidate tilings on this device (untimed setup)
 
     def tens(a, grad=True):
         return torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)

@@ -48,7 +48,7 @@ struct ewald_plan {
   Grid g;
   Tuning t;
   Work w;
-  int cap_qm, cap_mm, cap_frames, cap_slots, cap_kc;
+  int cap_qm, cap_mm, cap_frames, cap_slots, cap_kc, cap_cells;
   std::vector<void*> allocs;
   std::string describe;
   // batched graph state
@@ -168,9 +168,9 @@ void free_plan(ewald_plan* pl) {
 void set_describe(ewald_plan* pl) {
   char buf[256];
   static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-16col", "mfma-16col"};
-  snprintf(buf, sizeof(buf), "fwd=valu zc=%d nzp=%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", pl->g.Zc, pl->g.NZP,
-           bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY,
-           pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
+  snprintf(buf, sizeof(buf), "fwd=valu zc=%d nzp=%d blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", pl->g.Zc,
+           pl->g.NZP, pl->t.fwd_target, bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto",
+           pl->g.NX, pl->g.NY, pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
   pl->describe = buf;
 }
 
@@ -187,6 +187,32 @@ FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int
   f.moff = moff;
   f.slot_base = slot_base;
   return f;
+}
+
+// Cells of edge >= rcut per axis (capped); the cell list is used only when
+// every frame has at least 3 cells per axis, else real space runs over all
+// pairs.  Returns whether the cell list is used and fills nc/cell_base.
+bool assign_cells(const ewald_plan* pl, FrameDev* frames, int n) {
+  bool ok = (pl->p.flags & EWALD_CELL_LIST) != 0;
+  // Building the list costs a few kernel launches; over all pairs, real space
+  // costs one distance test per (QM site, MM atom).  Use cells only when that
+  // product is large, unless MPEWALD_CELLS forces the choice.
+  long pairs = 0;
+  for (int f = 0; f < n; f++) pairs += (long)frames[f].nq * frames[f].nm;
+  int force = -1;
+  if (const char* e = getenv("MPEWALD_CELLS")) force = atoi(e) ? 1 : 0;
+  if (force == 0 || (force < 0 && pairs < 8000000L)) ok = false;
+  for (int f = 0; f < n && ok; f++)
+    for (int a = 0; a < 3; a++)
+      if ((int)std::floor(frames[f].box[a] / pl->p.rcut) < 3) ok = false;
+  int base = 0;
+  for (int f = 0; f < n; f++) {
+    for (int a = 0; a < 3; a++)
+      frames[f].nc[a] = ok ? std::min(kMaxCellsPerAxis, (int)std::floor(frames[f].box[a] / pl->p.rcut)) : 0;
+    frames[f].cell_base = base;
+    if (ok) base += frames[f].nc[0] * frames[f].nc[1] * frames[f].nc[2] + 1;
+  }
+  return ok;
 }
 
 // atoms per forward block so that the grid has about kTargetBlocks blocks
@@ -279,6 +305,7 @@ struct Seq {
   int plain;
   int fp32;
   int qmqm;
+  int cells;  // real space over the cell list
 };
 
 #define LCHK_P(pl_, s_, name, expr)                                                                 \
@@ -292,13 +319,18 @@ struct Seq {
   } while (0)
 #define LCHK(expr) LCHK_P(pl, q.s, #expr, expr)
 
-ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mm_xyz,
-                         const double* mm_q, int mm_tables) {
+ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mu, const double* theta,
+                         const double* mm_xyz, const double* mm_q, int mm_tables, int unit_eff) {
   ewald_plan* pl = q.pl;
-  LCHK(launch_zero(pl->w.qacc, (size_t)q.total_nq * QA_STRIDE, q.s));
+  if (q.total_nq > q.max_nq)  // packed rows with gaps: clear every QM row (prep clears only the used ones)
+    LCHK(launch_zero(pl->w.qacc, (size_t)q.total_nq * QA_STRIDE, q.s));
   LCHK(launch_zero(pl->w.facc, (size_t)q.fa.n_frames * FA_COUNT, q.s));
-  LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm, pl->cap_mm,
-                   mm_tables));
+  LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm,
+                   pl->cap_mm, mm_tables, unit_eff));
+  if (q.cells) {
+    LCHK(launch_zero((double*)pl->w.cell_cnt, (size_t)(pl->cap_cells + 1) / 2, q.s));
+    LCHK(launch_cells(q.fa, q.max_nm, pl->cap_mm, pl->w, q.s));
+  }
   return EWALD_OK;
 }
 
@@ -308,7 +340,10 @@ ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu,
   ewald_plan* pl = q.pl;
   LCHK(launch_reduce_smm(pl->g, pl->t, q.fa, q.plain, smm, smm_stride, pl->w, q.s));
   LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 0, q.qmqm, pl->w, q.s));
-  LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
+  if (q.cells)
+    LCHK(launch_real_cells(pl->g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
+  else
+    LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
   if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
   LCHK(launch_finalize_fwd(pl->g, q.fa, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad, site, pl->w, q.s));
   return EWALD_OK;
@@ -338,9 +373,8 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   ewald_plan* pl = q.pl;
   Work& w = pl->w;
   const Grid& g = pl->g;
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, 1);
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, 1, 1);
   if (st != EWALD_OK) return st;
-  LCHK(launch_eff_moments(q.fa, q.max_nq, Q, mu, theta, nullptr, nullptr, nullptr, nullptr, w, q.s));
   LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
   st = fork_to(pl, q.s, aux);
   if (st != EWALD_OK) return st;
@@ -351,17 +385,23 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     {
       const Seq& q = q_;
       LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
-      LCHK(launch_real_mm(g, q.fa, q.max_nm, pl->cap_qm, pl->cap_mm, q.fp32, w, q.s));
+      if (q.cells) {
+        LCHK(launch_zero(w.rpart, (size_t)pl->cap_mm * 4, q.s));
+        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
+      } else {
+        LCHK(launch_real_mm(g, q.fa, q.max_nm, pl->cap_qm, pl->cap_mm, q.fp32, w, q.s));
+      }
       LCHK(launch_reduce_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, g_mm_xyz, g_mm_q, w, q.s));
     }
   }
   LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
   st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site);
   if (st != EWALD_OK) return st;
+  // QM-side adjoint pieces need only S_MM and the effective moments: still beside the MM adjoint
+  LCHK(launch_project_qm(g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 1, q.qmqm, w, q.s));
+  if (!q.cells) LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
   st = join_to(pl, aux, q.s);
   if (st != EWALD_OK) return st;
-  LCHK(launch_project_qm(g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 1, q.qmqm, w, q.s));
-  LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
   LCHK(launch_finalize_bwd(q.fa, q.max_nq, site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
   return EWALD_OK;
 }
@@ -385,7 +425,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   ewald_status_t st = validate_box(p.box, p.rcut);
   if (st != EWALD_OK) return st;
   if (p.precision != EWALD_FP64 && p.precision != EWALD_FP32_REAL) return fail(EWALD_ERR_ARG, "unknown precision");
-  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE)) return fail(EWALD_ERR_ARG, "unknown flags");
+  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE))
+    return fail(EWALD_ERR_ARG, "unknown flags");
   if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
   ewald_plan* pl = new ewald_plan();
   pl->p = p;
@@ -415,6 +456,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->cap_qm = std::max(p.max_qm, 1);
   pl->cap_mm = std::max(p.max_mm, 1);
   pl->cap_frames = p.max_frames;
+  pl->cap_cells = pl->cap_frames * (kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis + 1);
   pl->cap_slots = std::max(64, 4 * kTargetBlocks / std::max(1, fwd_kblocks(pl->g)) + 2 * pl->cap_frames);
   pl->cap_kc = (int)std::max<long>(1, std::min<long>(16, (kTargetBlocks * 256L + pl->cap_mm - 1) / pl->cap_mm));
   const Grid& g = pl->g;
@@ -447,6 +489,10 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.facc, cf * FA_COUNT);
   A(w.one, 1);
   A(w.frames, cf);
+  A(w.cell_cnt, (size_t)pl->cap_cells + 2);
+  A(w.cell_start, (size_t)pl->cap_cells + 2);
+  A(w.cell_atoms, cm);
+  A(w.atom_cell, cm);
 #undef A
   const double one = 1.0;
   if (hipMemset(w.wfrag, 0, sizeof(double2) * cf * (size_t)g.NG * g.NKS * 64 * 2) != hipSuccess ||
@@ -514,6 +560,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.fa.frames = nullptr;
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
   q.fa.n_frames = 1;
+  q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
   if (ctx && !q.plain) {
     plan->t.kc = choose_kc(plan, n_mm);
     CtxView cv = ctx_view(plan->g, ctx, n_qm, n_mm);
@@ -522,7 +569,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
     plan->t = saved;
     return st;
   }
-  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, q.plain ? 0 : 1);
+  st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, q.plain ? 0 : 1, 0);
   if (st == EWALD_OK) {
     hipError_t e;
     {
@@ -581,6 +628,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   q.fa.frames = nullptr;
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
   q.fa.n_frames = 1;
+  q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
   CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
   Work& w = plan->w;
   if (!g_phi && !g_efield && !g_efgrad && !(plan->p.flags & EWALD_PLAIN)) {
@@ -609,7 +657,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
     }                                                                                                  \
   } while (0)
   // the matrix-core backward kernel reads the MM phase tables in its epilogue
-  st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, plan->t.bwd_ilp >= 3 ? 1 : 0);
+  st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, plan->t.bwd_ilp >= 3 ? 1 : 0, 0);
   if (st != EWALD_OK) {
     plan->t = saved;
     return st;
@@ -617,10 +665,15 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   STEP(launch_eff_moments(q.fa, n_qm, Q, mu, theta, gE, g_phi, g_efield, g_efgrad, w, s));
   STEP(launch_sfac_qm(g, q.fa, n_qm, Q, mu, theta, w.qeff, gE, 1, w, s));
   STEP(launch_force_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, w, s));
-  STEP(launch_real_mm(g, q.fa, n_mm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
+  if (q.cells) {
+    STEP(launch_zero(w.rpart, (size_t)plan->cap_mm * 4, s));
+    STEP(launch_real_cells(g, q.fa, n_qm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
+  } else {
+    STEP(launch_real_mm(g, q.fa, n_mm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
+  }
   STEP(launch_reduce_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
   STEP(launch_project_qm(g, q.fa, n_qm, n_qm, cv.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
-  STEP(launch_real_qm(g, q.fa, n_qm, n_mm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
+  if (!q.cells) STEP(launch_real_qm(g, q.fa, n_qm, n_mm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
   if (q.qmqm && n_qm > 0) STEP(launch_qmqm(g, q.fa, n_qm, plan->cap_qm, Q, mu, theta, w, s));
   STEP(launch_finalize_bwd(q.fa, n_qm, cv.site, gE, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, s));
 #undef STEP
@@ -632,8 +685,8 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
 
 namespace {
 
-ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int max_nq, int max_nm, int total_nq,
-                             int total_nm, const double* qm_xyz, const double* Q, const double* mu,
+ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int cells, int max_nq, int max_nm,
+                             int total_nq, int total_nm, const double* qm_xyz, const double* Q, const double* mu,
                              const double* theta, const double* mm_xyz, const double* mm_q, int mode, double* energy,
                              double* phi, double* efield, double* efgrad, double* g_qm_xyz, double* g_Q,
                              double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q) {
@@ -651,13 +704,14 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   q.fa.frames = plan->w.frames;
   q.fa.n_frames = n_frames;
   memset(&q.fa.f0, 0, sizeof(q.fa.f0));
+  q.cells = cells;
   Work& w = plan->w;
   const Grid& g = plan->g;
   if (mode == EWALD_FWD_BWD) {
     return seq_fwd_bwd(q, plan->gaux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
                        w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
   }
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mm_xyz, mm_q, 1);
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, 1, 0);
   if (st != EWALD_OK) return st;
   LCHK(launch_sfac_qm(g, q.fa, max_nq, Q, mu, theta, w.qeff, nullptr, 0, w, s));
   LCHK(launch_sfac_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
@@ -721,6 +775,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     hf[f] = make_frame(frames[f].box, frames[f].n_qm, frames[f].n_mm, frames[f].qm_offset, frames[f].mm_offset, slot);
     slot += (frames[f].n_mm + use.a_chunk - 1) / use.a_chunk;
   }
+  const int cells = assign_cells(plan, hf.data(), n_frames) ? 1 : 0;
   // graph key: frames, pointers, mode, stream, tiles
   std::vector<unsigned char> key;
   for (auto& f : hf) key_push(key, f);
@@ -749,7 +804,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     HIPCHK(hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal));
     plan->capturing = true;
     // QM accumulators are indexed by packed row, so clear every row up to the last one used
-    st = enqueue_batch(plan, plan->gstream, n_frames, max_nq, max_nm, (int)end_q, (int)total_nm, qm_xyz, Q, mu,
+    st = enqueue_batch(plan, plan->gstream, n_frames, cells, max_nq, max_nm, (int)end_q, (int)total_nm, qm_xyz, Q, mu,
                        theta, mm_xyz, mm_q, mode, energy, phi, efield, efgrad, g_qm_xyz, g_Q, g_mu, g_theta,
                        g_mm_xyz, g_mm_q);
     hipError_t ce = hipStreamEndCapture(plan->gstream, &graph);
@@ -815,9 +870,200 @@ extern "C" ewald_status_t ewald_profile_report(ewald_plan* plan, char* buf, size
 }
 
 // ---------------------------------------------------------------- autotuner
+namespace {
+
+std::string tune_key(const ewald_plan* pl, int n_mm) {
+  int bucket = 1;
+  while (bucket < n_mm) bucket <<= 1;
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t cut = arch.find(':');
+  if (cut != std::string::npos) arch = arch.substr(0, cut);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s k%dx%dx%d zc%d nm%d", arch.c_str(), pl->g.NX, pl->g.NY, pl->g.NZ, pl->g.Zc, bucket);
+  return buf;
+}
+
+bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
+  if (!path) return false;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (fgets(line, sizeof(line), fp)) {
+    if (!strstr(line, pat.c_str())) continue;
+    int ft = 0, bw = 0, kc = 0;
+    const char* p1 = strstr(line, "\"fwd_target\": ");
+    const char* p2 = strstr(line, "\"bwd\": ");
+    const char* p3 = strstr(line, "\"kc\": ");
+    if (p1 && p2 && p3 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 && sscanf(p2, "\"bwd\": %d", &bw) == 1 &&
+        sscanf(p3, "\"kc\": %d", &kc) == 1 && ft >= 64 && bw >= 1 && bw <= 3 && kc >= 0 && kc <= pl->cap_kc) {
+      pl->t.fwd_target = ft;
+      pl->t.bwd_ilp = bw;
+      pl->t.kc = kc;
+      found = true;
+    }
+  }
+  fclose(fp);
+  return found;
+}
+
+}  // namespace
+
 extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char* cache_path) {
-  (void)n_mm;
-  (void)cache_path;
+  g_last_error.clear();
   if (!plan) return fail(EWALD_ERR_ARG, "null plan");
-  return fail(EWALD_ERR_ARG, "autotune not available in this build");
+  if (n_mm < 1 || n_mm > plan->cap_mm) return fail(EWALD_ERR_CAPACITY, "n_mm=%d outside 1..%d", n_mm, plan->cap_mm);
+  const std::string key = tune_key(plan, n_mm);
+  if (tune_lookup(plan, key, cache_path)) {
+    set_describe(plan);
+    return EWALD_OK;
+  }
+  // synthetic frame: uniform MM charges (neutral) and a few QM multipoles near the centre
+  const int nq = std::min(8, plan->cap_qm);
+  std::vector<double> hm(3 * (size_t)n_mm), hq(n_mm), hqp(3 * (size_t)nq), hQ(nq), hmu(3 * (size_t)nq),
+      hth(6 * (size_t)nq);
+  unsigned long long st64 = 0x9E3779B97F4A7C15ull;
+  auto rnd = [&]() {
+    st64 = st64 * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(st64 >> 11) * (1.0 / 9007199254740992.0);
+  };
+  double qs = 0.0;
+  for (int i = 0; i < n_mm; i++) {
+    for (int a = 0; a < 3; a++) hm[3 * (size_t)i + a] = rnd() * plan->p.box[a];
+    hq[i] = rnd() * 1.8 - 0.9;
+    qs += hq[i];
+  }
+  for (int i = 0; i < n_mm; i++) hq[i] -= qs / n_mm;
+  for (int j = 0; j < nq; j++) {
+    for (int a = 0; a < 3; a++) hqp[3 * j + a] = plan->p.box[a] * (0.45 + 0.1 * rnd());
+    hQ[j] = rnd() - 0.5;
+    for (int a = 0; a < 3; a++) hmu[3 * j + a] = 0.2 * (rnd() - 0.5);
+    for (int a = 0; a < 6; a++) hth[6 * j + a] = 0.1 * (rnd() - 0.5);
+  }
+  double *dm = nullptr, *dq = nullptr, *dqp = nullptr, *dQ = nullptr, *dmu = nullptr, *dth = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ewald_status_t st = EWALD_OK;
+  const Tuning saved = plan->t;
+  struct Cand {
+    int ft, bw, kc;
+  };
+  double best_f = 1e30, best_b = 1e30;
+  Tuning best = saved;
+  std::string report;
+#define TCHK(expr)                                                                  \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      st = fail(EWALD_ERR_HIP, "autotune %s: %s", #expr, hipGetErrorString(e_));    \
+      goto done;                                                                    \
+    }                                                                               \
+  } while (0)
+  {
+    TCHK(hipMalloc(&dm, hm.size() * 8));
+    TCHK(hipMalloc(&dq, hq.size() * 8));
+    TCHK(hipMalloc(&dqp, hqp.size() * 8));
+    TCHK(hipMalloc(&dQ, hQ.size() * 8));
+    TCHK(hipMalloc(&dmu, hmu.size() * 8));
+    TCHK(hipMalloc(&dth, hth.size() * 8));
+    TCHK(hipMemcpy(dm, hm.data(), hm.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipMemcpy(dq, hq.data(), hq.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipMemcpy(dqp, hqp.data(), hqp.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipMemcpy(dQ, hQ.data(), hQ.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipMemcpy(dmu, hmu.data(), hmu.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipMemcpy(dth, hth.data(), hth.size() * 8, hipMemcpyHostToDevice));
+    TCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    TCHK(hipEventCreate(&e0));
+    TCHK(hipEventCreate(&e1));
+    Seq q;
+    q.pl = plan;
+    q.s = s;
+    q.plain = 0;
+    q.fp32 = 0;
+    q.qmqm = 1;
+    q.cells = 0;
+    q.max_nq = q.total_nq = nq;
+    q.max_nm = q.total_nm = n_mm;
+    q.fa.frames = nullptr;
+    q.fa.f0 = make_frame(plan->p.box, nq, n_mm, 0, 0, 0);
+    q.fa.n_frames = 1;
+    st = seq_begin(q, dqp, dQ, dmu, dth, dm, dq, 1, 1);
+    if (st != EWALD_OK) goto done;
+    TCHK(launch_sfac_qm(plan->g, q.fa, nq, dQ, dmu, dth, plan->w.qeff, nullptr, 1, plan->w, s));
+    auto time_it = [&](auto&& launch) -> double {
+      hipError_t e = launch();  // warm-up
+      if (e != hipSuccess) return -1.0;
+      if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+      for (int r = 0; r < 3; r++)
+        if (launch() != hipSuccess) return -1.0;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+      return 1e3 * ms / 3.0;
+    };
+    char item[160];
+    for (int ft : {2048, 4096, 8192, 16384}) {
+      plan->t = saved;
+      plan->t.fwd_target = ft;
+      plan->t.a_chunk = 0;
+      plan->t.a_chunk = choose_a_chunk(plan, {n_mm});
+      const double us = time_it([&]() { return launch_sfac_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s); });
+      if (us < 0) {
+        st = fail(EWALD_ERR_HIP, "autotune: forward launch failed");
+        goto done;
+      }
+      snprintf(item, sizeof(item), "%s\"fwd%d\": %.1f", report.empty() ? "" : ", ", ft, us);
+      report += item;
+      if (us < best_f) {
+        best_f = us;
+        best.fwd_target = ft;
+      }
+    }
+    for (int bw : {2, 3}) {
+      if (bw == 3 && !force_mm_mfma_has_nks(plan->g.NKS)) continue;
+      for (int kc : {0, 1, 2, 4, 8, 16}) {
+        if (kc > plan->cap_kc) continue;
+        plan->t = saved;
+        plan->t.bwd_ilp = bw;
+        plan->t.kc = kc;
+        plan->t.kc = choose_kc(plan, n_mm);
+        const double us = time_it([&]() { return launch_force_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s); });
+        if (us < 0) {
+          st = fail(EWALD_ERR_HIP, "autotune: adjoint launch failed");
+          goto done;
+        }
+        snprintf(item, sizeof(item), ", \"bwd%d_kc%d\": %.1f", bw, plan->t.kc, us);
+        report += item;
+        if (us < best_b) {
+          best_b = us;
+          best.bwd_ilp = bw;
+          best.kc = kc;
+        }
+      }
+    }
+  }
+done:
+#undef TCHK
+  plan->t = st == EWALD_OK ? best : saved;
+  plan->t.a_chunk = 0;
+  if (s) (void)hipStreamSynchronize(s);
+  for (double* p : {dm, dq, dqp, dQ, dmu, dth})
+    if (p) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (st != EWALD_OK) return st;
+  set_describe(plan);
+  if (cache_path) {
+    FILE* fp = fopen(cache_path, "a");
+    if (fp) {
+      fprintf(fp, "{\"key\": \"%s\", \"fwd_target\": %d, \"bwd\": %d, \"kc\": %d, \"times_us\": {%s}}\n", key.c_str(),
+              plan->t.fwd_target, plan->t.bwd_ilp, plan->t.kc, report.c_str());
+      fclose(fp);
+    }
+  }
+  return EWALD_OK;
 }

@@ -14,7 +14,8 @@ struct FrameDev {
   int nq, nm;        // atoms in this frame
   int qoff, moff;    // first packed row of this frame
   int slot_base;     // first partial-sum slot of the forward structure-factor kernel
-  int pad;
+  int nc[3];         // real-space cells per axis (edge >= rcut); 0 = no cell list
+  int cell_base;     // first entry of this frame in the cell arrays
 };
 
 // Frames are either one descriptor passed by value (single-frame calls) or
@@ -97,7 +98,13 @@ struct Work {
   double* facc;       // [cap_frames][FA_COUNT]
   double* one;        // a device 1.0
   FrameDev* frames;   // [cap_frames]
+  int* cell_cnt;      // [cap_cells]          atoms per cell, then fill counters
+  int* cell_start;    // [cap_cells]          first sorted atom of each cell (+ end entry per frame)
+  int* cell_atoms;    // [cap_mm]             frame-local MM indices sorted by cell
+  int* atom_cell;     // [cap_mm]             cell of each MM atom
 };
+
+static constexpr int kMaxCellsPerAxis = 16;
 
 // Tunables of the two hot kernels.
 struct Tuning {
@@ -112,9 +119,12 @@ struct Tuning {
 // ---------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error; all are asynchronous.
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+// wrap positions, clear the QM accumulators, sum the charges, build the phase
+// tables; unit_eff also sets the effective moments for an upstream gradient of 1
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
-                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
-                       int cap_mm, int mm_tables);
+                       const double* Q, const double* mu, const double* theta, const double* mm_xyz,
+                       const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
+                       int unit_eff);
 hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const double* Q, const double* mu,
                           const double* theta, const double* qeff, const double* gE, int with_w, Work& w,
                           hipStream_t s);
@@ -132,6 +142,10 @@ hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max
                           int backward, int fp32, Work& w, hipStream_t s);
 hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
                           hipStream_t s);
+// cell list (edge >= rcut) of the MM atoms and the real-space kernels that use it
+hipError_t launch_cells(const FrameArg& fa, int max_nm, int cap_mm, Work& w, hipStream_t s);
+hipError_t launch_real_cells(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, int cap_mm, int backward,
+                             int fp32, Work& w, hipStream_t s);
 hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, const double* Q, const double* mu,
                        const double* theta, Work& w, hipStream_t s);
 hipError_t launch_finalize_fwd(const Grid& g, const FrameArg& fa, const double* Q, const double* mu,

@@ -41,6 +41,8 @@ DEV FrameDev get_frame(const FrameArg& fa, int f) {
   r.qoff = uniform_int(r.qoff);
   r.moff = uniform_int(r.moff);
   r.slot_base = uniform_int(r.slot_base);
+  for (int a = 0; a < 3; a++) r.nc[a] = uniform_int(r.nc[a]);
+  r.cell_base = uniform_int(r.cell_base);
   return r;
 }
 
@@ -101,8 +103,10 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
 // charges of each subsystem of the frame.
 __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __restrict__ qm_xyz,
                                                   const double* __restrict__ Q, const double* __restrict__ mm_xyz,
-                                                  const double* __restrict__ mm_q, double* __restrict__ qm4,
+                                                  const double* __restrict__ mm_q, const double* __restrict__ mu,
+                                                  const double* __restrict__ theta, double* __restrict__ qm4,
                                                   int cap_qm, double* __restrict__ mm4, int cap_mm,
+                                                  double* __restrict__ qacc, double* __restrict__ qeff, int unit_eff,
                                                   double* __restrict__ facc) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
@@ -119,49 +123,78 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
     for (int a = 0; a < 3; a++) qm4[(size_t)a * cap_qm + r] = wrap_coord(qm_xyz[3 * (size_t)r + a], fr.box[a]);
     qm4[(size_t)3 * cap_qm + r] = Q[r];
     v[1] = Q[r];
+    // the QM accumulators of this row start from zero
+    for (int t = 0; t < QA_STRIDE; t++) qacc[(size_t)r * QA_STRIDE + t] = 0.0;
+    if (unit_eff) {
+      // effective moments for an upstream gradient of 1 on E only: the moments themselves
+      double* o = qeff + 10 * (size_t)r;
+      o[0] = Q[r];
+      for (int t = 0; t < 3; t++) o[1 + t] = mu[3 * (size_t)r + t];
+      for (int t = 0; t < 6; t++) o[4 + t] = theta[6 * (size_t)r + t];
+    }
   }
   double tot[2];
   block_sum256<2>(v, tot);
   if (threadIdx.x == 0 && blockIdx.x * 256 < max(fr.nm, fr.nq)) {
     atomicAdd(&facc[f * FA_COUNT + FA_QTOT_MM], tot[0]);
     atomicAdd(&facc[f * FA_COUNT + FA_QTOT_QM], tot[1]);
+    if (unit_eff) atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[1]);
   }
 }
 
-// Per-atom phase tables: one thread per entry.  Row layout (complex):
+// Per-atom phase tables.  Row layout (complex):
 // [e^{i 2pi n x/Lx}, n = 0..mx][e^{i 2pi n y/Ly}, n = -my..my][e^{i 2pi n z/Lz}, n = -mz..mz, then zeros]
+// One thread per run of kTabRun entries of one axis: the first entry from
+// sincospi, the rest by multiplying with e^{i 2pi x/L} (at most kTabRun-1
+// rounding steps from an exact start).
+static constexpr int kTabRun = 8;
+
 __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, const double* __restrict__ pos4,
                                                   int cap, double2* __restrict__ tab) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
   const int off = qm_side ? fr.qoff : fr.moff;
+  const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
+            rz = (g.NZP + kTabRun - 1) / kTabRun;
+  const int runs = rx + ry + rz;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)n_atoms * g.R) return;
-  const int a = (int)(e / g.R), t = (int)(e - (long)a * g.R);
+  if (e >= (long)n_atoms * runs) return;
+  const int a = (int)(e / runs), t = (int)(e - (long)a * runs);
   const int row = off + a;
-  int axis, n;
-  if (t < g.NX) {
+  int axis, first, count, n0, dst;
+  if (t < rx) {
     axis = 0;
-    n = t;
-  } else if (t < g.NX + g.NY) {
+    first = t * kTabRun;
+    count = min(kTabRun, g.NX - first);
+    n0 = first;
+    dst = first;
+  } else if (t < rx + ry) {
     axis = 1;
-    n = t - g.NX - g.my;
+    first = (t - rx) * kTabRun;
+    count = min(kTabRun, g.NY - first);
+    n0 = first - g.my;
+    dst = g.NX + first;
   } else {
     axis = 2;
-    const int iz = t - g.NX - g.NY;
-    if (iz >= g.NZ) {
-      tab[(size_t)row * g.R + t] = make_double2(0.0, 0.0);
-      return;
-    }
-    n = iz - g.mz;
+    first = (t - rx - ry) * kTabRun;
+    count = min(kTabRun, g.NZP - first);
+    n0 = first - g.mz;
+    dst = g.NX + g.NY + first;
   }
-  const double x = pos4[(size_t)axis * cap + row];
-  double s, c;
-  sincospi(2.0 * (double)n * x / fr.box[axis], &s, &c);
-  tab[(size_t)row * g.R + t] = make_double2(c, s);
+  const double x = pos4[(size_t)axis * cap + row] / fr.box[axis];
+  double s0, c0, s1, c1;
+  sincospi(2.0 * (double)n0 * x, &s0, &c0);
+  sincospi(2.0 * x, &s1, &c1);
+  double2 v = make_double2(c0, s0);
+  const double2 step = make_double2(c1, s1);
+  double2* __restrict__ o = tab + (size_t)row * g.R + dst;
+  const int limit = axis == 2 ? g.NZ - first : count;  // z entries past NZ are padding
+  for (int u = 0; u < count; u++) {
+    o[u] = u < limit ? v : make_double2(0.0, 0.0);
+    v = cmul(v, step);
+  }
 }
-
 
 // ------------------------------------------------------------------ QM structure factors
 // A(k) = sum_j Q_j e_j, B(k) = sum_j i (k.mu_j) e_j, C(k) = sum_j -1/2 (k.theta_j.k) e_j,
@@ -1142,6 +1175,219 @@ hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ cell list
+// MM atoms are binned into nc[0] x nc[1] x nc[2] cells of edge >= rcut (at
+// least 3 per axis), so all minimum-image partners within rcut of a point lie
+// in its cell and the 26 around it.  Counting sort: count, scan, fill.
+DEV int cell_of(double x, double y, double z, const FrameDev& fr) {
+  const int cx = min(fr.nc[0] - 1, (int)(x * fr.inv_box[0] * fr.nc[0]));
+  const int cy = min(fr.nc[1] - 1, (int)(y * fr.inv_box[1] * fr.nc[1]));
+  const int cz = min(fr.nc[2] - 1, (int)(z * fr.inv_box[2] * fr.nc[2]));
+  return (cx * fr.nc[1] + cy) * fr.nc[2] + cz;
+}
+
+// block-local histogram in LDS, one global atomic per (block, occupied cell)
+__global__ __launch_bounds__(256) void k_cell_count(FrameArg fa, const double* __restrict__ mm4, int cap_mm,
+                                                    int* __restrict__ cell_cnt, int* __restrict__ atom_cell) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  if (fr.nc[0] == 0 || blockIdx.x * 256 >= fr.nm) return;
+  const int ncell = fr.nc[0] * fr.nc[1] * fr.nc[2];
+  __shared__ int hist[kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis];
+  for (int c = threadIdx.x; c < ncell; c += 256) hist[c] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < fr.nm) {
+    const int row = fr.moff + i;
+    const int c = cell_of(mm4[row], mm4[(size_t)cap_mm + row], mm4[(size_t)2 * cap_mm + row], fr);
+    atom_cell[row] = c;
+    atomicAdd(&hist[c], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncell; c += 256)
+    if (hist[c]) atomicAdd(&cell_cnt[fr.cell_base + c], hist[c]);
+}
+
+// one block per frame: exclusive scan of the counts (ncells + 1 entries), counts reset for the fill
+__global__ __launch_bounds__(256) void k_cell_scan(FrameArg fa, int* __restrict__ cell_cnt,
+                                                   int* __restrict__ cell_start) {
+  const int f = blockIdx.x;
+  const FrameDev fr = get_frame(fa, f);
+  if (fr.nc[0] == 0) return;
+  const int n = fr.nc[0] * fr.nc[1] * fr.nc[2];
+  const int per = (n + 255) / 256;
+  const int b0 = threadIdx.x * per, b1 = min(n, b0 + per);
+  int local = 0;
+  for (int c = b0; c < b1; c++) local += cell_cnt[fr.cell_base + c];
+  __shared__ int part[256];
+  part[threadIdx.x] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < 256; t++) {
+      const int v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int c = b0; c < b1; c++) {
+    const int v = cell_cnt[fr.cell_base + c];
+    cell_start[fr.cell_base + c] = run;
+    cell_cnt[fr.cell_base + c] = 0;
+    run += v;
+  }
+  if (threadIdx.x == 255) cell_start[fr.cell_base + n] = fr.nm;
+}
+
+// ranks within the block from LDS atomics, one global atomic per (block, cell) for the base
+__global__ __launch_bounds__(256) void k_cell_fill(FrameArg fa, int* __restrict__ cell_cnt,
+                                                   const int* __restrict__ cell_start,
+                                                   const int* __restrict__ atom_cell, int* __restrict__ cell_atoms) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  if (fr.nc[0] == 0 || blockIdx.x * 256 >= fr.nm) return;
+  const int ncell = fr.nc[0] * fr.nc[1] * fr.nc[2];
+  __shared__ int cnt[kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis];
+  for (int c = threadIdx.x; c < ncell; c += 256) cnt[c] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int c = -1, rank = 0;
+  if (i < fr.nm) {
+    c = atom_cell[fr.moff + i];
+    rank = atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  for (int cc = threadIdx.x; cc < ncell; cc += 256)
+    if (cnt[cc]) cnt[cc] = atomicAdd(&cell_cnt[fr.cell_base + cc], cnt[cc]);
+  __syncthreads();
+  if (c >= 0) cell_atoms[fr.moff + cell_start[fr.cell_base + c] + cnt[c] + rank] = i;
+}
+
+hipError_t launch_cells(const FrameArg& fa, int max_nm, int cap_mm, Work& w, hipStream_t s) {
+  if (max_nm == 0) return hipSuccess;
+  dim3 grid((max_nm + 255) / 256, fa.n_frames);
+  hipLaunchKernelGGL(k_cell_count, grid, dim3(256), 0, s, fa, w.mm4, cap_mm, w.cell_cnt, w.atom_cell);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cell_scan, dim3(fa.n_frames), dim3(256), 0, s, fa, w.cell_cnt, w.cell_start);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cell_fill, grid, dim3(256), 0, s, fa, w.cell_cnt, w.cell_start, w.atom_cell, w.cell_atoms);
+  return hipGetLastError();
+}
+
+// Real space over the cell list: block (QM site, one of the 27 neighbour
+// cells).  Forward accumulates phi, grad phi, 1/2 grad grad phi of the site;
+// backward accumulates dL/dR of the site (effective moments) and adds the MM
+// partners' dL/dR and dL/dq into rpart.
+template <typename T, int BWD>
+__global__ __launch_bounds__(256) void k_real_cells(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
+                                                    const double* __restrict__ mm4, int cap_mm,
+                                                    const int* __restrict__ cell_start,
+                                                    const int* __restrict__ cell_atoms,
+                                                    const double* __restrict__ qeff, double* __restrict__ qacc,
+                                                    double* __restrict__ rpart) {
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int j = blockIdx.x;
+  if (j >= fr.nq) return;
+  const int r = fr.qoff + j;
+  const double X = qm4[r], Y = qm4[(size_t)cap_qm + r], Zc = qm4[(size_t)2 * cap_qm + r];
+  // neighbour cell of this block
+  const int nb = blockIdx.y;
+  const int dx = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dz = nb % 3 - 1;
+  const int cx = min(fr.nc[0] - 1, (int)(X * fr.inv_box[0] * fr.nc[0]));
+  const int cy = min(fr.nc[1] - 1, (int)(Y * fr.inv_box[1] * fr.nc[1]));
+  const int cz = min(fr.nc[2] - 1, (int)(Zc * fr.inv_box[2] * fr.nc[2]));
+  const int c = (((cx + dx + fr.nc[0]) % fr.nc[0]) * fr.nc[1] + (cy + dy + fr.nc[1]) % fr.nc[1]) * fr.nc[2] +
+                (cz + dz + fr.nc[2]) % fr.nc[2];
+  const int s0 = cell_start[fr.cell_base + c], s1 = cell_start[fr.cell_base + c + 1];
+  const T a = (T)g.alpha;
+  const double rc2 = g.rcut * g.rcut;
+  constexpr int NV = BWD ? 3 : 10;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; t++) acc[t] = 0.0;
+  T Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
+  if (BWD) {
+    const double* qe = qeff + 10 * (size_t)r;
+    Qe = (T)qe[0]; m0 = (T)qe[1]; m1 = (T)qe[2]; m2 = (T)qe[3];
+    t0 = (T)qe[4]; t1 = (T)qe[5]; t2 = (T)qe[6]; t3 = (T)qe[7]; t4 = (T)qe[8]; t5 = (T)qe[9];
+  }
+  for (int p = s0 + threadIdx.x; p < s1; p += 256) {
+    const int i = cell_atoms[fr.moff + p];
+    const int row = fr.moff + i;
+    double ddx = X - mm4[row], ddy = Y - mm4[(size_t)cap_mm + row], ddz = Zc - mm4[(size_t)2 * cap_mm + row];
+    min_image(ddx, ddy, ddz, fr);
+    const double r2d = ddx * ddx + ddy * ddy + ddz * ddz;
+    if (!(r2d < rc2) || r2d == 0.0) continue;
+    const T x = (T)ddx, y = (T)ddy, z = (T)ddz;
+    const Radial<T> R = radial<T>((T)r2d, a);
+    const T q = (T)mm4[(size_t)3 * cap_mm + row];
+    if (!BWD) {
+      acc[0] += (double)(q * R.f1);
+      acc[1] += (double)(-q * x * R.f3);
+      acc[2] += (double)(-q * y * R.f3);
+      acc[3] += (double)(-q * z * R.f3);
+      const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
+      acc[4] += (double)(h5 * x * x - h3);
+      acc[5] += (double)(h5 * x * y);
+      acc[6] += (double)(h5 * x * z);
+      acc[7] += (double)(h5 * y * y - h3);
+      acc[8] += (double)(h5 * y * z);
+      acc[9] += (double)(h5 * z * z - h3);
+    } else {
+      const T md = m0 * x + m1 * y + m2 * z;
+      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+      const T dtd = x * thx + y * thy + z * thz;
+      const T tr = t0 + t3 + t5;
+      const T s1c = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+      const T s2 = -R.f3;
+      const T s3 = T(3) * R.f5;
+      const double gx = (double)(s1c * x + s2 * m0 + s3 * thx), gy = (double)(s1c * y + s2 * m1 + s3 * thy),
+                   gz = (double)(s1c * z + s2 * m2 + s3 * thz);
+      acc[0] += (double)q * gx;
+      acc[1] += (double)q * gy;
+      acc[2] += (double)q * gz;
+      double* o = rpart + (size_t)row * 4;
+      atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
+      atomicAdd(&o[1], -(double)q * gx);
+      atomicAdd(&o[2], -(double)q * gy);
+      atomicAdd(&o[3], -(double)q * gz);
+    }
+  }
+  double tot[NV];
+  block_sum256<NV>(acc, tot);
+  if (threadIdx.x == 0) {
+    double* qa = qacc + (size_t)r * QA_STRIDE;
+    if (!BWD) {
+      atomicAdd(&qa[QA_PHI_SR], tot[0]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_SR + t], tot[1 + t]);
+      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_SR + t], tot[4 + t]);
+    } else {
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], tot[t]);
+    }
+  }
+}
+
+hipError_t launch_real_cells(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, int cap_mm, int backward,
+                             int fp32, Work& w, hipStream_t s) {
+  if (max_nq == 0) return hipSuccess;
+  dim3 grid(max_nq, 27, fa.n_frames);
+#define RC(T, B)                                                                                                  \
+  hipLaunchKernelGGL((k_real_cells<T, B>), grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm,           \
+                     w.cell_start, w.cell_atoms, w.qeff, w.qacc, w.rpart)
+  if (fp32) {
+    if (backward) RC(float, 1); else RC(float, 0);
+  } else {
+    if (backward) RC(double, 1); else RC(double, 0);
+  }
+#undef RC
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ QM-QM real space, self, background
 // P(a,b) = Qa Qb psi0 + (Qb mu_a - Qa mu_b).psi1 + (Qb th_a + Qa th_b):psi2 - 2 mu_a.psi2.mu_b,
 // E = 1/2 sum_{a != b} P + sum_a self_a - (pi/(2 a^2 V)) Qtot^2.  One block per
@@ -1439,25 +1685,27 @@ hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq
 }
 
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
-                       const double* Q, const double* mm_xyz, const double* mm_q, Work& w, hipStream_t s, int cap_qm,
-                       int cap_mm, int mm_tables) {
+                       const double* Q, const double* mu, const double* theta, const double* mm_xyz,
+                       const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
+                       int unit_eff) {
   const int nmax = max_nq > max_nm ? max_nq : max_nm;
   if (nmax > 0) {
     dim3 grid((nmax + 255) / 256, fa.n_frames);
-    hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, w.qm4, cap_qm, w.mm4, cap_mm,
-                       w.facc);
+    hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, mu, theta, w.qm4, cap_qm,
+                       w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  const int runs = (g.NX + kTabRun - 1) / kTabRun + (g.NY + kTabRun - 1) / kTabRun + (g.NZP + kTabRun - 1) / kTabRun;
   if (max_nm > 0 && mm_tables) {
-    const long n = (long)max_nm * g.R;
+    const long n = (long)max_nm * runs;
     dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
     hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, w.mm4, cap_mm, w.mm_tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (max_nq > 0) {
-    const long n = (long)max_nq * g.R;
+    const long n = (long)max_nq * runs;
     dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
     hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 1, w.qm4, cap_qm, w.qm_tab);
     hipError_t e = hipGetLastError();

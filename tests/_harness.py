@@ -36,12 +36,12 @@ def to_dev(sys, device="cuda"):
                 theta=t(sys.theta.reshape(-1, 6)), mm_pos=t(sys.mm_pos.reshape(-1, 3)), mm_q=t(sys.q))
 
 
-def make_plan(sys, qmqm=True, precision="fp64", plain=False, max_qm=None, max_mm=None, max_frames=1):
+def make_plan(sys, qmqm=True, precision="fp64", plain=False, max_qm=None, max_mm=None, max_frames=1, cell_list=True):
     from paper_2408_03273_amd.ewald import EwaldConfig, Plan
     cfg = EwaldConfig(box=tuple(sys.box), alpha=sys.alpha, rcut=sys.rcut, kmax=tuple(sys.kmax),
                       max_qm=max_qm if max_qm is not None else max(sys.nq, 1),
                       max_mm=max_mm if max_mm is not None else max(sys.nm, 1), max_frames=max_frames, qmqm=qmqm,
-                      precision=precision, plain=plain)
+                      precision=precision, plain=plain, cell_list=cell_list)
     return Plan(cfg)
 
 

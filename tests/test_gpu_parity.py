@@ -84,3 +84,14 @@ def test_backward_kernel_variants(variant, monkeypatch):
     monkeypatch.setenv("MPEWALD_BWD", variant)
     _check(wl.random_system(41, 11, 3333, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11)))
     _check(wl.random_system(42, 3, 700, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=5))
+
+
+@pytest.mark.parametrize("cell_list", [True, False])
+def test_real_space_cell_list_and_all_pairs(cell_list, monkeypatch):
+    """Real space over the cell list (>= 3 cells of edge >= rcut per axis) and
+    over all pairs give the same results; the 26.5 A box with rcut 8 has
+    3 cells per axis, the smallest the cell list accepts."""
+    monkeypatch.setenv("MPEWALD_CELLS", "1" if cell_list else "0")
+    s = wl.random_system(43, 14, 3100, box=(26.5, 30.0, 41.0), alpha=0.35, rcut=8.0, kmax=(8, 9, 12))
+    _check(s, cell_list=cell_list)
+    _check(wl.make_config(2), cell_list=cell_list)
