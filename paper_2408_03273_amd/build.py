@@ -24,8 +24,11 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     """Compile every source to an object, then link the shared library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    # MFMA accumulators in ordinary VGPRs (gfx950 allows either file): keeps
+    # loop-carried accumulators from being copied between AGPRs and VGPRs
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-             "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
+             "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=1", "-Wall", "-Wno-unused-function",
+             "-Wno-unknown-pragmas"]
     procs = []
     objs = []
     for src in SOURCES:

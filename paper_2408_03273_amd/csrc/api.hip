@@ -56,6 +56,7 @@ struct ewald_plan {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // second stream for the adjoint chain that runs beside the forward chain
   hipStream_t aux = nullptr, gaux = nullptr;
+  int serial = 0;  // run the adjoint chain on the caller's stream (isolated kernel timings)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
@@ -125,7 +126,9 @@ Grid make_grid(const ewald_params_t& p) {
   g.NZP = ((g.NZ + g.Zc - 1) / g.Zc) * g.Zc;
   g.R = g.NX + g.NY + g.NZP;
   g.NG = (g.NCOL + 15) / 16;
-  g.NKS = (g.NZ + 3) / 4;
+  g.ZKP = 16 * ((2 * g.mz + 15) / 16);
+  g.NT = g.ZKP / 16;
+  g.NK2 = 2 * ((g.mz + 3) / 4);
   g.alpha = p.alpha;
   g.rcut = p.rcut;
   return g;
@@ -142,7 +145,24 @@ ewald_status_t alloc(ewald_plan* pl, T** ptr, size_t count) {
   return EWALD_OK;
 }
 
-int fwd_kblocks(const Grid& g) { return ((g.NCOL + 63) / 64) * (g.NZP / g.Zc); }
+int fwd_kblocks(const ewald_plan* pl) { return fwd_col_groups(pl->g, pl->t); }
+
+// smallest forward block count per atom chunk over the kernel variants (sizes the partial-sum slots)
+int min_fwd_kblocks(const Grid& g) {
+  Tuning t{};
+  t.fwd_mode = 0;
+  int kb = fwd_col_groups(g, t);
+  t.fwd_mode = 1;
+  for (int ct : {1, 2, 4})
+    if (mfma_fwd_ct_ok(g, ct)) {
+      t.fwd_ct = ct;
+      kb = std::min(kb, fwd_col_groups(g, t));
+    }
+  return std::max(kb, 1);
+}
+
+// which MM phase tables the selected kernels read
+int mm_tables_for(const ewald_plan* pl) { return pl->t.fwd_mode == 0 ? 2 : 1; }
 
 
 void free_plan(ewald_plan* pl) {
@@ -167,10 +187,15 @@ void free_plan(ewald_plan* pl) {
 
 void set_describe(ewald_plan* pl) {
   char buf[256];
-  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-16col", "mfma-16col"};
-  snprintf(buf, sizeof(buf), "fwd=valu zc=%d nzp=%d blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", pl->g.Zc,
-           pl->g.NZP, pl->t.fwd_target, bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto",
-           pl->g.NX, pl->g.NY, pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
+  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-fold-16", "mfma-fold-32"};
+  char fwd[64];
+  if (pl->t.fwd_mode == 1)
+    snprintf(fwd, sizeof(fwd), "mfma-fold ct=%d nt=%d", pl->t.fwd_ct, pl->g.NT);
+  else
+    snprintf(fwd, sizeof(fwd), "valu zc=%d nzp=%d", pl->g.Zc, pl->g.NZP);
+  snprintf(buf, sizeof(buf), "fwd=%s blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", fwd, pl->t.fwd_target,
+           bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY,
+           pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
   pl->describe = buf;
 }
 
@@ -220,10 +245,18 @@ bool assign_cells(const ewald_plan* pl, FrameDev* frames, int n) {
 int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
   long total = 0;
   for (int n : nms) total += n;
-  const long kb = fwd_kblocks(pl->g);
-  long ac = (kb * total + pl->t.fwd_target - 1) / pl->t.fwd_target;
-  ac = ((ac + 255) / 256) * 256;
-  if (ac < 256) ac = 256;
+  const long kb = fwd_kblocks(pl);
+  long ac;
+  if (nms.size() == 1) {
+    // one frame: at most fwd_target blocks (so that a target equal to the
+    // resident block count gives one full round)
+    const long nac = std::max<long>(1, pl->t.fwd_target / kb);
+    ac = (total + nac - 1) / nac;
+  } else {
+    ac = (kb * total + pl->t.fwd_target - 1) / pl->t.fwd_target;
+  }
+  ac = ((ac + 63) / 64) * 64;
+  if (ac < 64) ac = 64;
   if (pl->t.a_chunk > 0) ac = pl->t.a_chunk;  // tuned value
   for (;;) {
     long slots = 0;
@@ -235,7 +268,7 @@ int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
 }
 
 int choose_kc(const ewald_plan* pl, long total_nm) {
-  const long per_block = pl->t.bwd_ilp >= 3 ? 64L : 256L * (pl->t.bwd_ilp == 1 ? 1 : 2);
+  const long per_block = pl->t.bwd_ilp >= 3 ? 64L * (pl->t.bwd_ilp - 2) : 256L * (pl->t.bwd_ilp == 1 ? 1 : 2);
   const long ablocks = std::max<long>(1, (total_nm + per_block - 1) / per_block);
   long kc = (kTargetBlocks + ablocks - 1) / ablocks;
   if (pl->t.kc > 0) kc = pl->t.kc;
@@ -373,7 +406,7 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   ewald_plan* pl = q.pl;
   Work& w = pl->w;
   const Grid& g = pl->g;
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, 1, 1);
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 1);
   if (st != EWALD_OK) return st;
   LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
   st = fork_to(pl, q.s, aux);
@@ -438,15 +471,32 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->t.zc = pl->g.Zc;
   pl->t.a_chunk = 0;
   pl->t.kc = 0;
-  pl->t.bwd_ilp = 3;
   pl->t.fwd_pf = 0;
-  pl->t.fwd_target = 8192;
+  // matrix-core kernels where instantiated (mz <= 32), else the VALU kernels
+  pl->t.fwd_mode = mfma_fwd_ok(pl->g) ? 1 : 0;
+  pl->t.fwd_ct = mfma_fwd_ct_ok(pl->g, 2) ? 2 : 1;
+  pl->t.fwd_target = pl->t.fwd_mode == 1 ? 1024 : 8192;
+  pl->t.bwd_ilp = mfma_bwd_ok(pl->g) ? 4 : 2;
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
-  // atoms per lane) or 3 (matrix cores); MPEWALD_FWD_PF = 0|1 (prefetch);
-  // MPEWALD_FWD_TARGET = forward block count target
+  // atoms per lane) or 3|4 (matrix cores, 16|32 atoms per wave); MPEWALD_FWD =
+  // 0|1 (VALU | matrix cores); MPEWALD_FWD_CT = 1|2|4 (matrix-core column
+  // tiles per wave); MPEWALD_FWD_PF = 0|1 (VALU prefetch); MPEWALD_FWD_TARGET =
+  // forward block count target
   if (const char* e = getenv("MPEWALD_BWD")) {
     const int v = atoi(e);
-    if (v >= 1 && v <= 3) pl->t.bwd_ilp = v;
+    if ((v >= 1 && v <= 2) || (v >= 3 && v <= 4 && mfma_bwd_ok(pl->g))) pl->t.bwd_ilp = v;
+  }
+  if (const char* e = getenv("MPEWALD_FWD")) {
+    const int v = atoi(e);
+    if (v == 0 || (v == 1 && mfma_fwd_ok(pl->g))) {
+      pl->t.fwd_mode = v;
+      pl->t.fwd_target = v == 1 ? 1024 : 8192;
+    }
+  }
+  if (const char* e = getenv("MPEWALD_SERIAL")) pl->serial = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_FWD_CT")) {
+    const int v = atoi(e);
+    if (mfma_fwd_ct_ok(pl->g, v)) pl->t.fwd_ct = v;
   }
   if (const char* e = getenv("MPEWALD_FWD_PF")) pl->t.fwd_pf = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_FWD_TARGET")) {
@@ -457,7 +507,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->cap_mm = std::max(p.max_mm, 1);
   pl->cap_frames = p.max_frames;
   pl->cap_cells = pl->cap_frames * (kMaxCellsPerAxis * kMaxCellsPerAxis * kMaxCellsPerAxis + 1);
-  pl->cap_slots = std::max(64, 4 * kTargetBlocks / std::max(1, fwd_kblocks(pl->g)) + 2 * pl->cap_frames);
+  pl->cap_slots = std::max(64, 4 * kTargetBlocks / min_fwd_kblocks(pl->g) + 2 * pl->cap_frames);
   pl->cap_kc = (int)std::max<long>(1, std::min<long>(16, (kTargetBlocks * 256L + pl->cap_mm - 1) / pl->cap_mm));
   const Grid& g = pl->g;
   Work& w = pl->w;
@@ -474,12 +524,14 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.mm4, 4 * cm);
   A(w.qm4, 4 * cq);
   A(w.mm_tab, cm * g.R);
+  A(w.mm_ztab, cm * g.ZKP);
   A(w.qm_tab, cq * g.R);
   A(w.sabc, cf * g.KF * 3);
   A(w.wk, cf * g.KF);
   A(w.smm, cf * g.KF);
   A(w.kw, cf * g.KF);
-  A(w.wfrag, cf * (size_t)g.NG * g.NKS * 64 * 2);
+  A(w.wfrag, cf * (size_t)g.NG * g.NK2 * 256);
+  A(w.wk0, cf * (size_t)g.NG * 16);
   A(w.spart, (size_t)pl->cap_slots * g.NZP * g.NCOL);
   A(w.fpart, (size_t)pl->cap_kc * cm * 4);
   A(w.rpart, cm * 4);
@@ -495,7 +547,10 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.atom_cell, cm);
 #undef A
   const double one = 1.0;
-  if (hipMemset(w.wfrag, 0, sizeof(double2) * cf * (size_t)g.NG * g.NKS * 64 * 2) != hipSuccess ||
+  // padding entries of the matrix-core operands are never written by the kernels: zero them once
+  if (hipMemset(w.wfrag, 0, sizeof(double) * cf * (size_t)g.NG * g.NK2 * 256) != hipSuccess ||
+      hipMemset(w.wk0, 0, sizeof(double2) * cf * (size_t)g.NG * 16) != hipSuccess ||
+      hipMemset(w.mm_ztab, 0, sizeof(double) * cm * g.ZKP) != hipSuccess ||
       hipMemcpy(w.one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     free_plan(pl);
     delete pl;
@@ -564,12 +619,12 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   if (ctx && !q.plain) {
     plan->t.kc = choose_kc(plan, n_mm);
     CtxView cv = ctx_view(plan->g, ctx, n_qm, n_mm);
-    st = seq_fwd_bwd(q, plan->aux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, cv.smm, plan->g.KF, energy, phi, efield,
+    st = seq_fwd_bwd(q, plan->serial ? s : plan->aux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, cv.smm, plan->g.KF, energy, phi, efield,
                      efgrad, cv.site, cv.gq, cv.gQ, cv.gmu, cv.gth, cv.gm, cv.gmq);
     plan->t = saved;
     return st;
   }
-  st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, q.plain ? 0 : 1, 0);
+  st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, q.plain ? 0 : mm_tables_for(plan), 0);
   if (st == EWALD_OK) {
     hipError_t e;
     {
@@ -708,10 +763,10 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   Work& w = plan->w;
   const Grid& g = plan->g;
   if (mode == EWALD_FWD_BWD) {
-    return seq_fwd_bwd(q, plan->gaux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
+    return seq_fwd_bwd(q, plan->serial ? s : plan->gaux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
                        w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
   }
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, 1, 0);
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 0);
   if (st != EWALD_OK) return st;
   LCHK(launch_sfac_qm(g, q.fa, max_nq, Q, mu, theta, w.qeff, nullptr, 0, w, s));
   LCHK(launch_sfac_mm(g, plan->t, q.fa, max_nm, plan->cap_mm, w, s));
@@ -894,15 +949,22 @@ bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
   const std::string pat = "\"key\": \"" + key + "\"";
   while (fgets(line, sizeof(line), fp)) {
     if (!strstr(line, pat.c_str())) continue;
-    int ft = 0, bw = 0, kc = 0;
+    int ft = 0, bw = 0, kc = 0, fm = 0, ct = 0;
     const char* p1 = strstr(line, "\"fwd_target\": ");
     const char* p2 = strstr(line, "\"bwd\": ");
     const char* p3 = strstr(line, "\"kc\": ");
-    if (p1 && p2 && p3 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 && sscanf(p2, "\"bwd\": %d", &bw) == 1 &&
-        sscanf(p3, "\"kc\": %d", &kc) == 1 && ft >= 64 && bw >= 1 && bw <= 3 && kc >= 0 && kc <= pl->cap_kc) {
+    const char* p4 = strstr(line, "\"fwd\": ");
+    const char* p5 = strstr(line, "\"ct\": ");
+    if (p1 && p2 && p3 && p4 && p5 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 &&
+        sscanf(p2, "\"bwd\": %d", &bw) == 1 && sscanf(p3, "\"kc\": %d", &kc) == 1 &&
+        sscanf(p4, "\"fwd\": %d", &fm) == 1 && sscanf(p5, "\"ct\": %d", &ct) == 1 && ft >= 64 &&
+        (bw == 1 || bw == 2 || ((bw == 3 || bw == 4) && mfma_bwd_ok(pl->g))) && kc >= 0 && kc <= pl->cap_kc &&
+        (fm == 0 || (fm == 1 && mfma_fwd_ok(pl->g) && mfma_fwd_ct_ok(pl->g, ct)))) {
       pl->t.fwd_target = ft;
       pl->t.bwd_ilp = bw;
       pl->t.kc = kc;
+      pl->t.fwd_mode = fm;
+      if (fm == 1) pl->t.fwd_ct = ct;
       found = true;
     }
   }
@@ -948,9 +1010,6 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ewald_status_t st = EWALD_OK;
   const Tuning saved = plan->t;
-  struct Cand {
-    int ft, bw, kc;
-  };
   double best_f = 1e30, best_b = 1e30;
   Tuning best = saved;
   std::string report;
@@ -990,7 +1049,7 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     q.fa.frames = nullptr;
     q.fa.f0 = make_frame(plan->p.box, nq, n_mm, 0, 0, 0);
     q.fa.n_frames = 1;
-    st = seq_begin(q, dqp, dQ, dmu, dth, dm, dq, 1, 1);
+    st = seq_begin(q, dqp, dQ, dmu, dth, dm, dq, 2, 1);
     if (st != EWALD_OK) goto done;
     TCHK(launch_sfac_qm(plan->g, q.fa, nq, dQ, dmu, dth, plan->w.qeff, nullptr, 1, plan->w, s));
     auto time_it = [&](auto&& launch) -> double {
@@ -1005,9 +1064,20 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
       return 1e3 * ms / 3.0;
     };
     char item[160];
-    for (int ft : {2048, 4096, 8192, 16384}) {
+    struct FwdCand {
+      int mode, ct, ft;
+    };
+    std::vector<FwdCand> fc;
+    if (mfma_fwd_ok(plan->g))
+      for (int ct : {1, 2, 4})
+        if (mfma_fwd_ct_ok(plan->g, ct))
+          for (int ft : {512, 768, 1024, 1536, 2304}) fc.push_back({1, ct, ft});
+    for (int ft : {4096, 8192, 16384}) fc.push_back({0, 0, ft});
+    for (const FwdCand& c : fc) {
       plan->t = saved;
-      plan->t.fwd_target = ft;
+      plan->t.fwd_mode = c.mode;
+      if (c.mode == 1) plan->t.fwd_ct = c.ct;
+      plan->t.fwd_target = c.ft;
       plan->t.a_chunk = 0;
       plan->t.a_chunk = choose_a_chunk(plan, {n_mm});
       const double us = time_it([&]() { return launch_sfac_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s); });
@@ -1015,15 +1085,20 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
         st = fail(EWALD_ERR_HIP, "autotune: forward launch failed");
         goto done;
       }
-      snprintf(item, sizeof(item), "%s\"fwd%d\": %.1f", report.empty() ? "" : ", ", ft, us);
+      if (c.mode == 1)
+        snprintf(item, sizeof(item), "%s\"fwd_mfma_ct%d_%d\": %.1f", report.empty() ? "" : ", ", c.ct, c.ft, us);
+      else
+        snprintf(item, sizeof(item), "%s\"fwd_valu_%d\": %.1f", report.empty() ? "" : ", ", c.ft, us);
       report += item;
       if (us < best_f) {
         best_f = us;
-        best.fwd_target = ft;
+        best.fwd_mode = c.mode;
+        best.fwd_ct = c.mode == 1 ? c.ct : saved.fwd_ct;
+        best.fwd_target = c.ft;
       }
     }
-    for (int bw : {2, 3}) {
-      if (bw == 3 && !force_mm_mfma_has_nks(plan->g.NKS)) continue;
+    for (int bw : {2, 3, 4}) {
+      if (bw >= 3 && !mfma_bwd_ok(plan->g)) continue;
       for (int kc : {0, 1, 2, 4, 8, 16}) {
         if (kc > plan->cap_kc) continue;
         plan->t = saved;
@@ -1060,8 +1135,11 @@ done:
   if (cache_path) {
     FILE* fp = fopen(cache_path, "a");
     if (fp) {
-      fprintf(fp, "{\"key\": \"%s\", \"fwd_target\": %d, \"bwd\": %d, \"kc\": %d, \"times_us\": {%s}}\n", key.c_str(),
-              plan->t.fwd_target, plan->t.bwd_ilp, plan->t.kc, report.c_str());
+      fprintf(fp,
+              "{\"key\": \"%s\", \"fwd\": %d, \"ct\": %d, \"fwd_target\": %d, \"bwd\": %d, \"kc\": %d, "
+              "\"times_us\": {%s}}\n",
+              key.c_str(), plan->t.fwd_mode, plan->t.fwd_ct, plan->t.fwd_target, plan->t.bwd_ilp, plan->t.kc,
+              report.c_str());
       fclose(fp);
     }
   }

@@ -40,8 +40,10 @@ struct Grid {
   int Zc;           // nz chunk of the forward kernel
   int NZP;          // nz padded to a multiple of Zc
   int R;            // complex entries per atom in the phase tables: NX + NY + NZP
-  int NG;           // 16-column groups of the matrix-core backward kernel
-  int NKS;          // nz steps of 4 of the matrix-core backward kernel
+  int NG;           // 16-column tiles of the matrix-core kernels
+  int ZKP;          // real z-phase table row: cos(p kz0 z), p=1..mz, then sin, zero padded to a multiple of 16
+  int NT;           // ZKP/16: 16-wide z tiles of the matrix-core forward kernel
+  int NK2;          // K steps of 4 of the matrix-core adjoint kernel: 2*ceil(mz/4) (even, zero padded)
   double alpha, rcut;
 };
 
@@ -83,12 +85,14 @@ struct Work {
   double* mm4;        // [4][cap_mm]  wrapped x,y,z and q
   double* qm4;        // [4][cap_qm]  wrapped x,y,z and Q
   double2* mm_tab;    // [cap_mm][R]  e^{i 2 pi n x/L}: x (n=0..mx), y (-my..my), z (-mz..mz, zero padded)
+  double* mm_ztab;    // [cap_mm][ZKP] cos(2 pi p z/Lz), p=1..mz | sin(2 pi p z/Lz), p=1..mz | zeros
   double2* qm_tab;    // [cap_qm][R]
   double2* sabc;      // [cap_frames][KF][3]  A, B, C of the QM multipoles
   double2* wk;        // [cap_frames][KF]     backward weights (8 pi/V) g(k) S'_QM(k)
   double2* smm;       // [cap_frames][KF]     S_MM for batched calls
   double* kw;         // [cap_frames][KF]     (8 pi/V) e^{-k^2/4a^2}/k^2 on the half space, else 0
-  double2* wfrag;     // [cap_frames][NG][NKS][64][2] W and nz*W in matrix-core fragment order (zero padded)
+  double* wfrag;      // [cap_frames][NG][NK2][4][64] folded adjoint weights in matrix-core B order (zero padded)
+  double2* wk0;       // [cap_frames][NG*16]  W at nz = 0 per column (zero for padding columns)
   double2* spart;     // [cap_slots][NZP][NCOL] partial S_MM sums
   double* fpart;      // [cap_kc][cap_mm][4]  partial MM gradient data (phi, dx, dy, dz)
   double* rpart;      // [cap_mm][4]          real-space MM gradient data
@@ -108,19 +112,31 @@ static constexpr int kMaxCellsPerAxis = 16;
 
 // Tunables of the two hot kernels.
 struct Tuning {
-  int zc;         // forward nz chunk (template instance)
+  int zc;         // VALU forward nz chunk (template instance)
   int a_chunk;    // forward atoms per block
   int kc;         // backward column chunks
-  int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3 matrix cores
-  int fwd_pf;     // forward kernel prefetches the next atom's factors
+  int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3|4 matrix cores (16|32 atoms per wave)
+  int fwd_pf;     // VALU forward kernel prefetches the next atom's factors
   int fwd_target; // forward blocks the atom chunking aims for
+  int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
+  int fwd_ct;     // matrix-core forward: 16-column tiles per wave
 };
+
+// matrix-core kernels are instantiated for mz <= 32
+inline bool mfma_fwd_ok(const Grid& g) { return g.NT >= 1 && g.NT <= 4; }
+inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
+// the forward tiles per wave are limited by the LDS of the block reduction
+inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
+inline int fwd_col_groups(const Grid& g, const Tuning& t) {
+  return t.fwd_mode == 1 ? (g.NG + t.fwd_ct - 1) / t.fwd_ct : ((g.NCOL + 63) / 64) * (g.NZP / g.Zc);
+}
 
 // ---------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error; all are asynchronous.
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 // wrap positions, clear the QM accumulators, sum the charges, build the phase
-// tables; unit_eff also sets the effective moments for an upstream gradient of 1
+// tables (mm_tables: 0 none, 1 x/y complex and real z tables, 2 also complex z);
+// unit_eff also sets the effective moments for an upstream gradient of 1
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mu, const double* theta, const double* mm_xyz,
                        const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
@@ -162,7 +178,6 @@ hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* sit
 hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq, const double* gQ, const double* gmu,
                               const double* gth, const double* gm, const double* gmq, double* o_q, double* o_Q,
                               double* o_mu, double* o_th, double* o_m, double* o_mq, hipStream_t s);
-bool force_mm_mfma_has_nks(int nks);
 // forward kernel instances available for the nz chunk
 bool sfac_mm_has_zc(int zc);
 int pick_zc(int NZ);

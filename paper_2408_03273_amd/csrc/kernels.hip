@@ -144,52 +144,74 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
 
 // Per-atom phase tables.  Row layout (complex):
 // [e^{i 2pi n x/Lx}, n = 0..mx][e^{i 2pi n y/Ly}, n = -my..my][e^{i 2pi n z/Lz}, n = -mz..mz, then zeros]
+// and, for the MM atoms, a real z row [cos(2pi p z/Lz), p = 1..mz][sin(2pi p z/Lz), p = 1..mz]
+// (the padding after it is zeroed once at set-up).
 // One thread per run of kTabRun entries of one axis: the first entry from
 // sincospi, the rest by multiplying with e^{i 2pi x/L} (at most kTabRun-1
 // rounding steps from an exact start).
 static constexpr int kTabRun = 8;
 
-__global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, const double* __restrict__ pos4,
-                                                  int cap, double2* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, int with_ez,
+                                                  const double* __restrict__ pos4, int cap, double2* __restrict__ tab,
+                                                  double* __restrict__ ztab) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
   const int off = qm_side ? fr.qoff : fr.moff;
   const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
-            rz = (g.NZP + kTabRun - 1) / kTabRun;
-  const int runs = rx + ry + rz;
+            rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
+  const int runs = rx + ry + rz + rr;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)n_atoms * runs) return;
   const int a = (int)(e / runs), t = (int)(e - (long)a * runs);
   const int row = off + a;
-  int axis, first, count, n0, dst;
+  int axis, first, count, n0, dst, limit;
   if (t < rx) {
     axis = 0;
     first = t * kTabRun;
     count = min(kTabRun, g.NX - first);
     n0 = first;
     dst = first;
+    limit = count;
   } else if (t < rx + ry) {
     axis = 1;
     first = (t - rx) * kTabRun;
     count = min(kTabRun, g.NY - first);
     n0 = first - g.my;
     dst = g.NX + first;
-  } else {
+    limit = count;
+  } else if (t < rx + ry + rz) {
     axis = 2;
     first = (t - rx - ry) * kTabRun;
     count = min(kTabRun, g.NZP - first);
     n0 = first - g.mz;
     dst = g.NX + g.NY + first;
+    limit = g.NZ - first;  // z entries past NZ are padding
+  } else {
+    axis = 3;  // real z row, p = first+1 ..
+    first = (t - rx - ry - rz) * kTabRun;
+    count = min(kTabRun, g.mz - first);
+    n0 = first + 1;
+    dst = first;
+    limit = count;
   }
-  const double x = pos4[(size_t)axis * cap + row] / fr.box[axis];
+  const int ax = axis == 3 ? 2 : axis;
+  const double x = pos4[(size_t)ax * cap + row] / fr.box[ax];
   double s0, c0, s1, c1;
   sincospi(2.0 * (double)n0 * x, &s0, &c0);
   sincospi(2.0 * x, &s1, &c1);
   double2 v = make_double2(c0, s0);
   const double2 step = make_double2(c1, s1);
+  if (axis == 3) {
+    double* __restrict__ o = ztab + (size_t)row * g.ZKP + dst;
+    for (int u = 0; u < count; u++) {
+      o[u] = v.x;
+      o[g.mz + u] = v.y;
+      v = cmul(v, step);
+    }
+    return;
+  }
   double2* __restrict__ o = tab + (size_t)row * g.R + dst;
-  const int limit = axis == 2 ? g.NZ - first : count;  // z entries past NZ are padding
   for (int u = 0; u < count; u++) {
     o[u] = u < limit ? v : make_double2(0.0, 0.0);
     v = cmul(v, step);
@@ -199,56 +221,86 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
 // ------------------------------------------------------------------ QM structure factors
 // A(k) = sum_j Q_j e_j, B(k) = sum_j i (k.mu_j) e_j, C(k) = sum_j -1/2 (k.theta_j.k) e_j,
 // e_j = e^{i k.R_j}  (SI, multipolar long-range tensors contracted with the moments).
-// With with_w, also W(k) = (8 pi/V) g(k) S'(k) for the effective moments of the backward pass.
+// With with_w, also W(k) = (8 pi/V) g(k) S'(k) for the effective moments of the backward pass,
+// and its folded form for the matrix-core adjoint: for column c and p = |nz| > 0,
+// W+ = W(c, p), W- = W(c, -p), Ap = W+ + W-, Am = W+ - W-, so that
+//   sum_nz W(c,nz) e^{-i nz kz0 z} = W(c,0) + sum_p [Ap cos(p kz0 z) - i Am sin(p kz0 z)]
+//   sum_nz nz W(c,nz) e^{-i nz kz0 z} = sum_p p [Am cos(p kz0 z) - i Ap sin(p kz0 z)].
+// Each thread owns one column and one p and evaluates both k = (nx, ny, +p) and (nx, ny, -p).
+DEV void qm_terms(double (&v)[8], double2 e, double Qj, double kmu, double kthk) {
+  v[0] += Qj * e.x;
+  v[1] += Qj * e.y;
+  v[2] -= kmu * e.y;
+  v[3] += kmu * e.x;
+  v[4] -= 0.5 * kthk * e.x;
+  v[5] -= 0.5 * kthk * e.y;
+}
+
 __global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const double* __restrict__ Q,
                                                  const double* __restrict__ mu, const double* __restrict__ theta,
                                                  const double* __restrict__ qeff, const double2* __restrict__ qtab,
                                                  int with_w, double2* __restrict__ sabc, double2* __restrict__ wk,
-                                                 double* __restrict__ kw, double2* __restrict__ wfrag) {
+                                                 double* __restrict__ kw, double* __restrict__ wfrag,
+                                                 double2* __restrict__ wk0) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
-  const int k = blockIdx.x * 64 + lane;
-  const int kc = min(k, g.KF - 1);
-  const int col = kc / g.NZ, iz = kc - col * g.NZ;
+  const int NP = g.mz + 1;
+  const int t = blockIdx.x * 64 + lane;
+  const int tc = min(t, g.NCOL * NP - 1);
+  const int col = tc / NP, p = tc - col * NP;
   const int nx = col / g.NY, iy = col - nx * g.NY;
-  const int ny = iy - g.my, nz = iz - g.mz;
+  const int ny = iy - g.my;
   const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
-               kz = 2.0 * kPi * nz * fr.inv_box[2];
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // A, B, C, S' (re, im)
+               kz = 2.0 * kPi * p * fr.inv_box[2];
+  double vp[8] = {0, 0, 0, 0, 0, 0, 0, 0}, vm[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // A, B, C, S' at +p and -p
   for (int j = wave; j < fr.nq; j += 4) {
     const int r = fr.qoff + j;
     const double2* row = qtab + (size_t)r * g.R;
-    const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
+    const double2 exy = cmul(row[nx], row[g.NX + iy]);
+    const double2 ez = row[g.NX + g.NY + g.mz + p];
+    const double2 ep = cmul(exy, ez), em = cmul(exy, cconj(ez));
     const double* m = mu + 3 * (size_t)r;
-    const double* t = theta + 6 * (size_t)r;
-    const double kmu = kx * m[0] + ky * m[1] + kz * m[2];
-    const double kthk = kx * kx * t[0] + ky * ky * t[3] + kz * kz * t[5] +
-                        2.0 * (kx * ky * t[1] + kx * kz * t[2] + ky * kz * t[4]);
+    const double* th = theta + 6 * (size_t)r;
+    const double kmu_xy = kx * m[0] + ky * m[1], kmu_z = kz * m[2];
+    const double kthk_xy = kx * kx * th[0] + ky * ky * th[3] + 2.0 * kx * ky * th[1];
+    const double kthk_c = 2.0 * kz * (kx * th[2] + ky * th[4]), kthk_zz = kz * kz * th[5];
     const double Qj = Q[r];
-    v[0] += Qj * e.x;
-    v[1] += Qj * e.y;
-    v[2] -= kmu * e.y;
-    v[3] += kmu * e.x;
-    v[4] -= 0.5 * kthk * e.x;
-    v[5] -= 0.5 * kthk * e.y;
+    qm_terms(vp, ep, Qj, kmu_xy + kmu_z, kthk_xy + kthk_c + kthk_zz);
+    qm_terms(vm, em, Qj, kmu_xy - kmu_z, kthk_xy - kthk_c + kthk_zz);
     if (with_w) {
       const double* qe = qeff + 10 * (size_t)r;
-      const double kmu2 = kx * qe[1] + ky * qe[2] + kz * qe[3];
-      const double kthk2 = kx * kx * qe[4] + ky * ky * qe[7] + kz * kz * qe[9] +
-                           2.0 * (kx * ky * qe[5] + kx * kz * qe[6] + ky * kz * qe[8]);
-      const double wr = qe[0] - 0.5 * kthk2, wi = kmu2;
-      v[6] += wr * e.x - wi * e.y;
-      v[7] += wr * e.y + wi * e.x;
+      const double emu_xy = kx * qe[1] + ky * qe[2], emu_z = kz * qe[3];
+      const double eth_xy = kx * kx * qe[4] + ky * ky * qe[7] + 2.0 * kx * ky * qe[5];
+      const double eth_c = 2.0 * kz * (kx * qe[6] + ky * qe[8]), eth_zz = kz * kz * qe[9];
+      const double wrp = qe[0] - 0.5 * (eth_xy + eth_c + eth_zz), wip = emu_xy + emu_z;
+      const double wrm = qe[0] - 0.5 * (eth_xy - eth_c + eth_zz), wim = emu_xy - emu_z;
+      vp[6] += wrp * ep.x - wip * ep.y;
+      vp[7] += wrp * ep.y + wip * ep.x;
+      vm[6] += wrm * em.x - wim * em.y;
+      vm[7] += wrm * em.y + wim * em.x;
     }
   }
-  __shared__ double red[3][8][64];
+  __shared__ double red[3][16][64];
   if (wave > 0)
-    for (int t = 0; t < 8; t++) red[wave - 1][t][lane] = v[t];
+    for (int u = 0; u < 8; u++) {
+      red[wave - 1][u][lane] = vp[u];
+      red[wave - 1][8 + u][lane] = vm[u];
+    }
   __syncthreads();
-  if (wave == 0 && k < g.KF) {
-    for (int t = 0; t < 8; t++) v[t] += red[0][t][lane] + red[1][t][lane] + red[2][t][lane];
+  if (wave != 0 || t >= g.NCOL * NP) return;
+  for (int u = 0; u < 8; u++) {
+    vp[u] += red[0][u][lane] + red[1][u][lane] + red[2][u][lane];
+    vm[u] += red[0][8 + u][lane] + red[1][8 + u][lane] + red[2][8 + u][lane];
+  }
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  double2 W[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  for (int sg = 0; sg < 2; sg++) {
+    if (sg == 1 && p == 0) break;
+    const int nz = sg ? -p : p;
+    const double* v = sg ? vm : vp;
+    const int k = col * g.NZ + g.mz + nz;
     double2* o = sabc + ((size_t)f * g.KF + k) * 3;
     o[0] = make_double2(v[0], v[1]);
     o[1] = make_double2(v[2], v[3]);
@@ -256,21 +308,35 @@ __global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const doub
     double wgt = 0.0;
     if (in_half_space(nx, ny, nz)) {
       const double k2 = kx * kx + ky * ky + kz * kz;
-      const double V = fr.box[0] * fr.box[1] * fr.box[2];
       wgt = 8.0 * kPi / V * exp(-k2 / (4.0 * g.alpha * g.alpha)) / k2;
     }
     kw[(size_t)f * g.KF + k] = wgt;
     if (with_w) {
-      const double2 W = make_double2(wgt * v[6], wgt * v[7]);
-      wk[(size_t)f * g.KF + k] = W;
-      if (wfrag) {
-        // fragment-major copy: [group][step][lane], lane = column%16 + 16 (nz%4)
-        const int grp = col >> 4, s4 = iz >> 2;
-        const size_t fi = (((size_t)f * g.NG + grp) * g.NKS + s4) * 64 + (col & 15) + 16 * (iz & 3);
-        const double fz = (double)nz;
-        wfrag[2 * fi] = W;
-        wfrag[2 * fi + 1] = make_double2(fz * W.x, fz * W.y);
-      }
+      W[sg] = make_double2(wgt * v[6], wgt * v[7]);
+      wk[(size_t)f * g.KF + k] = W[sg];
+    }
+  }
+  if (with_w && wfrag) {
+    if (p == 0) {
+      wk0[(size_t)f * g.NG * 16 + col] = W[0];
+    } else {
+      const double2 Ap = make_double2(W[0].x + W[1].x, W[0].y + W[1].y);
+      const double2 Am = make_double2(W[0].x - W[1].x, W[0].y - W[1].y);
+      const double fp = (double)p;
+      double* base = wfrag + ((size_t)f * g.NG + (col >> 4)) * g.NK2 * 256 + (col & 15);
+      // K row p-1 multiplies cos(p kz0 z), K row mz+p-1 multiplies sin(p kz0 z);
+      // the four B matrices give Re P, Im P, Re Pz, Im Pz
+      double* o = base + (size_t)((p - 1) >> 2) * 256 + 16 * ((p - 1) & 3);
+      o[0] = Ap.x;
+      o[64] = Ap.y;
+      o[128] = fp * Am.x;
+      o[192] = fp * Am.y;
+      const int js = g.mz + p - 1;
+      o = base + (size_t)(js >> 2) * 256 + 16 * (js & 3);
+      o[0] = Am.y;
+      o[64] = -Am.x;
+      o[128] = fp * Ap.y;
+      o[192] = -fp * Ap.x;
     }
   }
 }
@@ -280,11 +346,17 @@ hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const d
                           hipStream_t s) {
   (void)max_nq;
   (void)gE;
-  dim3 grid((g.KF + 63) / 64, fa.n_frames);
+  dim3 grid((g.NCOL * (g.mz + 1) + 63) / 64, fa.n_frames);
   hipLaunchKernelGGL(k_sfac_qm, grid, dim3(256), 0, s, g, fa, Q, mu, theta, qeff, w.qm_tab, with_w, w.sabc, w.wk,
-                     w.kw, w.wfrag);
+                     w.kw, w.wfrag, w.wk0);
   return hipGetLastError();
 }
+
+// v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16).  A[i][k] sits in lane
+// i + 16k, B[k][j] in lane j + 16k, and element r of D in lane l is D[l/16 + 4r][l%16].
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+DEV v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 // ------------------------------------------------------------------ MM structure factor (forward hot loop)
 // S_MM(k) = sum_i q_i e^{i k.R_i}.  Each lane owns one column (nx,ny) and Z
@@ -440,8 +512,12 @@ static hipError_t launch_sfac_mm_z(const Grid& g, const Tuning& t, const FrameAr
   return hipGetLastError();
 }
 
+static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                                      Work& w, hipStream_t s);
+
 hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                           hipStream_t s) {
+  if (t.fwd_mode == 1) return launch_sfac_mm_mfma(g, t, fa, max_nm, cap_mm, w, s);
   switch (g.Zc) {
     case 7: return launch_sfac_mm_z<7>(g, t, fa, max_nm, cap_mm, w, s);
     case 8: return launch_sfac_mm_z<8>(g, t, fa, max_nm, cap_mm, w, s);
@@ -455,6 +531,191 @@ hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, in
     case 25: return launch_sfac_mm_z<25>(g, t, fa, max_nm, cap_mm, w, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ------------------------------------------------------------------ matrix-core forward
+// The z phases of +p and -p are complex conjugates, so with
+//   C_i(c) = q_i e^{i(kx x_i + ky y_i)}                   (column c = (nx, ny))
+//   U(c,p) = sum_i C_i(c) cos(p kz0 z_i),  V(c,p) = sum_i C_i(c) sin(p kz0 z_i)
+// the structure factor is S(c, +p) = U + iV, S(c, -p) = U - iV, S(c, 0) = sum_i C_i(c).
+// U and V are one real contraction over atoms: [Re C; Im C] (columns x atoms)
+// times the real z table (atoms x [cos | sin]), done on the FP64 matrix cores
+// with 4 atoms per K step.  A block of four waves covers CT 16-column tiles
+// and one atom chunk (the waves interleave its K steps); the waves are summed
+// through LDS and the block writes one partial S per k in k order.
+template <int CT, int NT>
+__global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
+                                                      const double* __restrict__ mm4, int cap_mm,
+                                                      const double2* __restrict__ tab,
+                                                      const double* __restrict__ ztab,
+                                                      double2* __restrict__ spart) {
+  static_assert(CT * NT <= 6, "LDS budget of the block reduction");
+  constexpr int NACC = CT * NT * 8;  // accumulator doubles per lane
+  __shared__ double red[2][NACC * 64];
+  __shared__ double s0red[4][CT][2][16];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int gc = blockIdx.x % ngc, ac = blockIdx.x / ngc;
+  if (ac >= nac) return;
+  const int a0 = ac * a_chunk;
+  if (a0 >= fr.nm) return;  // uniform over the block
+  const int a1 = min(fr.nm, a0 + a_chunk);
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  int cx[CT], cy[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) {
+    const int col = min((gc * CT + ct) * 16 + li, g.NCOL - 1);
+    const int nx = col / g.NY;
+    cx[ct] = nx;
+    cy[ct] = g.NX + col - nx * g.NY;
+  }
+  v4d dr[CT][NT], di[CT][NT];
+  double s0r[CT], s0i[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) {
+    s0r[ct] = s0i[ct] = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+      dr[ct][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+      di[ct][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+  const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
+  const double2* __restrict__ tb = tab + (size_t)fr.moff * g.R;
+  const double* __restrict__ zb = ztab + (size_t)fr.moff * g.ZKP + li;
+  // K step: atoms a .. a+3, lane atom a + lk (row k of B and column k of A)
+  for (int a = a0 + 4 * wave; a < a1; a += 16) {
+    const int ai = a + lk;
+    const bool ok = ai < a1;
+    const int ar = ok ? ai : a0;
+    // unconditional load of a valid row, then a select: no branch inside the loop
+    const double q = qv[ar] * (ok ? 1.0 : 0.0);
+    const double2* __restrict__ row = tb + (size_t)ar * g.R;
+    double bz[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) bz[nt] = zb[(size_t)ar * g.ZKP + nt * 16];
+    double2 ex[CT], ey[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      ex[ct] = row[cx[ct]];
+      ey[ct] = row[cy[ct]];
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      const double cr = q * (ex[ct].x * ey[ct].x - ex[ct].y * ey[ct].y);
+      const double ci = q * (ex[ct].x * ey[ct].y + ex[ct].y * ey[ct].x);
+      s0r[ct] += cr;
+      s0i[ct] += ci;
+#pragma unroll
+      for (int nt = 0; nt < NT; nt++) {
+        dr[ct][nt] = mfma4(cr, bz[nt], dr[ct][nt]);
+        di[ct][nt] = mfma4(ci, bz[nt], di[ct][nt]);
+      }
+    }
+  }
+  // nz = 0: sum over the four atom rows of the wave, then over the waves
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) {
+    s0r[ct] += __shfl_xor(s0r[ct], 16, 64);
+    s0r[ct] += __shfl_xor(s0r[ct], 32, 64);
+    s0i[ct] += __shfl_xor(s0i[ct], 16, 64);
+    s0i[ct] += __shfl_xor(s0i[ct], 32, 64);
+    if (lk == 0) {
+      s0red[wave][ct][0][li] = s0r[ct];
+      s0red[wave][ct][1][li] = s0i[ct];
+    }
+  }
+  // waves 3,2 -> 1,0 -> 0
+  auto store = [&](double* dst) {
+    int idx = 0;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          dst[(idx++) * 64 + lane] = dr[ct][nt][r];
+          dst[(idx++) * 64 + lane] = di[ct][nt][r];
+        }
+  };
+  auto add = [&](const double* src) {
+    int idx = 0;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          dr[ct][nt][r] += src[(idx++) * 64 + lane];
+          di[ct][nt][r] += src[(idx++) * 64 + lane];
+        }
+  };
+  if (wave >= 2) store(red[wave - 2]);
+  __syncthreads();
+  if (wave < 2) add(red[wave]);
+  __syncthreads();
+  if (wave == 1) store(red[0]);
+  __syncthreads();
+  constexpr int NCL = CT * 16, NJ = NT * 16;
+  double* T = red[1];  // T[0][c][j] = U/V real parts, T[1][c][j] = imaginary parts
+  if (wave == 0) {
+    add(red[0]);
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int c = ct * 16 + lk + 4 * r, j = nt * 16 + li;
+          T[c * NJ + j] = dr[ct][nt][r];
+          T[(NCL + c) * NJ + j] = di[ct][nt][r];
+        }
+  }
+  __syncthreads();
+  double2* __restrict__ out = spart + (size_t)(fr.slot_base + ac) * g.NZP * g.NCOL;
+  for (int e = threadIdx.x; e < NCL * g.NZ; e += 256) {
+    const int c = e / g.NZ, iz = e - c * g.NZ;
+    const int col = gc * NCL + c;
+    if (col >= g.NCOL) break;
+    const int nz = iz - g.mz;
+    double2 S;
+    if (nz == 0) {
+      const int ct = c >> 4, cl = c & 15;
+      S.x = ((s0red[0][ct][0][cl] + s0red[1][ct][0][cl]) + s0red[2][ct][0][cl]) + s0red[3][ct][0][cl];
+      S.y = ((s0red[0][ct][1][cl] + s0red[1][ct][1][cl]) + s0red[2][ct][1][cl]) + s0red[3][ct][1][cl];
+    } else {
+      const int pj = (nz > 0 ? nz : -nz) - 1;
+      const double ur = T[c * NJ + pj], ui = T[(NCL + c) * NJ + pj];
+      const double vr = T[c * NJ + g.mz + pj], vi = T[(NCL + c) * NJ + g.mz + pj];
+      S = nz > 0 ? make_double2(ur - vi, ui + vr) : make_double2(ur + vi, ui - vr);
+    }
+    out[(size_t)col * g.NZ + iz] = S;
+  }
+}
+
+template <int CT, int NT>
+static void launch_sfac_mm_mfma_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int a_chunk, int ngc,
+                                  int nac, int cap_mm, Work& w) {
+  hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, w.mm4, cap_mm,
+                     w.mm_tab, w.mm_ztab, w.spart);
+}
+
+static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                                      Work& w, hipStream_t s) {
+  const int ngc = fwd_col_groups(g, t);
+  const int nac = (max_nm + t.a_chunk - 1) / t.a_chunk;
+  if (nac == 0) return hipSuccess;
+  dim3 grid(ngc * nac, 1, fa.n_frames);
+#define SF(C, N)                                                                 \
+  if (t.fwd_ct == C && g.NT == N) {                                              \
+    launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, cap_mm, w); \
+    return hipGetLastError();                                                    \
+  }
+  SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(1, 3) SF(2, 3) SF(1, 4)
+#undef SF
+  return hipErrorInvalidValue;
 }
 
 // Reference GPU path: one thread per k, sincos of k.R for every atom.
@@ -491,26 +752,28 @@ hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, W
 // Sum the partial structure factors, store S_MM in k order, and accumulate
 // the reciprocal energies (8 pi/V) g Re[S_QM conj S_MM] and the order-2
 // truncated QM-QM term (4 pi/V) g (|A|^2 + 2Re A*B + 2Re A*C + |B|^2).
-__global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain,
+// Partial sums are in k order (kmajor, matrix-core forward) or nz-major
+// (VALU and plain forward).
+__global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain, int kmajor,
                                                     const double2* __restrict__ spart,
                                                     const double2* __restrict__ sabc,
                                                     const double* __restrict__ kw, double2* __restrict__ smm,
                                                     size_t smm_stride, double* __restrict__ facc) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.x * 256 + threadIdx.x;
   double v[2] = {0.0, 0.0};
-  if (e < g.NZ * g.NCOL) {
-    const int iz = e / g.NCOL, col = e - iz * g.NCOL;
+  if (k < g.KF) {
+    const int col = k / g.NZ, iz = k - col * g.NZ;
     const int nslots = plain ? 1 : (fr.nm + a_chunk - 1) / a_chunk;
+    const size_t idx = kmajor ? (size_t)k : (size_t)iz * g.NCOL + col;
     double sr = 0.0, si = 0.0;
     for (int sl = 0; sl < nslots; sl++) {
-      const double2 p = spart[(size_t)(fr.slot_base + sl) * g.NZP * g.NCOL + (size_t)iz * g.NCOL + col];
+      const double2 p = spart[(size_t)(fr.slot_base + sl) * g.NZP * g.NCOL + idx];
       sr += p.x;
       si += p.y;
     }
     if (plain && fr.nm == 0) sr = si = 0.0;
-    const int k = col * g.NZ + iz;
     smm[(size_t)f * smm_stride + k] = make_double2(sr, si);
     const double wgt = kw[(size_t)f * g.KF + k];
     if (wgt != 0.0) {
@@ -533,9 +796,10 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
 
 hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
                              size_t smm_frame_stride, Work& w, hipStream_t s) {
-  dim3 grid((g.NZ * g.NCOL + 255) / 256, fa.n_frames);
-  hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, w.spart, w.sabc, w.kw, smm_out,
-                     smm_frame_stride, w.facc);
+  dim3 grid((g.KF + 255) / 256, fa.n_frames);
+  const int kmajor = !plain && t.fwd_mode == 1;
+  hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, kmajor, w.spart, w.sabc, w.kw,
+                     smm_out, smm_frame_stride, w.facc);
   return hipGetLastError();
 }
 
@@ -573,66 +837,76 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
     const double* th = theta + 6 * (size_t)r;
     u0 = th[0]; u1 = th[1]; u2 = th[2]; u3 = th[3]; u4 = th[4]; u5 = th[5];
   }
-  for (int k = blockIdx.y * 256 + threadIdx.x; k < g.KF; k += n_pc * 256) {
-    const int col = k / g.NZ, iz = k - col * g.NZ;
+  // thread item = (column, p = |nz|): k = (nx, ny, +p) and (nx, ny, -p) share e^{i(kx x + ky y)}
+  const int NP = g.mz + 1;
+  const int n_items = g.NCOL * NP;
+  for (int t = blockIdx.y * 256 + threadIdx.x; t < n_items; t += n_pc * 256) {
+    const int col = t / NP, p = t - col * NP;
     const int nx = col / g.NY, iy = col - nx * g.NY;
-    const int ny = iy - g.my, nz = iz - g.mz;
-    const double w = kw[(size_t)f * g.KF + k];
-    if (w == 0.0) continue;
-    const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
-                 kz = 2.0 * kPi * nz * fr.inv_box[2];
-    const double2 e = cmul(cmul(row[nx], row[g.NX + iy]), row[g.NX + g.NY + iz]);
-    const double2 S = smm[(size_t)f * smm_stride + k];
-    // Y = e conj(S)
-    const double yr = e.x * S.x + e.y * S.y, yi = e.y * S.x - e.x * S.y;
-    if (!BWD) {
-      acc[0] += w * yr;
-      acc[1] -= w * kx * yi;
-      acc[2] -= w * ky * yi;
-      acc[3] -= w * kz * yi;
-      const double h = -0.5 * w * yr;
-      acc[4] += h * kx * kx;
-      acc[5] += h * kx * ky;
-      acc[6] += h * kx * kz;
-      acc[7] += h * ky * ky;
-      acc[8] += h * ky * kz;
-      acc[9] += h * kz * kz;
-    } else {
-      // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
-      const double kthk = kx * kx * t0 + ky * ky * t3 + kz * kz * t5 + 2.0 * (kx * ky * t1 + kx * kz * t2 + ky * kz * t4);
-      const double wr = Qe - 0.5 * kthk, wi = kx * m0 + ky * m1 + kz * m2;
-      const double gr = -(wr * yi + wi * yr);
-      acc[0] += w * kx * gr;
-      acc[1] += w * ky * gr;
-      acc[2] += w * kz * gr;
-      if (qmqm) {
-        const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
-        const double2 A = abc[0], B = abc[1], C = abc[2];
-        const double kmu = kx * o0 + ky * o1 + kz * o2;
-        const double kthko = kx * kx * u0 + ky * ky * u3 + kz * kz * u5 + 2.0 * (kx * ky * u1 + kx * kz * u2 + ky * kz * u4);
-        // a_j = Q e, b_j = i kmu e, c_j = -1/2 kthk e
-        const double ajr = Qo * e.x, aji = Qo * e.y;
-        const double bjr = -kmu * e.y, bji = kmu * e.x;
-        const double cjr = -0.5 * kthko * e.x, cji = -0.5 * kthko * e.y;
-        const double T1r = A.x + B.x + C.x, T1i = A.y + B.y + C.y;
-        const double T2r = A.x + B.x, T2i = A.y + B.y;
-        // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
-        const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
-        acc[3] -= w * kx * zi;
-        acc[4] -= w * ky * zi;
-        acc[5] -= w * kz * zi;
-        acc[6] += w * (e.x * T1r + e.y * T1i);
-        const double ime = e.y * T2r - e.x * T2i;
-        acc[7] -= w * kx * ime;
-        acc[8] -= w * ky * ime;
-        acc[9] -= w * kz * ime;
-        const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
-        acc[10] += h * kx * kx;
-        acc[11] += h * kx * ky;
-        acc[12] += h * kx * kz;
-        acc[13] += h * ky * ky;
-        acc[14] += h * ky * kz;
-        acc[15] += h * kz * kz;
+    const int ny = iy - g.my;
+    const double2 exy = cmul(row[nx], row[g.NX + iy]);
+    const double2 ez = row[g.NX + g.NY + g.mz + p];
+    for (int sg = 0; sg < 2; sg++) {
+      if (sg == 1 && p == 0) break;
+      const int nz = sg ? -p : p;
+      const int k = col * g.NZ + g.mz + nz;
+      const double w = kw[(size_t)f * g.KF + k];
+      if (w == 0.0) continue;
+      const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
+                   kz = 2.0 * kPi * nz * fr.inv_box[2];
+      const double2 e = cmul(exy, sg ? cconj(ez) : ez);
+      const double2 S = smm[(size_t)f * smm_stride + k];
+      // Y = e conj(S)
+      const double yr = e.x * S.x + e.y * S.y, yi = e.y * S.x - e.x * S.y;
+      if (!BWD) {
+        acc[0] += w * yr;
+        acc[1] -= w * kx * yi;
+        acc[2] -= w * ky * yi;
+        acc[3] -= w * kz * yi;
+        const double h = -0.5 * w * yr;
+        acc[4] += h * kx * kx;
+        acc[5] += h * kx * ky;
+        acc[6] += h * kx * kz;
+        acc[7] += h * ky * ky;
+        acc[8] += h * ky * kz;
+        acc[9] += h * kz * kz;
+      } else {
+        // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
+        const double kthk = kx * kx * t0 + ky * ky * t3 + kz * kz * t5 + 2.0 * (kx * ky * t1 + kx * kz * t2 + ky * kz * t4);
+        const double wr = Qe - 0.5 * kthk, wi = kx * m0 + ky * m1 + kz * m2;
+        const double gr = -(wr * yi + wi * yr);
+        acc[0] += w * kx * gr;
+        acc[1] += w * ky * gr;
+        acc[2] += w * kz * gr;
+        if (qmqm) {
+          const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
+          const double2 A = abc[0], B = abc[1], C = abc[2];
+          const double kmu = kx * o0 + ky * o1 + kz * o2;
+          const double kthko = kx * kx * u0 + ky * ky * u3 + kz * kz * u5 + 2.0 * (kx * ky * u1 + kx * kz * u2 + ky * kz * u4);
+          // a_j = Q e, b_j = i kmu e, c_j = -1/2 kthk e
+          const double ajr = Qo * e.x, aji = Qo * e.y;
+          const double bjr = -kmu * e.y, bji = kmu * e.x;
+          const double cjr = -0.5 * kthko * e.x, cji = -0.5 * kthko * e.y;
+          const double T1r = A.x + B.x + C.x, T1i = A.y + B.y + C.y;
+          const double T2r = A.x + B.x, T2i = A.y + B.y;
+          // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
+          const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
+          acc[3] -= w * kx * zi;
+          acc[4] -= w * ky * zi;
+          acc[5] -= w * kz * zi;
+          acc[6] += w * (e.x * T1r + e.y * T1i);
+          const double ime = e.y * T2r - e.x * T2i;
+          acc[7] -= w * kx * ime;
+          acc[8] -= w * ky * ime;
+          acc[9] -= w * kz * ime;
+          const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
+          acc[10] += h * kx * kx;
+          acc[11] += h * kx * ky;
+          acc[12] += h * kx * kz;
+          acc[13] += h * ky * ky;
+          acc[14] += h * ky * kz;
+          acc[15] += h * kz * kz;
+        }
       }
     }
   }
@@ -658,8 +932,9 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
                              size_t smm_frame_stride, const double* Q, const double* mu, const double* theta,
                              int backward, int qmqm, Work& w, hipStream_t s) {
   if (max_nq == 0) return hipSuccess;
-  int n_pc = (2048 + total_nq - 1) / (total_nq > 0 ? total_nq : 1);
-  const int kblocks = (g.KF + 255) / 256;
+  // about 640 blocks in all: enough k items per thread to amortise the block reduction
+  int n_pc = (640 + total_nq - 1) / (total_nq > 0 ? total_nq : 1);
+  const int kblocks = (g.NCOL * (g.mz + 1) + 255) / 256;
   if (n_pc > kblocks) n_pc = kblocks;
   if (n_pc < 1) n_pc = 1;
   dim3 grid(max_nq, n_pc, fa.n_frames);
@@ -827,128 +1102,158 @@ __global__ __launch_bounds__(256) void k_force_mm(Grid g, FrameArg fa, int kc_n,
 //   P[a][c]  = sum_nz E[a][nz] W[nz][c],   Pz[a][c] = sum_nz E[a][nz] nz W[nz][c],
 //   E[a][nz] = e^{-i nz kz0 z_a},
 // are complex products with the contraction over nz, four nz per
-// v_mfma_f64_16x16x4f64 (A = E: lane l holds atom l%16, nz 4s + l/16;
-// B = W: lane l holds column l%16, nz 4s + l/16; D: lane l, element r holds
-// atom l/16 + 4r, column l%16).  E advances by e^{-4 i kz0 z} per step in
-// registers.  The epilogue multiplies by e^{-i(kx x + ky y)} from the phase
-// tables and accumulates the four outputs per atom across the wave's columns.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-DEV v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-
-template <int NKS>
-__global__ __launch_bounds__(256) void k_force_mm_mfma(Grid g, FrameArg fa, int kc_n, const double* __restrict__ mm4,
-                                                       int cap_mm, const double2* __restrict__ tab,
-                                                       const double2* __restrict__ wfrag, double* __restrict__ fpart) {
+// ------------------------------------------------------------------ matrix-core adjoint
+// For MM atom i and column c, with the folded weights of k_sfac_qm:
+//   P(i,c)  = W(c,0) + sum_p [Ap cos(p kz0 z_i) - i Am sin(p kz0 z_i)]
+//   Pz(i,c) = sum_p p [Am cos(p kz0 z_i) - i Ap sin(p kz0 z_i)]
+// Re P, Im P, Re Pz, Im Pz are four real contractions of the z table
+// (atoms x K, A operand, held in registers for the whole wave) with the
+// folded weights (K x columns, B operand, fragment order).  The epilogue
+// multiplies by c = e^{-i(kx x + ky y)} from the phase tables and accumulates
+// per atom: Re(cP) (potential), nx Im(cP), ny Im(cP) and Im(c Pz) (forces
+// up to the factors kx0, ky0, kz0).  AT tiles of 16 atoms per wave share the
+// B operand.  The four waves of a block (different atoms, same columns) read
+// each column group's B operand from LDS: the block copies it there once,
+// double buffered, the next group's copy in flight during the contraction.
+template <int NK, int AT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3 : 1))) void k_force_mm_mfma(Grid g, FrameArg fa, int kc_n, int cap_mm,
+                                                       const double2* __restrict__ tab,
+                                                       const double* __restrict__ ztab,
+                                                       const double* __restrict__ wfrag,
+                                                       const double2* __restrict__ wk0, double* __restrict__ fpart) {
+  __shared__ double bsh[2][NK * 256];
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
-  const int a0 = (blockIdx.x * 4 + wave) * 16;
-  if (a0 >= fr.nm) return;
+  if (blockIdx.x * 64 * AT >= fr.nm) return;  // uniform over the block
+  // waves past the last atom still take part in the staging (their atoms are clamped, nothing is written)
+  const int a0 = (blockIdx.x * 4 + wave) * 16 * AT;
   const int kc = blockIdx.y;
   const int per = (g.NG + kc_n - 1) / kc_n;
   const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
   const int li = lane & 15, lk = lane >> 4;
-  const int mz = g.mz;
-  // A operands for every step, once per wave: E[s] = e^{-i (4s + lk - mz) kz0 z}, atom a0 + li
-  const int aA = min(a0 + li, fr.nm - 1);
-  const double zA = mm4[(size_t)2 * cap_mm + fr.moff + aA] * fr.inv_box[2];
-  double er[NKS], ei[NKS];
-  {
-    double s_, c_;
-    sincospi(-2.0 * (double)(lk - mz) * zA, &s_, &c_);
-    double2 E = make_double2(c_, s_);
-    sincospi(-8.0 * zA, &s_, &c_);
-    const double2 u4 = make_double2(c_, s_);
+  // A operands of every K step: z table of atom a0 + 16t + li, entry 4s + lk
+  double za[AT][NK];
 #pragma unroll
-    for (int st = 0; st < NKS; st++) {
-      er[st] = E.x;
-      ei[st] = E.y;
-      E = cmul(E, u4);
-    }
+  for (int t = 0; t < AT; t++) {
+    const int aA = min(a0 + 16 * t + li, fr.nm - 1);
+    const double* __restrict__ zr = ztab + (size_t)(fr.moff + aA) * g.ZKP + lk;
+#pragma unroll
+    for (int st = 0; st < NK; st++) za[t][st] = zr[4 * st];
   }
-  double acc0[4], acc1[4], acc2[4], acc3[4];
+  double acc0[AT][4], acc1[AT][4], acc2[AT][4], acc3[AT][4];
+  int arow[AT][4];
 #pragma unroll
-  for (int r = 0; r < 4; r++) acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
-  int arow[4];
+  for (int t = 0; t < AT; t++)
 #pragma unroll
-  for (int r = 0; r < 4; r++) arow[r] = fr.moff + min(a0 + lk + 4 * r, fr.nm - 1);
+    for (int r = 0; r < 4; r++) {
+      acc0[t][r] = acc1[t][r] = acc2[t][r] = acc3[t][r] = 0.0;
+      arow[t][r] = fr.moff + min(a0 + 16 * t + lk + 4 * r, fr.nm - 1);
+    }
+  const double* __restrict__ wfr = wfrag + (size_t)f * g.NG * NK * 256 + threadIdx.x;
+  double stg[NK];
+  if (gbeg < gend) {
+#pragma unroll
+    for (int u = 0; u < NK; u++) stg[u] = wfr[(size_t)gbeg * NK * 256 + 256 * u];
+#pragma unroll
+    for (int u = 0; u < NK; u++) bsh[0][threadIdx.x + 256 * u] = stg[u];
+  }
+  __syncthreads();
+  int cur = 0;
   for (int grp = gbeg; grp < gend; grp++) {
+    const bool more = grp + 1 < gend;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NK; u++) stg[u] = wfr[(size_t)(grp + 1) * NK * 256 + 256 * u];
+    }
     const int col = grp * 16 + li;
     const bool cok = col < g.NCOL;
     const int colc = cok ? col : g.NCOL - 1;
     const int nx = colc / g.NY, iy = colc - nx * g.NY;
     // column phases of the epilogue, loaded ahead of the contraction
-    double2 ex[4], ey[4];
+    double2 ex[AT][4], ey[AT][4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const double2* __restrict__ row = tab + (size_t)arow[r] * g.R;
-      ex[r] = row[nx];
-      ey[r] = row[g.NX + iy];
+    for (int t = 0; t < AT; t++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const double2* __restrict__ row = tab + (size_t)arow[t][r] * g.R;
+        ex[t][r] = row[nx];
+        ey[t][r] = row[g.NX + iy];
+      }
+    const double2 w0 = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
+    const double* __restrict__ wg = bsh[cur] + lane;
+    v4d Pr[AT], Pi[AT], Zr[AT], Zi[AT];
+#pragma unroll
+    for (int t = 0; t < AT; t++) {
+      Pr[t] = v4d{w0.x, w0.x, w0.x, w0.x};
+      Pi[t] = v4d{w0.y, w0.y, w0.y, w0.y};
+      Zr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      Zi[t] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-    const double2* __restrict__ wg = wfrag + (((size_t)f * g.NG + grp) * NKS * 64 + lane) * 2;
-    v4d Pr = {0, 0, 0, 0}, Pi = {0, 0, 0, 0}, Zr = {0, 0, 0, 0}, Zi = {0, 0, 0, 0};
 #pragma unroll
-    for (int st = 0; st < NKS; st++) {
-      const double2 w = wg[st * 128];
-      const double2 wz = wg[st * 128 + 1];
-      Pr = mfma4(er[st], w.x, Pr);
-      Pi = mfma4(er[st], w.y, Pi);
-      Zr = mfma4(er[st], wz.x, Zr);
-      Zi = mfma4(er[st], wz.y, Zi);
-      Pr = mfma4(-ei[st], w.y, Pr);
-      Pi = mfma4(ei[st], w.x, Pi);
-      Zr = mfma4(-ei[st], wz.y, Zr);
-      Zi = mfma4(ei[st], wz.x, Zi);
+    for (int st = 0; st < NK; st++) {
+      const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
+#pragma unroll
+      for (int t = 0; t < AT; t++) {
+        Pr[t] = mfma4(za[t][st], b0, Pr[t]);
+        Pi[t] = mfma4(za[t][st], b1, Pi[t]);
+        Zr[t] = mfma4(za[t][st], b2, Zr[t]);
+        Zi[t] = mfma4(za[t][st], b3, Zi[t]);
+      }
     }
     const double fnx = (double)nx, fny = (double)(iy - g.my);
     if (cok) {
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
-        const double2 c = cconj(cmul(ex[r], ey[r]));
-        const double cpr = c.x * Pr[r] - c.y * Pi[r];
-        const double cpi = c.x * Pi[r] + c.y * Pr[r];
-        const double czi = c.x * Zi[r] + c.y * Zr[r];
-        acc0[r] += cpr;
-        acc1[r] += fnx * cpi;
-        acc2[r] += fny * cpi;
-        acc3[r] += czi;
-      }
+      for (int t = 0; t < AT; t++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
+          const double2 c = cconj(cmul(ex[t][r], ey[t][r]));
+          const double cpr = c.x * Pr[t][r] - c.y * Pi[t][r];
+          const double cpi = c.x * Pi[t][r] + c.y * Pr[t][r];
+          const double czi = c.x * Zi[t][r] + c.y * Zr[t][r];
+          acc0[t][r] += cpr;
+          acc1[t][r] += fnx * cpi;
+          acc2[t][r] += fny * cpi;
+          acc3[t][r] += czi;
+        }
     }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NK; u++) bsh[cur ^ 1][threadIdx.x + 256 * u] = stg[u];
+    }
+    __syncthreads();
+    cur ^= 1;
   }
   // sum over the 16 columns held by lanes with the same lk
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
+  for (int t = 0; t < AT; t++)
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      acc0[r] += __shfl_xor(acc0[r], o, 64);
-      acc1[r] += __shfl_xor(acc1[r], o, 64);
-      acc2[r] += __shfl_xor(acc2[r], o, 64);
-      acc3[r] += __shfl_xor(acc3[r], o, 64);
+    for (int r = 0; r < 4; r++) {
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        acc0[t][r] += __shfl_xor(acc0[t][r], o, 64);
+        acc1[t][r] += __shfl_xor(acc1[t][r], o, 64);
+        acc2[t][r] += __shfl_xor(acc2[t][r], o, 64);
+        acc3[t][r] += __shfl_xor(acc3[t][r], o, 64);
+      }
     }
-  }
   if (li == 0) {
     const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int a = a0 + lk + 4 * r;
-      if (a < fr.nm) {
-        double* o = fpart + ((size_t)kc * cap_mm + fr.moff + a) * 4;
-        o[0] = acc0[r];
-        o[1] = kx0 * acc1[r];
-        o[2] = ky0 * acc2[r];
-        o[3] = kz0 * acc3[r];
+    for (int t = 0; t < AT; t++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int a = a0 + 16 * t + lk + 4 * r;
+        if (a < fr.nm) {
+          double* o = fpart + ((size_t)kc * cap_mm + fr.moff + a) * 4;
+          o[0] = acc0[t][r];
+          o[1] = kx0 * acc1[t][r];
+          o[2] = ky0 * acc2[t][r];
+          o[3] = kz0 * acc3[t][r];
+        }
       }
-    }
-  }
-}
-
-bool force_mm_mfma_has_nks(int nks) {
-  switch (nks) {
-    case 3: case 5: case 7: case 9: case 11: case 13: case 15: case 17: return true;
-    default: return false;
   }
 }
 
@@ -961,14 +1266,21 @@ static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const Fra
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
-  if (t.bwd_ilp >= 3 && force_mm_mfma_has_nks(g.NKS)) {  // matrix-core path: 64 atoms per block
-    dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
-#define FM(N)                                                                                                   \
-  case N:                                                                                                       \
-    hipLaunchKernelGGL(k_force_mm_mfma<N>, grid, dim3(256), 0, s, g, fa, t.kc, w.mm4, cap_mm, w.mm_tab, w.wfrag, \
-                       w.fpart);                                                                                \
+  if (t.bwd_ilp >= 3 && mfma_bwd_ok(g)) {  // matrix-core path: 64 (AT=1) or 128 (AT=2) atoms per block
+    const int at = t.bwd_ilp == 4 ? 2 : 1;
+    dim3 grid((max_nm + 64 * at - 1) / (64 * at), t.kc, fa.n_frames);
+#define FM(N, AT)                                                                                          \
+  hipLaunchKernelGGL((k_force_mm_mfma<N, AT>), grid, dim3(256), 0, s, g, fa, t.kc, cap_mm, w.mm_tab, w.mm_ztab, \
+                     w.wfrag, w.wk0, w.fpart)
+#define FMC(N)              \
+  case N:                   \
+    if (at == 2)            \
+      FM(N, 2);             \
+    else                    \
+      FM(N, 1);             \
     break;
-    switch (g.NKS) { FM(3) FM(5) FM(7) FM(9) FM(11) FM(13) FM(15) FM(17) default: break; }
+    switch (g.NK2) { FMC(2) FMC(4) FMC(6) FMC(8) FMC(10) FMC(12) FMC(14) FMC(16) default: return hipErrorInvalidValue; }
+#undef FMC
 #undef FM
     return hipGetLastError();
   }
@@ -1696,18 +2008,20 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int runs = (g.NX + kTabRun - 1) / kTabRun + (g.NY + kTabRun - 1) / kTabRun + (g.NZP + kTabRun - 1) / kTabRun;
+  const int rxy = (g.NX + kTabRun - 1) / kTabRun + (g.NY + kTabRun - 1) / kTabRun;
+  const int rz = (g.NZP + kTabRun - 1) / kTabRun, rr = (g.mz + kTabRun - 1) / kTabRun;
   if (max_nm > 0 && mm_tables) {
-    const long n = (long)max_nm * runs;
+    const int with_ez = mm_tables >= 2;
+    const long n = (long)max_nm * (rxy + rr + (with_ez ? rz : 0));
     dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, w.mm4, cap_mm, w.mm_tab);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, with_ez, w.mm4, cap_mm, w.mm_tab, w.mm_ztab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (max_nq > 0) {
-    const long n = (long)max_nq * runs;
+    const long n = (long)max_nq * (rxy + rz);
     dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 1, w.qm4, cap_qm, w.qm_tab);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 1, 1, w.qm4, cap_qm, w.qm_tab, (double*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
