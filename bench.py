@@ -91,11 +91,18 @@ def main():
         del src, dst
     s = wl.make_config(3)
     nh = n_half_space(s.kmax)
-    # the plan records HIP events around every launch on the stream it runs on
-    pplan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
-                             profile=True))
-    if not args.no_autotune:
-        pplan.autotune(s.nm)   # times candidate tilings on this device (untimed setup)
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(prefix="mpewald_tune_"), "tune.jsonl")
+
+    def make_plan(profile):
+        p = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                             profile=profile))
+        if not args.no_autotune:
+            p.autotune(s.nm, cache)   # times candidate tilings once (untimed setup); later plans read the cache
+        return p
+
+    # the timed plan brackets only the two hot loops with HIP events on their own streams
+    pplan = make_plan("hot")
 
     def tens(a, grad=True):
         return torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
@@ -119,29 +126,52 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    kern = pplan.profile_report()
+    hot_kern = pplan.profile_report()
     assert np.isfinite(E.item())
 
-    # per-kernel averages and the roofline of the dominant hot kernel
+    # roofline of the dominant hot kernel, from the events of the timed region.
+    # Algorithmic flops per (k, MM atom): 8 forward, 6 adjoint (the method's
+    # per-term work).  The matrix-core kernels fold +nz and -nz into one real
+    # contraction and execute 4 (forward) and 8 (adjoint) FP64 flops per term.
     per = {k: dict(count=v["count"], avg_us=1e3 * v["total_ms"] / max(v["count"], 1),
-                   ms_per_step=v["total_ms"] / args.steps) for k, v in kern.items()}
+                   ms_per_step=v["total_ms"] / args.steps) for k, v in hot_kern.items()}
     flops = {"sfac_mm": 8.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm}
+    executed = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 8.0 * nh * s.nm}
     hot = {k: per[k] for k in flops if k in per}
     dom = max(hot, key=lambda k: hot[k]["ms_per_step"])
     achieved = flops[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12
     src_hash = kernel_source_hash()
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=traffic_from_profiles(dom, src_hash),
-                kernel=dom, flops_per_launch=flops[dom], avg_launch_us=round(per[dom]["avg_us"], 2))
+                kernel=dom, flops_per_launch=flops[dom], avg_launch_us=round(per[dom]["avg_us"], 2),
+                executed_flops_per_launch=executed[dom],
+                executed_frac=round(executed[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4))
     hot_total_us = sum(per[k]["avg_us"] for k in hot)
     path_flops = 14.0 * nh * s.nm
     extra = dict(
-        hot_path=dict(kernels=sorted(hot), flops_per_step=path_flops, kernel_us=round(hot_total_us, 2),
-                      frac_of_fp64_peak=round(path_flops / (hot_total_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        hot_path=dict(kernels={k: dict(avg_us=round(per[k]["avg_us"], 2),
+                                       algorithmic_frac=round(flops[k] / (per[k]["avg_us"] * 1e-6) / 1e12
+                                                              / FP64_PEAK_TFLOPS, 4),
+                                       executed_frac=round(executed[k] / (per[k]["avg_us"] * 1e-6) / 1e12
+                                                           / FP64_PEAK_TFLOPS, 4)) for k in sorted(hot)},
+                      flops_per_step=path_flops, kernel_us=round(hot_total_us, 2),
+                      note="the two hot loops run concurrently on two streams; their durations overlap",
                       step_frac_of_fp64_peak=round(path_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
-        kernels={k: dict(avg_us=round(v["avg_us"], 2), per_step=round(v["count"] / args.steps, 2))
-                 for k, v in per.items()},
         kernel_source_hash=src_hash, plan=pplan.describe())
+
+    # every launch timed separately (events perturb the step, so not in the timed region)
+    fplan = make_plan(True)
+    for _ in range(3):
+        step(fplan)
+    torch.cuda.synchronize()
+    fplan.profile_report()
+    nprof = 5
+    for _ in range(nprof):
+        step(fplan)
+    torch.cuda.synchronize()
+    extra["kernels"] = {k: dict(avg_us=round(1e3 * v["total_ms"] / max(v["count"], 1), 2),
+                                per_step=round(v["count"] / nprof, 2)) for k, v in fplan.profile_report().items()}
+    fplan.close()
 
     if not args.no_extras:
         extra["plain_path"] = _plain_path(s, dev, nh)

@@ -73,8 +73,10 @@ enum {
   EWALD_PLAIN = 2,         /* forward uses the unoptimised reference GPU path:
                               one thread per k, direct sincos per (k, atom) */
   EWALD_CELL_LIST = 4,     /* real space visits only neighbouring cells */
-  EWALD_PROFILE = 8        /* time every kernel launch with events on its stream
+  EWALD_PROFILE = 8,       /* time every kernel launch with events on its stream
                               (single-frame calls only; read with ewald_profile_report) */
+  EWALD_PROFILE_HOT = 16   /* as EWALD_PROFILE, but only the two reciprocal-space
+                              hot loops (sfac_mm, force_mm): two events per launch */
 };
 
 typedef struct {
@@ -83,7 +85,7 @@ typedef struct {
   double rcut;     /* real-space cutoff, pairs with |r| < rcut, <= min(box)/2 */
   int kmax[3];     /* reciprocal cube |n_a| <= kmax[a], each >= 1 */
   int precision;   /* EWALD_FP64 or EWALD_FP32_REAL */
-  int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST */
+  int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT */
   int max_qm;      /* capacity: QM sites per call (sum over frames in a batch) */
   int max_mm;      /* capacity: MM charges per call (sum over frames in a batch) */
   int max_frames;  /* capacity: frames per ewald_batch call (>= 1) */

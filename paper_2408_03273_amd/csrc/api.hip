@@ -74,7 +74,16 @@ struct ewald_plan {
 
 namespace {
 
-bool profiling(const ewald_plan* pl) { return (pl->p.flags & EWALD_PROFILE) && !pl->capturing; }
+bool profiling(const ewald_plan* pl) {
+  return (pl->p.flags & (EWALD_PROFILE | EWALD_PROFILE_HOT)) && !pl->capturing;
+}
+
+// EWALD_PROFILE_HOT brackets only the two reciprocal-space hot loops
+bool profiled_launch(const ewald_plan* pl, const char* name) {
+  if (!profiling(pl)) return false;
+  if (pl->p.flags & EWALD_PROFILE) return true;
+  return strncmp(name, "launch_force_mm(", 16) == 0 || strncmp(name, "launch_sfac_mm(", 15) == 0;
+}
 
 hipEvent_t pool_event(ewald_plan* pl) {
   if (!pl->ev_pool.empty()) {
@@ -92,7 +101,7 @@ struct ProfScope {
   ewald_plan* pl;
   hipStream_t s;
   bool on;
-  ProfScope(ewald_plan* p, const char* name, hipStream_t st) : pl(p), s(st), on(profiling(p)) {
+  ProfScope(ewald_plan* p, const char* name, hipStream_t st) : pl(p), s(st), on(profiled_launch(p, name)) {
     if (!on) return;
     ewald_plan::ProfRec r{name, pool_event(pl), pool_event(pl)};
     (void)hipEventRecord(r.a, s);
@@ -367,16 +376,21 @@ ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, co
   return EWALD_OK;
 }
 
+// with_adjoint: the QM-side projection and the all-pairs real-space kernel
+// also accumulate the adjoint sums of the effective moments (real space: QM
+// and MM side, the latter into the zeroed rpart)
 ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu, const double* theta, double2* smm,
                                 size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
-                                double* site) {
+                                double* site, int with_adjoint = 0) {
   ewald_plan* pl = q.pl;
+  const int mode = with_adjoint ? 2 : 0;
   LCHK(launch_reduce_smm(pl->g, pl->t, q.fa, q.plain, smm, smm_stride, pl->w, q.s));
-  LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 0, q.qmqm, pl->w, q.s));
+  LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, mode, q.qmqm, pl->w, q.s));
   if (q.cells)
     LCHK(launch_real_cells(pl->g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
   else
-    LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
+    LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, mode, q.fp32, pl->w, q.s,
+                        with_adjoint ? pl->w.rpart : nullptr));
   if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
   LCHK(launch_finalize_fwd(pl->g, q.fa, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad, site, pl->w, q.s));
   return EWALD_OK;
@@ -409,6 +423,7 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 1);
   if (st != EWALD_OK) return st;
   LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
+  // (prep has zeroed rpart: the real-space MM-side adjoint terms accumulate with atomics)
   st = fork_to(pl, q.s, aux);
   if (st != EWALD_OK) return st;
   {
@@ -418,23 +433,17 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     {
       const Seq& q = q_;
       LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
-      if (q.cells) {
-        LCHK(launch_zero(w.rpart, (size_t)pl->cap_mm * 4, q.s));
-        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
-      } else {
-        LCHK(launch_real_mm(g, q.fa, q.max_nm, pl->cap_qm, pl->cap_mm, q.fp32, w, q.s));
-      }
-      LCHK(launch_reduce_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, g_mm_xyz, g_mm_q, w, q.s));
+      if (q.cells) LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
     }
   }
   LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
-  st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site);
+  // the adjoint sums of the QM-side kernels (and, over all pairs, of the MM
+  // side of real space) ride along with the forward kernels
+  st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site, 1);
   if (st != EWALD_OK) return st;
-  // QM-side adjoint pieces need only S_MM and the effective moments: still beside the MM adjoint
-  LCHK(launch_project_qm(g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, 1, q.qmqm, w, q.s));
-  if (!q.cells) LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
   st = join_to(pl, aux, q.s);
   if (st != EWALD_OK) return st;
+  LCHK(launch_reduce_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, g_mm_xyz, g_mm_q, w, q.s));
   LCHK(launch_finalize_bwd(q.fa, q.max_nq, site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
   return EWALD_OK;
 }
@@ -458,7 +467,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   ewald_status_t st = validate_box(p.box, p.rcut);
   if (st != EWALD_OK) return st;
   if (p.precision != EWALD_FP64 && p.precision != EWALD_FP32_REAL) return fail(EWALD_ERR_ARG, "unknown precision");
-  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE))
+  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT))
     return fail(EWALD_ERR_ARG, "unknown flags");
   if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
   ewald_plan* pl = new ewald_plan();

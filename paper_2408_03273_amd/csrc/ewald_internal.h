@@ -136,7 +136,8 @@ inline int fwd_col_groups(const Grid& g, const Tuning& t) {
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 // wrap positions, clear the QM accumulators, sum the charges, build the phase
 // tables (mm_tables: 0 none, 1 x/y complex and real z tables, 2 also complex z);
-// unit_eff also sets the effective moments for an upstream gradient of 1
+// unit_eff also sets the effective moments for an upstream gradient of 1 and
+// zeroes the real-space MM adjoint data (fused forward + adjoint)
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mu, const double* theta, const double* mm_xyz,
                        const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
@@ -149,13 +150,16 @@ hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, in
 hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, Work& w, hipStream_t s);
 hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
                              size_t smm_frame_stride, Work& w, hipStream_t s);
+// backward: 0 forward sums, 1 adjoint sums, 2 both
 hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int total_nq, const double2* smm,
                              size_t smm_frame_stride, const double* Q, const double* mu, const double* theta,
                              int backward, int qmqm, Work& w, hipStream_t s);
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s);
+// backward: 0 forward sums, 1 QM-side adjoint, 2 both; rpart (zeroed, may be
+// null) also receives the MM-side adjoint terms
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
-                          int backward, int fp32, Work& w, hipStream_t s);
+                          int backward, int fp32, Work& w, hipStream_t s, double* rpart = nullptr);
 hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
                           hipStream_t s);
 // cell list (edge >= rcut) of the MM atoms and the real-space kernels that use it

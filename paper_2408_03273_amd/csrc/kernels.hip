@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
                                                   const double* __restrict__ theta, double* __restrict__ qm4,
                                                   int cap_qm, double* __restrict__ mm4, int cap_mm,
                                                   double* __restrict__ qacc, double* __restrict__ qeff, int unit_eff,
-                                                  double* __restrict__ facc) {
+                                                  double* __restrict__ facc, double* __restrict__ rpart) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -117,6 +117,9 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
     for (int a = 0; a < 3; a++) mm4[(size_t)a * cap_mm + r] = wrap_coord(mm_xyz[3 * (size_t)r + a], fr.box[a]);
     mm4[(size_t)3 * cap_mm + r] = mm_q[r];
     v[0] = mm_q[r];
+    // real-space MM adjoint data accumulate with atomics from zero
+    if (rpart)
+      for (int t = 0; t < 4; t++) rpart[(size_t)r * 4 + t] = 0.0;
   }
   if (i < fr.nq) {
     const int r = fr.qoff + i;
@@ -146,75 +149,158 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
 // [e^{i 2pi n x/Lx}, n = 0..mx][e^{i 2pi n y/Ly}, n = -my..my][e^{i 2pi n z/Lz}, n = -mz..mz, then zeros]
 // and, for the MM atoms, a real z row [cos(2pi p z/Lz), p = 1..mz][sin(2pi p z/Lz), p = 1..mz]
 // (the padding after it is zeroed once at set-up).
-// One thread per run of kTabRun entries of one axis: the first entry from
-// sincospi, the rest by multiplying with e^{i 2pi x/L} (at most kTabRun-1
-// rounding steps from an exact start).
+// A block builds the rows of kTabAtoms consecutive atoms in LDS: one thread
+// per run of kTabRun entries of one axis, the first entry from sincospi and
+// the rest by multiplying with e^{i 2pi x/L} (at most kTabRun-1 rounding
+// steps from an exact start); the rows, contiguous in memory, are then
+// written out with consecutive threads on consecutive entries.
 static constexpr int kTabRun = 8;
+static constexpr int kTabAtoms = 16;
+static constexpr int kTabMaxR = 192;    // complex entries per row held in LDS
+static constexpr int kTabMaxZ = 64;     // real z entries per row held in LDS
 
 __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, int with_ez,
                                                   const double* __restrict__ pos4, int cap, double2* __restrict__ tab,
                                                   double* __restrict__ ztab) {
+  __shared__ double2 rows[kTabAtoms][kTabMaxR];
+  __shared__ double zrows[kTabAtoms][kTabMaxZ];
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
   const int off = qm_side ? fr.qoff : fr.moff;
+  const int a0 = blockIdx.x * kTabAtoms;
+  if (a0 >= n_atoms) return;  // uniform over the block
+  const int na = min(kTabAtoms, n_atoms - a0);
+  const int nc = g.NX + g.NY + (with_ez ? g.NZP : 0);  // complex entries built per row
   const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
             rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
   const int runs = rx + ry + rz + rr;
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)n_atoms * runs) return;
-  const int a = (int)(e / runs), t = (int)(e - (long)a * runs);
-  const int row = off + a;
-  int axis, first, count, n0, dst, limit;
-  if (t < rx) {
-    axis = 0;
-    first = t * kTabRun;
-    count = min(kTabRun, g.NX - first);
-    n0 = first;
-    dst = first;
-    limit = count;
-  } else if (t < rx + ry) {
-    axis = 1;
-    first = (t - rx) * kTabRun;
-    count = min(kTabRun, g.NY - first);
-    n0 = first - g.my;
-    dst = g.NX + first;
-    limit = count;
-  } else if (t < rx + ry + rz) {
-    axis = 2;
-    first = (t - rx - ry) * kTabRun;
-    count = min(kTabRun, g.NZP - first);
-    n0 = first - g.mz;
-    dst = g.NX + g.NY + first;
-    limit = g.NZ - first;  // z entries past NZ are padding
-  } else {
-    axis = 3;  // real z row, p = first+1 ..
-    first = (t - rx - ry - rz) * kTabRun;
-    count = min(kTabRun, g.mz - first);
-    n0 = first + 1;
-    dst = first;
-    limit = count;
-  }
-  const int ax = axis == 3 ? 2 : axis;
-  const double x = pos4[(size_t)ax * cap + row] / fr.box[ax];
-  double s0, c0, s1, c1;
-  sincospi(2.0 * (double)n0 * x, &s0, &c0);
-  sincospi(2.0 * x, &s1, &c1);
-  double2 v = make_double2(c0, s0);
-  const double2 step = make_double2(c1, s1);
-  if (axis == 3) {
-    double* __restrict__ o = ztab + (size_t)row * g.ZKP + dst;
-    for (int u = 0; u < count; u++) {
-      o[u] = v.x;
-      o[g.mz + u] = v.y;
+  for (int t = threadIdx.x; t < na * runs; t += 256) {
+    const int a = t / runs, u = t - a * runs;
+    int axis, first, count, n0, limit;
+    if (u < rx) {
+      axis = 0;
+      first = u * kTabRun;
+      count = min(kTabRun, g.NX - first);
+      n0 = first;
+      limit = count;
+    } else if (u < rx + ry) {
+      axis = 1;
+      first = (u - rx) * kTabRun;
+      count = min(kTabRun, g.NY - first);
+      n0 = first - g.my;
+      first += g.NX;
+      limit = count;
+    } else if (u < rx + ry + rz) {
+      axis = 2;
+      first = (u - rx - ry) * kTabRun;
+      count = min(kTabRun, g.NZP - first);
+      n0 = first - g.mz;
+      limit = g.NZ - first;  // z entries past NZ are padding
+      first += g.NX + g.NY;
+    } else {
+      axis = 3;  // real z row, p = first+1 ..
+      first = (u - rx - ry - rz) * kTabRun;
+      count = min(kTabRun, g.mz - first);
+      n0 = first + 1;
+      limit = count;
+    }
+    const int ax = axis == 3 ? 2 : axis;
+    const double x = pos4[(size_t)ax * cap + off + a0 + a] / fr.box[ax];
+    double s0, c0, s1, c1;
+    sincospi(2.0 * (double)n0 * x, &s0, &c0);
+    sincospi(2.0 * x, &s1, &c1);
+    double2 v = make_double2(c0, s0);
+    const double2 step = make_double2(c1, s1);
+    for (int e = 0; e < count; e++) {
+      if (axis == 3) {
+        zrows[a][first + e] = v.x;
+        zrows[a][g.mz + first + e] = v.y;
+      } else {
+        rows[a][first + e] = e < limit ? v : make_double2(0.0, 0.0);
+      }
       v = cmul(v, step);
     }
-    return;
   }
-  double2* __restrict__ o = tab + (size_t)row * g.R + dst;
-  for (int u = 0; u < count; u++) {
-    o[u] = u < limit ? v : make_double2(0.0, 0.0);
-    v = cmul(v, step);
+  __syncthreads();
+  if (with_ez) {
+    // whole rows: one contiguous run of na * R entries
+    double2* __restrict__ o = tab + (size_t)(off + a0) * g.R;
+    for (int e = threadIdx.x; e < na * g.R; e += 256) {
+      const int a = e / g.R, c = e - a * g.R;
+      o[e] = rows[a][c];
+    }
+  } else {
+    const int w = g.NX + g.NY;
+    for (int e = threadIdx.x; e < na * w; e += 256) {
+      const int a = e / w, c = e - a * w;
+      tab[(size_t)(off + a0 + a) * g.R + c] = rows[a][c];
+    }
+  }
+  if (ztab) {
+    const int zw = 2 * g.mz;
+    for (int e = threadIdx.x; e < na * zw; e += 256) {
+      const int a = e / zw, c = e - a * zw;
+      ztab[(size_t)(off + a0 + a) * g.ZKP + c] = zrows[a][c];
+    }
+  }
+  (void)nc;
+}
+
+// Grids whose rows do not fit the LDS tile: one thread per entry, each from its own sincospi.
+__global__ __launch_bounds__(256) void k_prep_tab_direct(Grid g, FrameArg fa, int qm_side, int with_ez,
+                                                         const double* __restrict__ pos4, int cap,
+                                                         double2* __restrict__ tab, double* __restrict__ ztab) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int n_atoms = qm_side ? fr.nq : fr.nm;
+  const int off = qm_side ? fr.qoff : fr.moff;
+  const int nc = g.NX + g.NY + (with_ez ? g.NZP : 0);
+  const int per = nc + (ztab ? g.mz : 0);
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n_atoms * per) return;
+  const int a = (int)(e / per), u = (int)(e - (long)a * per);
+  const int row = off + a;
+  int ax, n;
+  if (u < g.NX) {
+    ax = 0;
+    n = u;
+  } else if (u < g.NX + g.NY) {
+    ax = 1;
+    n = u - g.NX - g.my;
+  } else if (u < nc) {
+    ax = 2;
+    const int iz = u - g.NX - g.NY;
+    if (iz >= g.NZ) {
+      tab[(size_t)row * g.R + u] = make_double2(0.0, 0.0);
+      return;
+    }
+    n = iz - g.mz;
+  } else {
+    ax = 3;
+    n = u - nc + 1;
+  }
+  const int axc = ax == 3 ? 2 : ax;
+  const double x = pos4[(size_t)axc * cap + row] / fr.box[axc];
+  double sn, cs;
+  sincospi(2.0 * (double)n * x, &sn, &cs);
+  if (ax == 3) {
+    ztab[(size_t)row * g.ZKP + n - 1] = cs;
+    ztab[(size_t)row * g.ZKP + g.mz + n - 1] = sn;
+  } else {
+    tab[(size_t)row * g.R + u] = make_double2(cs, sn);
+  }
+}
+
+static void launch_tab(const Grid& g, const FrameArg& fa, int qm_side, int with_ez, int max_n, const double* pos4,
+                       int cap, double2* tab, double* ztab, hipStream_t s) {
+  if (g.R <= kTabMaxR && 2 * g.mz <= kTabMaxZ) {
+    dim3 grid((max_n + kTabAtoms - 1) / kTabAtoms, fa.n_frames);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab);
+  } else {
+    const long per = g.NX + g.NY + (with_ez ? g.NZP : 0) + (ztab ? g.mz : 0);
+    dim3 grid((unsigned)(((long)max_n * per + 255) / 256), fa.n_frames);
+    hipLaunchKernelGGL(k_prep_tab_direct, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab);
   }
 }
 
@@ -822,7 +908,9 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
   const int j = blockIdx.x;
   if (j >= fr.nq) return;
   const int r = fr.qoff + j;
-  constexpr int NV = BWD ? 16 : 10;
+  // BWD: 0 forward (10 sums), 1 adjoint (16), 2 both (26, adjoint after the forward ones)
+  constexpr int NV = BWD == 0 ? 10 : BWD == 1 ? 16 : 26;
+  constexpr int OB = BWD == 2 ? 10 : 0;
   double acc[NV];
 #pragma unroll
   for (int t = 0; t < NV; t++) acc[t] = 0.0;
@@ -858,7 +946,7 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
       const double2 S = smm[(size_t)f * smm_stride + k];
       // Y = e conj(S)
       const double yr = e.x * S.x + e.y * S.y, yi = e.y * S.x - e.x * S.y;
-      if (!BWD) {
+      if (BWD != 1) {
         acc[0] += w * yr;
         acc[1] -= w * kx * yi;
         acc[2] -= w * ky * yi;
@@ -870,14 +958,15 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
         acc[7] += h * ky * ky;
         acc[8] += h * ky * kz;
         acc[9] += h * kz * kz;
-      } else {
+      }
+      if (BWD != 0) {
         // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
         const double kthk = kx * kx * t0 + ky * ky * t3 + kz * kz * t5 + 2.0 * (kx * ky * t1 + kx * kz * t2 + ky * kz * t4);
         const double wr = Qe - 0.5 * kthk, wi = kx * m0 + ky * m1 + kz * m2;
         const double gr = -(wr * yi + wi * yr);
-        acc[0] += w * kx * gr;
-        acc[1] += w * ky * gr;
-        acc[2] += w * kz * gr;
+        acc[OB + 0] += w * kx * gr;
+        acc[OB + 1] += w * ky * gr;
+        acc[OB + 2] += w * kz * gr;
         if (qmqm) {
           const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
           const double2 A = abc[0], B = abc[1], C = abc[2];
@@ -891,21 +980,21 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
           const double T2r = A.x + B.x, T2i = A.y + B.y;
           // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
           const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
-          acc[3] -= w * kx * zi;
-          acc[4] -= w * ky * zi;
-          acc[5] -= w * kz * zi;
-          acc[6] += w * (e.x * T1r + e.y * T1i);
+          acc[OB + 3] -= w * kx * zi;
+          acc[OB + 4] -= w * ky * zi;
+          acc[OB + 5] -= w * kz * zi;
+          acc[OB + 6] += w * (e.x * T1r + e.y * T1i);
           const double ime = e.y * T2r - e.x * T2i;
-          acc[7] -= w * kx * ime;
-          acc[8] -= w * ky * ime;
-          acc[9] -= w * kz * ime;
+          acc[OB + 7] -= w * kx * ime;
+          acc[OB + 8] -= w * ky * ime;
+          acc[OB + 9] -= w * kz * ime;
           const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
-          acc[10] += h * kx * kx;
-          acc[11] += h * kx * ky;
-          acc[12] += h * kx * kz;
-          acc[13] += h * ky * ky;
-          acc[14] += h * ky * kz;
-          acc[15] += h * kz * kz;
+          acc[OB + 10] += h * kx * kx;
+          acc[OB + 11] += h * kx * ky;
+          acc[OB + 12] += h * kx * kz;
+          acc[OB + 13] += h * ky * ky;
+          acc[OB + 14] += h * ky * kz;
+          acc[OB + 15] += h * kz * kz;
         }
       }
     }
@@ -914,16 +1003,19 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
   block_sum256<NV>(acc, tot);
   if (threadIdx.x == 0) {
     double* qa = qacc + (size_t)r * QA_STRIDE;
-    if (!BWD) {
+    if (BWD != 1) {
       atomicAdd(&qa[QA_PHI_LR], tot[0]);
       for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_LR + t], tot[1 + t]);
       for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_LR + t], tot[4 + t]);
-    } else {
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_LR + t], tot[t]);
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QQ_LR + t], tot[3 + t]);
-      atomicAdd(&qa[QA_DQ_QQ_LR], tot[6]);
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DMU_QQ_LR + t], tot[7 + t]);
-      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_DTH_QQ_LR + t], tot[10 + t]);
+    }
+    if (BWD != 0) {
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_LR + t], tot[OB + t]);
+      if (qmqm) {
+        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QQ_LR + t], tot[OB + 3 + t]);
+        atomicAdd(&qa[QA_DQ_QQ_LR], tot[OB + 6]);
+        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DMU_QQ_LR + t], tot[OB + 7 + t]);
+        for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_DTH_QQ_LR + t], tot[OB + 10 + t]);
+      }
     }
   }
 }
@@ -938,12 +1030,16 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
   if (n_pc > kblocks) n_pc = kblocks;
   if (n_pc < 1) n_pc = 1;
   dim3 grid(max_nq, n_pc, fa.n_frames);
-  if (backward)
-    hipLaunchKernelGGL(k_project_qm<1>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
-                       w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc);
+#define PQ(B)                                                                                               \
+  hipLaunchKernelGGL(k_project_qm<B>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta, \
+                     w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc)
+  if (backward == 2)
+    PQ(2);
+  else if (backward)
+    PQ(1);
   else
-    hipLaunchKernelGGL(k_project_qm<0>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta,
-                       w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc);
+    PQ(0);
+#undef PQ
   return hipGetLastError();
 }
 
@@ -1337,7 +1433,8 @@ DEV void min_image(double& dx, double& dy, double& dz, const FrameDev& fr) {
 template <typename T, int BWD>
 __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk, const double* __restrict__ qm4,
                                                  int cap_qm, const double* __restrict__ mm4, int cap_mm,
-                                                 const double* __restrict__ qeff, double* __restrict__ qacc) {
+                                                 const double* __restrict__ qeff, double* __restrict__ qacc,
+                                                 double* __restrict__ rpart) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int j = blockIdx.x;
@@ -1349,7 +1446,10 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
   const double X = qm4[r], Y = qm4[(size_t)cap_qm + r], Zc = qm4[(size_t)2 * cap_qm + r];
   const T a = (T)g.alpha;
   const double rc2 = g.rcut * g.rcut;
-  constexpr int NV = BWD ? 3 : 10;
+  // BWD: 0 forward (10 sums), 1 adjoint (3), 2 both (13).  With rpart (zeroed
+  // beforehand) the adjoint also adds the MM-side terms of each pair.
+  constexpr int NV = BWD == 0 ? 10 : BWD == 1 ? 3 : 13;
+  constexpr int OB = BWD == 2 ? 10 : 0;
   double acc[NV];
 #pragma unroll
   for (int t = 0; t < NV; t++) acc[t] = 0.0;
@@ -1371,7 +1471,7 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
     const T x = (T)dx, y = (T)dy, z = (T)dz;
     const Radial<T> R = radial<T>((T)r2d, a);
     const T q = (T)mq_[i];
-    if (!BWD) {
+    if (BWD != 1) {
       acc[0] += (double)(q * R.f1);
       acc[1] += (double)(-q * x * R.f3);
       acc[2] += (double)(-q * y * R.f3);
@@ -1383,7 +1483,8 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
       acc[7] += (double)(h5 * y * y - h3);
       acc[8] += (double)(h5 * y * z);
       acc[9] += (double)(h5 * z * z - h3);
-    } else {
+    }
+    if (BWD != 0) {
       // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
       const T md = m0 * x + m1 * y + m2 * z;
       const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
@@ -1392,37 +1493,48 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
       const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
       const T s2 = -R.f3;
       const T s3 = T(3) * R.f5;
-      acc[0] += (double)(q * (s1 * x + s2 * m0 + s3 * thx));
-      acc[1] += (double)(q * (s1 * y + s2 * m1 + s3 * thy));
-      acc[2] += (double)(q * (s1 * z + s2 * m2 + s3 * thz));
+      const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
+                   gz = (double)(s1 * z + s2 * m2 + s3 * thz);
+      acc[OB + 0] += (double)q * gx;
+      acc[OB + 1] += (double)q * gy;
+      acc[OB + 2] += (double)q * gz;
+      if (rpart) {
+        // MM side: potential of the effective moments per unit charge, and -q g
+        double* o = rpart + (size_t)(fr.moff + i) * 4;
+        atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
+        atomicAdd(&o[1], -(double)q * gx);
+        atomicAdd(&o[2], -(double)q * gy);
+        atomicAdd(&o[3], -(double)q * gz);
+      }
     }
   }
   double tot[NV];
   block_sum256<NV>(acc, tot);
   if (threadIdx.x == 0) {
     double* qa = qacc + (size_t)r * QA_STRIDE;
-    if (!BWD) {
+    if (BWD != 1) {
       atomicAdd(&qa[QA_PHI_SR], tot[0]);
       for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_SR + t], tot[1 + t]);
       for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_SR + t], tot[4 + t]);
-    } else {
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], tot[t]);
     }
+    if (BWD != 0)
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], tot[OB + t]);
   }
 }
 
 static constexpr int kRealChunk = 2048;
 
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
-                          int backward, int fp32, Work& w, hipStream_t s) {
+                          int backward, int fp32, Work& w, hipStream_t s, double* rpart) {
   if (max_nq == 0 || max_nm == 0) return hipSuccess;
   dim3 grid(max_nq, (max_nm + kRealChunk - 1) / kRealChunk, fa.n_frames);
-#define RQ(T, B) \
-  hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, kRealChunk, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.qacc)
+#define RQ(T, B)                                                                                                   \
+  hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, kRealChunk, w.qm4, cap_qm, w.mm4, cap_mm, \
+                     w.qeff, w.qacc, rpart)
   if (fp32) {
-    if (backward) RQ(float, 1); else RQ(float, 0);
+    if (backward == 2) RQ(float, 2); else if (backward) RQ(float, 1); else RQ(float, 0);
   } else {
-    if (backward) RQ(double, 1); else RQ(double, 0);
+    if (backward == 2) RQ(double, 2); else if (backward) RQ(double, 1); else RQ(double, 0);
   }
 #undef RQ
   return hipGetLastError();
@@ -2004,24 +2116,17 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
   if (nmax > 0) {
     dim3 grid((nmax + 255) / 256, fa.n_frames);
     hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, mu, theta, w.qm4, cap_qm,
-                       w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc);
+                       w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc, unit_eff ? w.rpart : (double*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int rxy = (g.NX + kTabRun - 1) / kTabRun + (g.NY + kTabRun - 1) / kTabRun;
-  const int rz = (g.NZP + kTabRun - 1) / kTabRun, rr = (g.mz + kTabRun - 1) / kTabRun;
   if (max_nm > 0 && mm_tables) {
-    const int with_ez = mm_tables >= 2;
-    const long n = (long)max_nm * (rxy + rr + (with_ez ? rz : 0));
-    dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 0, with_ez, w.mm4, cap_mm, w.mm_tab, w.mm_ztab);
+    launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (max_nq > 0) {
-    const long n = (long)max_nq * (rxy + rz);
-    dim3 grid((unsigned)((n + 255) / 256), fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, 1, 1, w.qm4, cap_qm, w.qm_tab, (double*)nullptr);
+    launch_tab(g, fa, 1, 1, max_nq, w.qm4, cap_qm, w.qm_tab, (double*)nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

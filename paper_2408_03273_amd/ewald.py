@@ -58,7 +58,7 @@ class EwaldConfig:
     qmqm: bool = True
     precision: str = "fp64"   # or "fp32_real"
     plain: bool = False       # unoptimised reference GPU path for the forward pass
-    profile: bool = False     # bracket every kernel launch with HIP events (see profile_report)
+    profile: object = False   # True: bracket every launch with HIP events; "hot": only the two hot loops
     cell_list: bool = True    # real space over cells of edge >= rcut when the box has >= 3 per axis
 
 
@@ -79,7 +79,8 @@ class Plan:
         p.kmax[:] = km
         p.precision = {"fp64": _lib.EWALD_FP64, "fp32_real": _lib.EWALD_FP32_REAL}[cfg.precision]
         p.flags = ((_lib.EWALD_QMQM if cfg.qmqm else 0) | (_lib.EWALD_PLAIN if cfg.plain else 0)
-                   | (_lib.EWALD_PROFILE if cfg.profile else 0) | (_lib.EWALD_CELL_LIST if cfg.cell_list else 0))
+                   | (_lib.EWALD_PROFILE_HOT if cfg.profile == "hot" else _lib.EWALD_PROFILE if cfg.profile else 0)
+                   | (_lib.EWALD_CELL_LIST if cfg.cell_list else 0))
         p.max_qm, p.max_mm, p.max_frames = int(cfg.max_qm), int(cfg.max_mm), int(cfg.max_frames)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -109,3 +109,11 @@ def test_forward_kernel_variants(mode, ct, monkeypatch):
            keys=H.FWD_KEYS)
     _check(wl.random_system(45, 5, 1203, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=(5, 5, 3)),
            keys=H.FWD_KEYS)
+
+
+def test_large_kgrid_valu_kernels_and_direct_tables():
+    """kmax beyond the matrix-core instances (mz > 32) selects the VALU hot
+    loops, and table rows longer than the LDS tile use the per-entry table
+    kernel."""
+    s = wl.random_system(46, 4, 420, box=(21.0, 23.0, 25.0), alpha=0.5, rcut=9.0, kmax=(30, 40, 34))
+    _check(s)
