@@ -58,6 +58,7 @@ struct ewald_plan {
   hipStream_t aux = nullptr, gaux = nullptr;
   int serial = 0;  // run the adjoint chain on the caller's stream (isolated kernel timings)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_qside = nullptr, ev_mtab = nullptr;  // QM structure factors done; MM tables done
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
   std::vector<FrameDev> host_frames;
@@ -183,6 +184,8 @@ void free_plan(ewald_plan* pl) {
   if (pl->gaux) (void)hipStreamDestroy(pl->gaux);
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->ev_qside) (void)hipEventDestroy(pl->ev_qside);
+  if (pl->ev_mtab) (void)hipEventDestroy(pl->ev_mtab);
   for (auto& r : pl->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -196,10 +199,10 @@ void free_plan(ewald_plan* pl) {
 
 void set_describe(ewald_plan* pl) {
   char buf[256];
-  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-fold-16", "mfma-fold-32"};
+  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-fold-16", "mfma-fold-32", "mfma-fold-ws"};
   char fwd[64];
   if (pl->t.fwd_mode == 1)
-    snprintf(fwd, sizeof(fwd), "mfma-fold ct=%d nt=%d", pl->t.fwd_ct, pl->g.NT);
+    snprintf(fwd, sizeof(fwd), "mfma-fold ct=%d nt=%d xcd=%d", pl->t.fwd_ct, pl->g.NT, pl->t.fwd_xcd);
   else
     snprintf(fwd, sizeof(fwd), "valu zc=%d nzp=%d", pl->g.Zc, pl->g.NZP);
   snprintf(buf, sizeof(buf), "fwd=%s blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", fwd, pl->t.fwd_target,
@@ -277,7 +280,7 @@ int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
 }
 
 int choose_kc(const ewald_plan* pl, long total_nm) {
-  const long per_block = pl->t.bwd_ilp >= 3 ? 64L * (pl->t.bwd_ilp - 2) : 256L * (pl->t.bwd_ilp == 1 ? 1 : 2);
+  const long per_block = pl->t.bwd_ilp == 4 ? 128L : pl->t.bwd_ilp >= 3 ? 64L : 256L * (pl->t.bwd_ilp == 1 ? 1 : 2);
   const long ablocks = std::max<long>(1, (total_nm + per_block - 1) / per_block);
   long kc = (kTargetBlocks + ablocks - 1) / ablocks;
   if (pl->t.kc > 0) kc = pl->t.kc;
@@ -362,13 +365,14 @@ struct Seq {
 #define LCHK(expr) LCHK_P(pl, q.s, #expr, expr)
 
 ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, const double* mu, const double* theta,
-                         const double* mm_xyz, const double* mm_q, int mm_tables, int unit_eff) {
+                         const double* mm_xyz, const double* mm_q, int mm_tables, int unit_eff,
+                         int parts = PREP_ALL) {
   ewald_plan* pl = q.pl;
   if (q.total_nq > q.max_nq)  // packed rows with gaps: clear every QM row (prep clears only the used ones)
     LCHK(launch_zero(pl->w.qacc, (size_t)q.total_nq * QA_STRIDE, q.s));
   LCHK(launch_zero(pl->w.facc, (size_t)q.fa.n_frames * FA_COUNT, q.s));
   LCHK(launch_prep(pl->g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, pl->w, q.s, pl->cap_qm,
-                   pl->cap_mm, mm_tables, unit_eff));
+                   pl->cap_mm, mm_tables, unit_eff, parts));
   if (q.cells) {
     LCHK(launch_zero((double*)pl->w.cell_cnt, (size_t)(pl->cap_cells + 1) / 2, q.s));
     LCHK(launch_cells(q.fa, q.max_nm, pl->cap_mm, pl->w, q.s));
@@ -381,17 +385,20 @@ ewald_status_t seq_begin(const Seq& q, const double* qm_xyz, const double* Q, co
 // and MM side, the latter into the zeroed rpart)
 ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu, const double* theta, double2* smm,
                                 size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
-                                double* site, int with_adjoint = 0) {
+                                double* site, int with_adjoint = 0, int early = 0, int finalize = 1) {
   ewald_plan* pl = q.pl;
   const int mode = with_adjoint ? 2 : 0;
   LCHK(launch_reduce_smm(pl->g, pl->t, q.fa, q.plain, smm, smm_stride, pl->w, q.s));
   LCHK(launch_project_qm(pl->g, q.fa, q.max_nq, q.total_nq, smm, smm_stride, Q, mu, theta, mode, q.qmqm, pl->w, q.s));
-  if (q.cells)
-    LCHK(launch_real_cells(pl->g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
-  else
-    LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, mode, q.fp32, pl->w, q.s,
-                        with_adjoint ? pl->w.rpart : nullptr));
-  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
+  if (!early) {  // early: real space and QM-QM were launched before the reciprocal work
+    if (q.cells)
+      LCHK(launch_real_cells(pl->g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
+    else
+      LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, mode, q.fp32, pl->w, q.s,
+                          with_adjoint ? pl->w.rpart : nullptr));
+    if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
+  }
+  if (!finalize) return EWALD_OK;
   LCHK(launch_finalize_fwd(pl->g, q.fa, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad, site, pl->w, q.s));
   return EWALD_OK;
 }
@@ -420,10 +427,10 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   ewald_plan* pl = q.pl;
   Work& w = pl->w;
   const Grid& g = pl->g;
-  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 1);
+  const int tables = mm_tables_for(pl);
+  // positions, charge sums, cleared accumulators, unit effective moments
+  ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, tables, 1, PREP_POS);
   if (st != EWALD_OK) return st;
-  LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
-  // (prep has zeroed rpart: the real-space MM-side adjoint terms accumulate with atomics)
   st = fork_to(pl, q.s, aux);
   if (st != EWALD_OK) return st;
   {
@@ -432,19 +439,48 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
+      // second stream: QM phase tables and structure factors (A, B, C, adjoint
+      // weights), then real space, which needs no reciprocal data (prep has
+      // zeroed rpart: over all pairs the MM-side adjoint terms accumulate there
+      // with atomics); the small kernels run before the big grids of the hot
+      // loops fill the GPU
+      LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm,
+                       pl->cap_mm, tables, 1, PREP_QM_TAB));
+      LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
+      if (q.cells)
+        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
+      else
+        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+      HIPCHK(hipEventRecord(pl->ev_qside, q.s));
+    }
+  }
+  // caller stream: MM phase tables and the (small) QM-QM image sums
+  LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm, pl->cap_mm,
+                   tables, 1, PREP_MM_TAB));
+  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
+  HIPCHK(hipEventRecord(pl->ev_mtab, q.s));
+  // caller stream: the forward hot loop
+  LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
+  {
+    Seq qa = q;
+    qa.s = aux;
+    const Seq& q_ = qa;
+    {
+      const Seq& q = q_;
+      // second stream: the adjoint hot loop (and the MM side of real space with the cell list)
+      HIPCHK(hipStreamWaitEvent(q.s, pl->ev_mtab, 0));
       LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
       if (q.cells) LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
     }
   }
-  LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
-  // the adjoint sums of the QM-side kernels (and, over all pairs, of the MM
-  // side of real space) ride along with the forward kernels
-  st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site, 1);
+  HIPCHK(hipStreamWaitEvent(q.s, pl->ev_qside, 0));
+  // the adjoint sums of the QM-side projection ride along with the forward ones
+  st = seq_forward_tail(q, Q, mu, theta, smm, smm_stride, energy, phi, efield, efgrad, site, 1, 1, 0);
   if (st != EWALD_OK) return st;
   st = join_to(pl, aux, q.s);
   if (st != EWALD_OK) return st;
-  LCHK(launch_reduce_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, g_mm_xyz, g_mm_q, w, q.s));
-  LCHK(launch_finalize_bwd(q.fa, q.max_nq, site, nullptr, q.qmqm, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
+  LCHK(launch_finish_fused(g, pl->t, q.fa, q.max_nm, pl->cap_mm, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad,
+                           site, g_mm_xyz, g_mm_q, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
   return EWALD_OK;
 }
 
@@ -484,6 +520,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   // matrix-core kernels where instantiated (mz <= 32), else the VALU kernels
   pl->t.fwd_mode = mfma_fwd_ok(pl->g) ? 1 : 0;
   pl->t.fwd_ct = mfma_fwd_ct_ok(pl->g, 2) ? 2 : 1;
+  pl->t.fwd_xcd = 1;
   pl->t.fwd_target = pl->t.fwd_mode == 1 ? 1024 : 8192;
   pl->t.bwd_ilp = mfma_bwd_ok(pl->g) ? 4 : 2;
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
@@ -493,7 +530,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   // forward block count target
   if (const char* e = getenv("MPEWALD_BWD")) {
     const int v = atoi(e);
-    if ((v >= 1 && v <= 2) || (v >= 3 && v <= 4 && mfma_bwd_ok(pl->g))) pl->t.bwd_ilp = v;
+    if ((v >= 1 && v <= 2) || (v >= 3 && v <= 5 && mfma_bwd_ok(pl->g))) pl->t.bwd_ilp = v;
   }
   if (const char* e = getenv("MPEWALD_FWD")) {
     const int v = atoi(e);
@@ -503,6 +540,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     }
   }
   if (const char* e = getenv("MPEWALD_SERIAL")) pl->serial = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_FWD_XCD")) pl->t.fwd_xcd = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_FWD_CT")) {
     const int v = atoi(e);
     if (mfma_fwd_ct_ok(pl->g, v)) pl->t.fwd_ct = v;
@@ -567,7 +605,9 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   }
   if (hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_qside, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_mtab, hipEventDisableTiming) != hipSuccess) {
     free_plan(pl);
     delete pl;
     return fail(EWALD_ERR_HIP, "stream or event creation failed");
@@ -964,15 +1004,19 @@ bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
     const char* p3 = strstr(line, "\"kc\": ");
     const char* p4 = strstr(line, "\"fwd\": ");
     const char* p5 = strstr(line, "\"ct\": ");
+    const char* p6 = strstr(line, "\"xcd\": ");
+    int xcd = 0;
+    if (!p6 || sscanf(p6, "\"xcd\": %d", &xcd) != 1) continue;
     if (p1 && p2 && p3 && p4 && p5 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 &&
         sscanf(p2, "\"bwd\": %d", &bw) == 1 && sscanf(p3, "\"kc\": %d", &kc) == 1 &&
         sscanf(p4, "\"fwd\": %d", &fm) == 1 && sscanf(p5, "\"ct\": %d", &ct) == 1 && ft >= 64 &&
-        (bw == 1 || bw == 2 || ((bw == 3 || bw == 4) && mfma_bwd_ok(pl->g))) && kc >= 0 && kc <= pl->cap_kc &&
+        (bw == 1 || bw == 2 || (bw >= 3 && bw <= 5 && mfma_bwd_ok(pl->g))) && kc >= 0 && kc <= pl->cap_kc &&
         (fm == 0 || (fm == 1 && mfma_fwd_ok(pl->g) && mfma_fwd_ct_ok(pl->g, ct)))) {
       pl->t.fwd_target = ft;
       pl->t.bwd_ilp = bw;
       pl->t.kc = kc;
       pl->t.fwd_mode = fm;
+      pl->t.fwd_xcd = xcd ? 1 : 0;
       if (fm == 1) pl->t.fwd_ct = ct;
       found = true;
     }
@@ -1074,17 +1118,19 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     };
     char item[160];
     struct FwdCand {
-      int mode, ct, ft;
+      int mode, ct, ft, xcd;
     };
     std::vector<FwdCand> fc;
     if (mfma_fwd_ok(plan->g))
       for (int ct : {1, 2, 4})
         if (mfma_fwd_ct_ok(plan->g, ct))
-          for (int ft : {512, 768, 1024, 1536, 2304}) fc.push_back({1, ct, ft});
-    for (int ft : {4096, 8192, 16384}) fc.push_back({0, 0, ft});
+          for (int ft : {512, 768, 1024, 1536, 2304})
+            for (int xcd : {0, 1}) fc.push_back({1, ct, ft, xcd});
+    for (int ft : {4096, 8192, 16384}) fc.push_back({0, 0, ft, 0});
     for (const FwdCand& c : fc) {
       plan->t = saved;
       plan->t.fwd_mode = c.mode;
+      plan->t.fwd_xcd = c.xcd;
       if (c.mode == 1) plan->t.fwd_ct = c.ct;
       plan->t.fwd_target = c.ft;
       plan->t.a_chunk = 0;
@@ -1095,18 +1141,20 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
         goto done;
       }
       if (c.mode == 1)
-        snprintf(item, sizeof(item), "%s\"fwd_mfma_ct%d_%d\": %.1f", report.empty() ? "" : ", ", c.ct, c.ft, us);
+        snprintf(item, sizeof(item), "%s\"fwd_mfma_ct%d_%d_x%d\": %.1f", report.empty() ? "" : ", ", c.ct, c.ft,
+                 c.xcd, us);
       else
         snprintf(item, sizeof(item), "%s\"fwd_valu_%d\": %.1f", report.empty() ? "" : ", ", c.ft, us);
       report += item;
       if (us < best_f) {
         best_f = us;
         best.fwd_mode = c.mode;
+        best.fwd_xcd = c.xcd;
         best.fwd_ct = c.mode == 1 ? c.ct : saved.fwd_ct;
         best.fwd_target = c.ft;
       }
     }
-    for (int bw : {2, 3, 4}) {
+    for (int bw : {2, 3, 4, 5}) {
       if (bw >= 3 && !mfma_bwd_ok(plan->g)) continue;
       for (int kc : {0, 1, 2, 4, 8, 16}) {
         if (kc > plan->cap_kc) continue;
@@ -1145,10 +1193,10 @@ done:
     FILE* fp = fopen(cache_path, "a");
     if (fp) {
       fprintf(fp,
-              "{\"key\": \"%s\", \"fwd\": %d, \"ct\": %d, \"fwd_target\": %d, \"bwd\": %d, \"kc\": %d, "
-              "\"times_us\": {%s}}\n",
-              key.c_str(), plan->t.fwd_mode, plan->t.fwd_ct, plan->t.fwd_target, plan->t.bwd_ilp, plan->t.kc,
-              report.c_str());
+              "{\"key\": \"%s\", \"fwd\": %d, \"ct\": %d, \"xcd\": %d, \"fwd_target\": %d, \"bwd\": %d, "
+              "\"kc\": %d, \"times_us\": {%s}}\n",
+              key.c_str(), plan->t.fwd_mode, plan->t.fwd_ct, plan->t.fwd_xcd, plan->t.fwd_target, plan->t.bwd_ilp,
+              plan->t.kc, report.c_str());
       fclose(fp);
     }
   }

@@ -115,11 +115,13 @@ struct Tuning {
   int zc;         // VALU forward nz chunk (template instance)
   int a_chunk;    // forward atoms per block
   int kc;         // backward column chunks
-  int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3|4 matrix cores (16|32 atoms per wave)
+  int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3|4 matrix cores (16|32 atoms per
+                  // wave), 5 matrix cores with separate epilogue waves
   int fwd_pf;     // VALU forward kernel prefetches the next atom's factors
   int fwd_target; // forward blocks the atom chunking aims for
   int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
   int fwd_ct;     // matrix-core forward: 16-column tiles per wave
+  int fwd_xcd;    // matrix-core forward: XCD-aware block order (single-frame calls)
 };
 
 // matrix-core kernels are instantiated for mz <= 32
@@ -138,10 +140,12 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 // tables (mm_tables: 0 none, 1 x/y complex and real z tables, 2 also complex z);
 // unit_eff also sets the effective moments for an upstream gradient of 1 and
 // zeroes the real-space MM adjoint data (fused forward + adjoint)
+// parts: which of the three stages to launch (positions and sums, MM tables, QM tables)
+enum { PREP_POS = 1, PREP_MM_TAB = 2, PREP_QM_TAB = 4, PREP_ALL = 7 };
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mu, const double* theta, const double* mm_xyz,
                        const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
-                       int unit_eff);
+                       int unit_eff, int parts = PREP_ALL);
 hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const double* Q, const double* mu,
                           const double* theta, const double* qeff, const double* gE, int with_w, Work& w,
                           hipStream_t s);
@@ -176,6 +180,12 @@ hipError_t launch_eff_moments(const FrameArg& fa, int max_nq, const double* Q, c
                               Work& w, hipStream_t s);
 hipError_t launch_reduce_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
                             double* g_mm_xyz, double* g_mm_q, Work& w, hipStream_t s);
+// fused forward + adjoint: MM gradient sums, QM outputs, energy and QM gradients (gE = 1) in one launch
+hipError_t launch_finish_fused(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                               const double* Q, const double* mu, const double* theta, int qmqm, double* energy,
+                               double* phi, double* efield, double* efgrad, double* site, double* g_mm_xyz,
+                               double* g_mm_q, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
+                               Work& w, hipStream_t s);
 hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
                                double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s);
 

@@ -149,11 +149,13 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
 // [e^{i 2pi n x/Lx}, n = 0..mx][e^{i 2pi n y/Ly}, n = -my..my][e^{i 2pi n z/Lz}, n = -mz..mz, then zeros]
 // and, for the MM atoms, a real z row [cos(2pi p z/Lz), p = 1..mz][sin(2pi p z/Lz), p = 1..mz]
 // (the padding after it is zeroed once at set-up).
-// A block builds the rows of kTabAtoms consecutive atoms in LDS: one thread
-// per run of kTabRun entries of one axis, the first entry from sincospi and
-// the rest by multiplying with e^{i 2pi x/L} (at most kTabRun-1 rounding
-// steps from an exact start); the rows, contiguous in memory, are then
-// written out with consecutive threads on consecutive entries.
+// A block builds the rows of kTabAtoms consecutive atoms in LDS: first
+// u = e^{i 2pi x/L} per atom and axis (one sincospi each), then one thread
+// per run of kTabRun entries of one axis, whose first entry is u^n by binary
+// powering (conjugated for n < 0) and the rest by multiplying with u (about
+// 2 log2(n) + kTabRun rounding steps in all, ~1e-15 relative); the rows,
+// contiguous in memory, are then written out with consecutive threads on
+// consecutive entries.
 static constexpr int kTabRun = 8;
 static constexpr int kTabAtoms = 16;
 static constexpr int kTabMaxR = 192;    // complex entries per row held in LDS
@@ -164,6 +166,7 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
                                                   double* __restrict__ ztab) {
   __shared__ double2 rows[kTabAtoms][kTabMaxR];
   __shared__ double zrows[kTabAtoms][kTabMaxZ];
+  __shared__ double2 base[kTabAtoms][3];
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
@@ -175,6 +178,14 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
   const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
             rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
   const int runs = rx + ry + rz + rr;
+  if (threadIdx.x < na * 3) {
+    const int a = threadIdx.x / 3, ax = threadIdx.x - 3 * a;
+    const double x = pos4[(size_t)ax * cap + off + a0 + a] / fr.box[ax];
+    double sn, cs;
+    sincospi(2.0 * x, &sn, &cs);
+    base[a][ax] = make_double2(cs, sn);
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < na * runs; t += 256) {
     const int a = t / runs, u = t - a * runs;
     int axis, first, count, n0, limit;
@@ -206,12 +217,14 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
       limit = count;
     }
     const int ax = axis == 3 ? 2 : axis;
-    const double x = pos4[(size_t)ax * cap + off + a0 + a] / fr.box[ax];
-    double s0, c0, s1, c1;
-    sincospi(2.0 * (double)n0 * x, &s0, &c0);
-    sincospi(2.0 * x, &s1, &c1);
-    double2 v = make_double2(c0, s0);
-    const double2 step = make_double2(c1, s1);
+    const double2 step = base[a][ax];
+    // v = step^n0
+    double2 v = make_double2(1.0, 0.0), pw = step;
+    for (int m = n0 < 0 ? -n0 : n0; m; m >>= 1) {
+      if (m & 1) v = cmul(v, pw);
+      pw = cmul(pw, pw);
+    }
+    if (n0 < 0) v = cconj(v);
     for (int e = 0; e < count; e++) {
       if (axis == 3) {
         zrows[a][first + e] = v.x;
@@ -631,7 +644,7 @@ hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, in
 // through LDS and the block writes one partial S per k in k order.
 template <int CT, int NT>
 __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
-                                                      const double* __restrict__ mm4, int cap_mm,
+                                                      int xcd_remap, const double* __restrict__ mm4, int cap_mm,
                                                       const double2* __restrict__ tab,
                                                       const double* __restrict__ ztab,
                                                       double2* __restrict__ spart) {
@@ -641,7 +654,15 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
   __shared__ double s0red[4][CT][2][16];
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
-  const int gc = blockIdx.x % ngc, ac = blockIdx.x / ngc;
+  // Consecutive workgroups go to the 8 XCDs in turn.  With xcd_remap (single
+  // frame) the blocks that share an atom chunk (consecutive logical ids) are
+  // placed on one XCD, so that its L2 serves their common atom rows.
+  int bid = blockIdx.x;
+  if (xcd_remap) {
+    const int per = (int)gridDim.x / 8;
+    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  }
+  const int gc = bid % ngc, ac = bid / ngc;
   if (ac >= nac) return;
   const int a0 = ac * a_chunk;
   if (a0 >= fr.nm) return;  // uniform over the block
@@ -783,8 +804,8 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
 
 template <int CT, int NT>
 static void launch_sfac_mm_mfma_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int a_chunk, int ngc,
-                                  int nac, int cap_mm, Work& w) {
-  hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, w.mm4, cap_mm,
+                                  int nac, int xcd, int cap_mm, Work& w) {
+  hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, xcd, w.mm4, cap_mm,
                      w.mm_tab, w.mm_ztab, w.spart);
 }
 
@@ -794,10 +815,11 @@ static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const Fram
   const int nac = (max_nm + t.a_chunk - 1) / t.a_chunk;
   if (nac == 0) return hipSuccess;
   dim3 grid(ngc * nac, 1, fa.n_frames);
-#define SF(C, N)                                                                 \
-  if (t.fwd_ct == C && g.NT == N) {                                              \
-    launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, cap_mm, w); \
-    return hipGetLastError();                                                    \
+  const int xcd = (t.fwd_xcd && fa.n_frames == 1) ? 1 : 0;
+#define SF(C, N)                                                                      \
+  if (t.fwd_ct == C && g.NT == N) {                                                   \
+    launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, xcd, cap_mm, w); \
+    return hipGetLastError();                                                         \
   }
   SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(1, 3) SF(2, 3) SF(1, 4)
 #undef SF
@@ -1353,6 +1375,124 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
   }
 }
 
+// Warp-specialised matrix-core adjoint: in a block of eight waves, waves 0-3
+// (one 16-atom tile each) only issue the contraction (B operand from L2,
+// where the folded weights stay resident) and write their four accumulator
+// tiles to LDS; waves 4-7 apply the epilogue of the previous column group
+// (phase tables, complex products, per-atom sums), so that no FP64 VALU work
+// sits between the matrix-core instructions of a wave.  One barrier per
+// column group; the tile exchange is double buffered (64 KB, two blocks per CU).
+template <int NK>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_force_mm_ws(
+    Grid g, FrameArg fa, int kc_n, int cap_mm, const double2* __restrict__ tab, const double* __restrict__ ztab,
+    const double* __restrict__ wfrag, const double2* __restrict__ wk0, double* __restrict__ fpart) {
+  __shared__ double psh[2][4][16][64];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = uniform_int(tid >> 6);
+  const bool mma = wave < 4;
+  const int wt = wave & 3;
+  if (blockIdx.x * 64 >= fr.nm) return;  // uniform over the block
+  const int a0 = (blockIdx.x * 4 + wt) * 16;
+  const int kc = blockIdx.y;
+  const int per = (g.NG + kc_n - 1) / kc_n;
+  // an empty column range (more chunks than groups) still writes its zero partial sums
+  const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
+  const int li = lane & 15, lk = lane >> 4;
+  // matrix-core waves: A operands of every K step
+  double za[NK];
+  if (mma) {
+    const int aA = min(a0 + li, fr.nm - 1);
+    const double* __restrict__ zr = ztab + (size_t)(fr.moff + aA) * g.ZKP + lk;
+#pragma unroll
+    for (int st = 0; st < NK; st++) za[st] = zr[4 * st];
+  }
+  // epilogue waves: per-atom sums
+  double acc0[4], acc1[4], acc2[4], acc3[4];
+  int arow[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
+    arow[r] = fr.moff + min(a0 + lk + 4 * r, fr.nm - 1);
+  }
+  for (int it = gbeg; it <= gend && gbeg < gend; it++) {
+    const int cur = (it - gbeg) & 1;
+    if (mma) {
+      if (it < gend) {
+        const double2 w0 = wk0[(size_t)f * g.NG * 16 + it * 16 + li];
+        v4d Pr = v4d{w0.x, w0.x, w0.x, w0.x}, Pi = v4d{w0.y, w0.y, w0.y, w0.y};
+        v4d Zr = v4d{0.0, 0.0, 0.0, 0.0}, Zi = v4d{0.0, 0.0, 0.0, 0.0};
+        const double* __restrict__ wg = wfrag + ((size_t)f * g.NG + it) * NK * 256 + lane;
+#pragma unroll
+        for (int st = 0; st < NK; st++) {
+          const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
+          Pr = mfma4(za[st], b0, Pr);
+          Pi = mfma4(za[st], b1, Pi);
+          Zr = mfma4(za[st], b2, Zr);
+          Zi = mfma4(za[st], b3, Zi);
+        }
+        double* __restrict__ pt = &psh[cur][wt][0][lane];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          pt[(0 + r) * 64] = Pr[r];
+          pt[(4 + r) * 64] = Pi[r];
+          pt[(8 + r) * 64] = Zr[r];
+          pt[(12 + r) * 64] = Zi[r];
+        }
+      }
+    } else if (it > gbeg) {
+      const int grp = it - 1;
+      const int col = grp * 16 + li;
+      if (col < g.NCOL) {
+        const int nx = col / g.NY, iy = col - nx * g.NY;
+        const double fnx = (double)nx, fny = (double)(iy - g.my);
+        const double* __restrict__ pt = &psh[cur ^ 1][wt][0][lane];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const double2* __restrict__ row = tab + (size_t)arow[r] * g.R;
+          const double2 c = cconj(cmul(row[nx], row[g.NX + iy]));
+          const double pr = pt[(0 + r) * 64], pi = pt[(4 + r) * 64];
+          const double zr = pt[(8 + r) * 64], zi = pt[(12 + r) * 64];
+          const double cpi = c.x * pi + c.y * pr;
+          acc0[r] += c.x * pr - c.y * pi;
+          acc1[r] += fnx * cpi;
+          acc2[r] += fny * cpi;
+          acc3[r] += c.x * zi + c.y * zr;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (mma) return;
+  // sum over the 16 columns held by lanes with the same lk
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      acc0[r] += __shfl_xor(acc0[r], o, 64);
+      acc1[r] += __shfl_xor(acc1[r], o, 64);
+      acc2[r] += __shfl_xor(acc2[r], o, 64);
+      acc3[r] += __shfl_xor(acc3[r], o, 64);
+    }
+  }
+  if (li == 0) {
+    const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int a = a0 + lk + 4 * r;
+      if (a < fr.nm) {
+        double* o = fpart + ((size_t)kc * cap_mm + fr.moff + a) * 4;
+        o[0] = acc0[r];
+        o[1] = kx0 * acc1[r];
+        o[2] = ky0 * acc2[r];
+        o[3] = kz0 * acc3[r];
+      }
+    }
+  }
+}
+
 template <int MZ, int A>
 static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int kc, int cap_mm,
                               Work& w) {
@@ -1362,6 +1502,17 @@ static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const Fra
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
+  if (t.bwd_ilp == 5 && mfma_bwd_ok(g)) {  // warp-specialised matrix-core path: 64 atoms per 512-thread block
+    dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
+#define FW(N)                                                                                                 \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL((k_force_mm_ws<N>), grid, dim3(512), 0, s, g, fa, t.kc, cap_mm, w.mm_tab, w.mm_ztab, \
+                       w.wfrag, w.wk0, w.fpart);                                                              \
+    break;
+    switch (g.NK2) { FW(2) FW(4) FW(6) FW(8) FW(10) FW(12) FW(14) FW(16) default: return hipErrorInvalidValue; }
+#undef FW
+    return hipGetLastError();
+  }
   if (t.bwd_ilp >= 3 && mfma_bwd_ok(g)) {  // matrix-core path: 64 (AT=1) or 128 (AT=2) atoms per block
     const int at = t.bwd_ilp == 4 ? 2 : 1;
     dim3 grid((max_nm + 64 * at - 1) / (64 * at), t.kc, fa.n_frames);
@@ -2068,6 +2219,103 @@ __global__ __launch_bounds__(256) void k_finalize_bwd(FrameArg fa, const double*
     g_theta[6 * (size_t)r + t] = ge * mult[t] * (st[4 + t] + w * (qa[QA_DTH_QQ_LR + t] + qa[QA_DTH_QQ_SR + t]));
 }
 
+// Fused forward + adjoint epilogue (one launch after both streams join):
+// blocks below n_mm_blocks sum the MM gradient data of their atoms; the last
+// block of each frame forms phi, field, field gradient and energy of the QM
+// sites and, from the same values, the QM gradients for an upstream gradient
+// of 1 (gE = 1: the stored context is scaled later).
+__global__ __launch_bounds__(256) void k_finish_fused(Grid g, FrameArg fa, int n_mm_blocks, int kc_n, int cap_mm,
+                                                      const double* __restrict__ mm4,
+                                                      const double* __restrict__ fpart,
+                                                      const double* __restrict__ rpart,
+                                                      const double* __restrict__ Q, const double* __restrict__ mu,
+                                                      const double* __restrict__ theta, int qmqm,
+                                                      const double* __restrict__ qacc,
+                                                      const double* __restrict__ facc, double* __restrict__ energy,
+                                                      double* __restrict__ phi, double* __restrict__ efield,
+                                                      double* __restrict__ efgrad, double* __restrict__ site,
+                                                      double* __restrict__ g_mm_xyz, double* __restrict__ g_mm_q,
+                                                      double* __restrict__ g_qm_xyz, double* __restrict__ g_Q,
+                                                      double* __restrict__ g_mu, double* __restrict__ g_theta) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const double V = fr.box[0] * fr.box[1] * fr.box[2];
+  if ((int)blockIdx.x < n_mm_blocks) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= fr.nm) return;
+    const int row = fr.moff + i;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int kc = 0; kc < kc_n; kc++) {
+      const double* p = fpart + ((size_t)kc * cap_mm + row) * 4;
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+      s3 += p[3];
+    }
+    const double q = mm4[(size_t)3 * cap_mm + row];
+    const double* rp = rpart + (size_t)row * 4;
+    g_mm_xyz[3 * (size_t)row + 0] = q * s1 + rp[1];
+    g_mm_xyz[3 * (size_t)row + 1] = q * s2 + rp[2];
+    g_mm_xyz[3 * (size_t)row + 2] = q * s3 + rp[3];
+    if (g_mm_q) g_mm_q[row] = s0 + rp[0] - kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
+    return;
+  }
+  const double bg = -kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
+  const double w = qmqm ? 1.0 : 0.0;
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double esum = 0.0;
+  for (int j = threadIdx.x; j < fr.nq; j += 256) {
+    const int r = fr.qoff + j;
+    const double* qa = qacc + (size_t)r * QA_STRIDE;
+    const double p = qa[QA_PHI_SR] + qa[QA_PHI_LR] + bg;
+    double d[3], h[6];
+    for (int t = 0; t < 3; t++) d[t] = qa[QA_DPHI_SR + t] + qa[QA_DPHI_LR + t];
+    for (int t = 0; t < 6; t++) h[t] = qa[QA_H_SR + t] + qa[QA_H_LR + t];
+    if (phi) phi[r] = p;
+    if (efield)
+      for (int t = 0; t < 3; t++) efield[3 * (size_t)r + t] = -d[t];
+    if (efgrad)
+      for (int t = 0; t < 6; t++) efgrad[6 * (size_t)r + t] = -2.0 * h[t];
+    if (site) {
+      double* o = site + 10 * (size_t)r;
+      o[0] = p;
+      for (int t = 0; t < 3; t++) o[1 + t] = d[t];
+      for (int t = 0; t < 6; t++) o[4 + t] = h[t];
+    }
+    const double* m = mu + 3 * (size_t)r;
+    const double* th = theta + 6 * (size_t)r;
+    esum += Q[r] * p + m[0] * d[0] + m[1] * d[1] + m[2] * d[2] + th[0] * h[0] + th[3] * h[3] + th[5] * h[5] +
+            2.0 * (th[1] * h[1] + th[2] * h[2] + th[4] * h[4]);
+    for (int t = 0; t < 3; t++)
+      g_qm_xyz[3 * (size_t)r + t] =
+          qa[QA_G_QMMM_SR + t] + qa[QA_G_QMMM_LR + t] + w * (qa[QA_G_QQ_LR + t] + qa[QA_G_QQ_SR + t]);
+    g_Q[r] = p + w * (qa[QA_DQ_QQ_LR] + qa[QA_DQ_QQ_SR]);
+    for (int t = 0; t < 3; t++) g_mu[3 * (size_t)r + t] = d[t] + w * (qa[QA_DMU_QQ_LR + t] + qa[QA_DMU_QQ_SR + t]);
+    for (int t = 0; t < 6; t++)
+      g_theta[6 * (size_t)r + t] = mult[t] * (h[t] + w * (qa[QA_DTH_QQ_LR + t] + qa[QA_DTH_QQ_SR + t]));
+  }
+  double v[1] = {esum}, tot[1];
+  block_sum256<1>(v, tot);
+  if (threadIdx.x == 0) {
+    double e = tot[0];
+    if (qmqm) e += facc[f * FA_COUNT + FA_E_QQ_LR] + facc[f * FA_COUNT + FA_E_QQ_SR];
+    energy[f] = e;
+  }
+}
+
+hipError_t launch_finish_fused(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
+                               const double* Q, const double* mu, const double* theta, int qmqm, double* energy,
+                               double* phi, double* efield, double* efgrad, double* site, double* g_mm_xyz,
+                               double* g_mm_q, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
+                               Work& w, hipStream_t s) {
+  const int nb = (max_nm + 255) / 256;
+  dim3 grid(nb + 1, fa.n_frames);
+  hipLaunchKernelGGL(k_finish_fused, grid, dim3(256), 0, s, g, fa, nb, t.kc, cap_mm, w.mm4, w.fpart, w.rpart, Q, mu,
+                     theta, qmqm, w.qacc, w.facc, energy, phi, efield, efgrad, site, g_mm_xyz, g_mm_q, g_qm_xyz, g_Q,
+                     g_mu, g_theta);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
                                double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s) {
   if (max_nq == 0) return hipSuccess;
@@ -2111,21 +2359,21 @@ hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq
 hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, const double* qm_xyz,
                        const double* Q, const double* mu, const double* theta, const double* mm_xyz,
                        const double* mm_q, Work& w, hipStream_t s, int cap_qm, int cap_mm, int mm_tables,
-                       int unit_eff) {
+                       int unit_eff, int parts) {
   const int nmax = max_nq > max_nm ? max_nq : max_nm;
-  if (nmax > 0) {
+  if (nmax > 0 && (parts & PREP_POS)) {
     dim3 grid((nmax + 255) / 256, fa.n_frames);
     hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, mu, theta, w.qm4, cap_qm,
                        w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc, unit_eff ? w.rpart : (double*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (max_nm > 0 && mm_tables) {
+  if (max_nm > 0 && mm_tables && (parts & PREP_MM_TAB)) {
     launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (max_nq > 0) {
+  if (max_nq > 0 && (parts & PREP_QM_TAB)) {
     launch_tab(g, fa, 1, 1, max_nq, w.qm4, cap_qm, w.qm_tab, (double*)nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

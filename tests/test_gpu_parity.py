@@ -77,7 +77,7 @@ def test_fp32_real_space_error_report():
     assert max(errs.values()) < 1e-3
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "3", "4"])
+@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5"])
 def test_backward_kernel_variants(variant, monkeypatch):
     """Every backward kernel variant (VALU Horner with 1 or 2 atoms per lane,
     folded matrix-core contraction with 16 or 32 atoms per wave) meets the
@@ -98,13 +98,16 @@ def test_real_space_cell_list_and_all_pairs(cell_list, monkeypatch):
     _check(wl.make_config(2), cell_list=cell_list)
 
 
-@pytest.mark.parametrize("mode,ct", [("0", "1"), ("1", "1"), ("1", "2"), ("1", "4")])
-def test_forward_kernel_variants(mode, ct, monkeypatch):
+@pytest.mark.parametrize("mode,ct,xcd", [("0", "1", "0"), ("1", "1", "1"), ("1", "2", "0"), ("1", "2", "1"),
+                                         ("1", "4", "1")])
+def test_forward_kernel_variants(mode, ct, xcd, monkeypatch):
     """VALU forward and the folded matrix-core forward with 1, 2 or 4 column
-    tiles per wave (where the z tiles allow it) meet the parity bar, on a
-    ragged atom count and a column count that is not a multiple of 16."""
+    tiles per wave (where the z tiles allow it), in natural and XCD-grouped
+    block order, meet the parity bar, on a ragged atom count and a column
+    count that is not a multiple of 16."""
     monkeypatch.setenv("MPEWALD_FWD", mode)
     monkeypatch.setenv("MPEWALD_FWD_CT", ct)
+    monkeypatch.setenv("MPEWALD_FWD_XCD", xcd)
     _check(wl.random_system(44, 7, 2901, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11)),
            keys=H.FWD_KEYS)
     _check(wl.random_system(45, 5, 1203, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=(5, 5, 3)),

@@ -19,7 +19,7 @@ def test_autotune_cache_and_parity(tmp_path):
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == 1
     entry = json.loads(lines[0])
-    assert {"key", "fwd", "ct", "fwd_target", "bwd", "kc", "times_us"} <= set(entry)
+    assert {"key", "fwd", "ct", "xcd", "fwd_target", "bwd", "kc", "times_us"} <= set(entry)
     print("[tune]", before, "->", plan.describe(), entry["times_us"], flush=True)
     ref = H.oracle_outputs(s)
     got = H.gpu_outputs(s, plan=plan)
