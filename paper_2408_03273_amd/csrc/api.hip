@@ -135,6 +135,7 @@ Grid make_grid(const ewald_params_t& p) {
   g.Zc = pick_zc(g.NZ);
   g.NZP = ((g.NZ + g.Zc - 1) / g.Zc) * g.Zc;
   g.R = g.NX + g.NY + g.NZP;
+  g.NXY = g.NX + g.NY;
   g.NG = (g.NCOL + 15) / 16;
   g.ZKP = 16 * ((2 * g.mz + 15) / 16);
   g.NT = g.ZKP / 16;
@@ -199,7 +200,8 @@ void free_plan(ewald_plan* pl) {
 
 void set_describe(ewald_plan* pl) {
   char buf[256];
-  static const char* bwd[] = {"", "valu-horner-1", "valu-horner-2", "mfma-fold-16", "mfma-fold-32", "mfma-fold-ws"};
+  static const char* bwd[] = {"",           "valu-horner-1", "valu-horner-2", "mfma-fold-16",
+                              "mfma-fold-32", "mfma-fold-ws",  "mfma-fold-eyl"};
   char fwd[64];
   if (pl->t.fwd_mode == 1)
     snprintf(fwd, sizeof(fwd), "mfma-fold ct=%d nt=%d xcd=%d", pl->t.fwd_ct, pl->g.NT, pl->t.fwd_xcd);
@@ -457,8 +459,8 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   // caller stream: MM phase tables and the (small) QM-QM image sums
   LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm, pl->cap_mm,
                    tables, 1, PREP_MM_TAB));
-  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
   HIPCHK(hipEventRecord(pl->ev_mtab, q.s));
+  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
   // caller stream: the forward hot loop
   LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
   {
@@ -522,7 +524,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->t.fwd_ct = mfma_fwd_ct_ok(pl->g, 2) ? 2 : 1;
   pl->t.fwd_xcd = 1;
   pl->t.fwd_target = pl->t.fwd_mode == 1 ? 1024 : 8192;
-  pl->t.bwd_ilp = mfma_bwd_ok(pl->g) ? 4 : 2;
+  pl->t.bwd_ilp = mfma_bwd_eyl_ok(pl->g) ? 6 : mfma_bwd_ok(pl->g) ? 3 : 2;
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
   // atoms per lane) or 3|4 (matrix cores, 16|32 atoms per wave); MPEWALD_FWD =
   // 0|1 (VALU | matrix cores); MPEWALD_FWD_CT = 1|2|4 (matrix-core column
@@ -530,7 +532,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   // forward block count target
   if (const char* e = getenv("MPEWALD_BWD")) {
     const int v = atoi(e);
-    if ((v >= 1 && v <= 2) || (v >= 3 && v <= 5 && mfma_bwd_ok(pl->g))) pl->t.bwd_ilp = v;
+    if ((v >= 1 && v <= 2) || (v >= 3 && v <= 5 && mfma_bwd_ok(pl->g)) || (v == 6 && mfma_bwd_eyl_ok(pl->g)))
+      pl->t.bwd_ilp = v;
   }
   if (const char* e = getenv("MPEWALD_FWD")) {
     const int v = atoi(e);
@@ -572,6 +575,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.qm4, 4 * cq);
   A(w.mm_tab, cm * g.R);
   A(w.mm_ztab, cm * g.ZKP);
+  A(w.mm_xy, cm * g.NXY);
   A(w.qm_tab, cq * g.R);
   A(w.sabc, cf * g.KF * 3);
   A(w.wk, cf * g.KF);
@@ -1010,7 +1014,8 @@ bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
     if (p1 && p2 && p3 && p4 && p5 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 &&
         sscanf(p2, "\"bwd\": %d", &bw) == 1 && sscanf(p3, "\"kc\": %d", &kc) == 1 &&
         sscanf(p4, "\"fwd\": %d", &fm) == 1 && sscanf(p5, "\"ct\": %d", &ct) == 1 && ft >= 64 &&
-        (bw == 1 || bw == 2 || (bw >= 3 && bw <= 5 && mfma_bwd_ok(pl->g))) && kc >= 0 && kc <= pl->cap_kc &&
+        (bw == 1 || bw == 2 || (bw >= 3 && bw <= 5 && mfma_bwd_ok(pl->g)) || (bw == 6 && mfma_bwd_eyl_ok(pl->g))) &&
+        kc >= 0 && kc <= pl->cap_kc &&
         (fm == 0 || (fm == 1 && mfma_fwd_ok(pl->g) && mfma_fwd_ct_ok(pl->g, ct)))) {
       pl->t.fwd_target = ft;
       pl->t.bwd_ilp = bw;
@@ -1154,8 +1159,9 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
         best.fwd_target = c.ft;
       }
     }
-    for (int bw : {2, 3, 4, 5}) {
+    for (int bw : {2, 3, 4, 5, 6}) {
       if (bw >= 3 && !mfma_bwd_ok(plan->g)) continue;
+      if (bw == 6 && !mfma_bwd_eyl_ok(plan->g)) continue;
       for (int kc : {0, 1, 2, 4, 8, 16}) {
         if (kc > plan->cap_kc) continue;
         plan->t = saved;

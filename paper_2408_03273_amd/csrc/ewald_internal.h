@@ -40,6 +40,7 @@ struct Grid {
   int Zc;           // nz chunk of the forward kernel
   int NZP;          // nz padded to a multiple of Zc
   int R;            // complex entries per atom in the phase tables: NX + NY + NZP
+  int NXY;          // complex entries per atom in the compact x/y table: NX + NY
   int NG;           // 16-column tiles of the matrix-core kernels
   int ZKP;          // real z-phase table row: cos(p kz0 z), p=1..mz, then sin, zero padded to a multiple of 16
   int NT;           // ZKP/16: 16-wide z tiles of the matrix-core forward kernel
@@ -86,6 +87,7 @@ struct Work {
   double* qm4;        // [4][cap_qm]  wrapped x,y,z and Q
   double2* mm_tab;    // [cap_mm][R]  e^{i 2 pi n x/L}: x (n=0..mx), y (-my..my), z (-mz..mz, zero padded)
   double* mm_ztab;    // [cap_mm][ZKP] cos(2 pi p z/Lz), p=1..mz | sin(2 pi p z/Lz), p=1..mz | zeros
+  double2* mm_xy;     // [cap_mm][NXY]  x and y parts of mm_tab, compact (matrix-core kernels)
   double2* qm_tab;    // [cap_qm][R]
   double2* sabc;      // [cap_frames][KF][3]  A, B, C of the QM multipoles
   double2* wk;        // [cap_frames][KF]     backward weights (8 pi/V) g(k) S'_QM(k)
@@ -116,7 +118,8 @@ struct Tuning {
   int a_chunk;    // forward atoms per block
   int kc;         // backward column chunks
   int bwd_ilp;    // backward kernel: 1|2 VALU Horner (atoms per lane), 3|4 matrix cores (16|32 atoms per
-                  // wave), 5 matrix cores with separate epilogue waves
+                  // wave), 5 matrix cores with separate epilogue waves, 6 matrix cores
+                  // with the y phases of the block's atoms in LDS
   int fwd_pf;     // VALU forward kernel prefetches the next atom's factors
   int fwd_target; // forward blocks the atom chunking aims for
   int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
@@ -127,6 +130,8 @@ struct Tuning {
 // matrix-core kernels are instantiated for mz <= 32
 inline bool mfma_fwd_ok(const Grid& g) { return g.NT >= 1 && g.NT <= 4; }
 inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
+// the y-phase LDS tile of 64 atoms must fit in 64 KB
+inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && 64 * (g.NY + 1) * 16 <= 65536; }
 // the forward tiles per wave are limited by the LDS of the block reduction
 inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
 inline int fwd_col_groups(const Grid& g, const Tuning& t) {

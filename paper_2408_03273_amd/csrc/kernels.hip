@@ -156,16 +156,18 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
 // 2 log2(n) + kTabRun rounding steps in all, ~1e-15 relative); the rows,
 // contiguous in memory, are then written out with consecutive threads on
 // consecutive entries.
-static constexpr int kTabRun = 8;
+// (run length and LDS row strides chosen so that the 16-byte LDS writes of a
+// wave spread over the banks)
+static constexpr int kTabRun = 7;
 static constexpr int kTabAtoms = 16;
 static constexpr int kTabMaxR = 192;    // complex entries per row held in LDS
 static constexpr int kTabMaxZ = 64;     // real z entries per row held in LDS
 
 __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, int with_ez,
                                                   const double* __restrict__ pos4, int cap, double2* __restrict__ tab,
-                                                  double* __restrict__ ztab) {
-  __shared__ double2 rows[kTabAtoms][kTabMaxR];
-  __shared__ double zrows[kTabAtoms][kTabMaxZ];
+                                                  double* __restrict__ ztab, double2* __restrict__ xy) {
+  __shared__ double2 rows[kTabAtoms][kTabMaxR + 1];
+  __shared__ double zrows[kTabAtoms][kTabMaxZ + 1];
   __shared__ double2 base[kTabAtoms][3];
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
@@ -243,11 +245,13 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
       const int a = e / g.R, c = e - a * g.R;
       o[e] = rows[a][c];
     }
-  } else {
-    const int w = g.NX + g.NY;
-    for (int e = threadIdx.x; e < na * w; e += 256) {
-      const int a = e / w, c = e - a * w;
-      tab[(size_t)(off + a0 + a) * g.R + c] = rows[a][c];
+  }
+  if (xy) {
+    // compact x/y rows (stride NX + NY): one contiguous run of na * NXY entries
+    double2* __restrict__ o = xy + (size_t)(off + a0) * g.NXY;
+    for (int e = threadIdx.x; e < na * g.NXY; e += 256) {
+      const int a = e / g.NXY, c = e - a * g.NXY;
+      o[e] = rows[a][c];
     }
   }
   if (ztab) {
@@ -263,7 +267,8 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
 // Grids whose rows do not fit the LDS tile: one thread per entry, each from its own sincospi.
 __global__ __launch_bounds__(256) void k_prep_tab_direct(Grid g, FrameArg fa, int qm_side, int with_ez,
                                                          const double* __restrict__ pos4, int cap,
-                                                         double2* __restrict__ tab, double* __restrict__ ztab) {
+                                                         double2* __restrict__ tab, double* __restrict__ ztab,
+                                                         double2* __restrict__ xy) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
@@ -301,19 +306,21 @@ __global__ __launch_bounds__(256) void k_prep_tab_direct(Grid g, FrameArg fa, in
     ztab[(size_t)row * g.ZKP + n - 1] = cs;
     ztab[(size_t)row * g.ZKP + g.mz + n - 1] = sn;
   } else {
-    tab[(size_t)row * g.R + u] = make_double2(cs, sn);
+    if (with_ez || ax == 2) tab[(size_t)row * g.R + u] = make_double2(cs, sn);
+    if (xy && ax < 2) xy[(size_t)row * g.NXY + u] = make_double2(cs, sn);
   }
 }
 
+// with_ez: full complex rows into tab; xy (may be null): compact x/y rows; ztab (may be null): real z rows
 static void launch_tab(const Grid& g, const FrameArg& fa, int qm_side, int with_ez, int max_n, const double* pos4,
-                       int cap, double2* tab, double* ztab, hipStream_t s) {
+                       int cap, double2* tab, double* ztab, double2* xy, hipStream_t s) {
   if (g.R <= kTabMaxR && 2 * g.mz <= kTabMaxZ) {
     dim3 grid((max_n + kTabAtoms - 1) / kTabAtoms, fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab, xy);
   } else {
     const long per = g.NX + g.NY + (with_ez ? g.NZP : 0) + (ztab ? g.mz : 0);
     dim3 grid((unsigned)(((long)max_n * per + 255) / 256), fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab_direct, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab);
+    hipLaunchKernelGGL(k_prep_tab_direct, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab, xy);
   }
 }
 
@@ -690,7 +697,7 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
     }
   }
   const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
-  const double2* __restrict__ tb = tab + (size_t)fr.moff * g.R;
+  const double2* __restrict__ tb = tab + (size_t)fr.moff * g.NXY;
   const double* __restrict__ zb = ztab + (size_t)fr.moff * g.ZKP + li;
   // K step: atoms a .. a+3, lane atom a + lk (row k of B and column k of A)
   for (int a = a0 + 4 * wave; a < a1; a += 16) {
@@ -699,7 +706,7 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
     const int ar = ok ? ai : a0;
     // unconditional load of a valid row, then a select: no branch inside the loop
     const double q = qv[ar] * (ok ? 1.0 : 0.0);
-    const double2* __restrict__ row = tb + (size_t)ar * g.R;
+    const double2* __restrict__ row = tb + (size_t)ar * g.NXY;
     double bz[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) bz[nt] = zb[(size_t)ar * g.ZKP + nt * 16];
@@ -806,7 +813,7 @@ template <int CT, int NT>
 static void launch_sfac_mm_mfma_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int a_chunk, int ngc,
                                   int nac, int xcd, int cap_mm, Work& w) {
   hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, xcd, w.mm4, cap_mm,
-                     w.mm_tab, w.mm_ztab, w.spart);
+                     w.mm_xy, w.mm_ztab, w.spart);
 }
 
 static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
@@ -1295,7 +1302,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
     for (int t = 0; t < AT; t++)
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const double2* __restrict__ row = tab + (size_t)arow[t][r] * g.R;
+        const double2* __restrict__ row = tab + (size_t)arow[t][r] * g.NXY;
         ex[t][r] = row[nx];
         ey[t][r] = row[g.NX + iy];
       }
@@ -1375,6 +1382,111 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
   }
 }
 
+// Matrix-core adjoint with the y phases of the block's 64 atoms staged in
+// LDS once: the epilogue reads e^{i ky y} for every (atom, column) of every
+// column group, and from LDS these re-reads no longer compete for L2 with the
+// other blocks (from L2 they spilled to HBM).  The B operand (the folded
+// weights of one frame, ~2 MB at |n| <= 24) is read from L2.  The LDS tile is
+// 64 x (NY + 1) complex entries, dynamic.
+template <int NK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
+    Grid g, FrameArg fa, int kc_n, int cap_mm, const double2* __restrict__ tab, const double* __restrict__ ztab,
+    const double* __restrict__ wfrag, const double2* __restrict__ wk0, double* __restrict__ fpart) {
+  extern __shared__ double2 eysh[];  // [64][NY + 1]
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int ablk = blockIdx.x * 64;
+  if (ablk >= fr.nm) return;  // uniform over the block
+  const int ys = g.NY + 1;
+  for (int e = threadIdx.x; e < 64 * g.NY; e += 256) {
+    const int a = e / g.NY, c = e - a * g.NY;
+    eysh[a * ys + c] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
+  }
+  __syncthreads();
+  const int a0 = ablk + wave * 16;
+  if (a0 >= fr.nm) return;  // no barrier after this point
+  const int kc = blockIdx.y;
+  const int per = (g.NG + kc_n - 1) / kc_n;
+  const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
+  const int li = lane & 15, lk = lane >> 4;
+  double za[NK];
+  {
+    const int aA = min(a0 + li, fr.nm - 1);
+    const double* __restrict__ zr = ztab + (size_t)(fr.moff + aA) * g.ZKP + lk;
+#pragma unroll
+    for (int st = 0; st < NK; st++) za[st] = zr[4 * st];
+  }
+  double acc0[4], acc1[4], acc2[4], acc3[4];
+  int arow[4], erow[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
+    arow[r] = fr.moff + min(a0 + lk + 4 * r, fr.nm - 1);
+    erow[r] = (wave * 16 + lk + 4 * r) * ys;
+  }
+  for (int grp = gbeg; grp < gend; grp++) {
+    const int col = grp * 16 + li;
+    const bool cok = col < g.NCOL;
+    const int colc = cok ? col : g.NCOL - 1;
+    const int nx = colc / g.NY, iy = colc - nx * g.NY;
+    double2 ex[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) ex[r] = tab[(size_t)arow[r] * g.NXY + nx];
+    const double2 w0 = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
+    const double* __restrict__ wg = wfrag + ((size_t)f * g.NG + grp) * NK * 256 + lane;
+    v4d Pr = v4d{w0.x, w0.x, w0.x, w0.x}, Pi = v4d{w0.y, w0.y, w0.y, w0.y};
+    v4d Zr = v4d{0.0, 0.0, 0.0, 0.0}, Zi = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < NK; st++) {
+      const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
+      Pr = mfma4(za[st], b0, Pr);
+      Pi = mfma4(za[st], b1, Pi);
+      Zr = mfma4(za[st], b2, Zr);
+      Zi = mfma4(za[st], b3, Zi);
+    }
+    if (cok) {
+      const double fnx = (double)nx, fny = (double)(iy - g.my);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
+        const double2 c = cconj(cmul(ex[r], eysh[erow[r] + iy]));
+        const double cpi = c.x * Pi[r] + c.y * Pr[r];
+        acc0[r] += c.x * Pr[r] - c.y * Pi[r];
+        acc1[r] += fnx * cpi;
+        acc2[r] += fny * cpi;
+        acc3[r] += c.x * Zi[r] + c.y * Zr[r];
+      }
+    }
+  }
+  // sum over the 16 columns held by lanes with the same lk
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      acc0[r] += __shfl_xor(acc0[r], o, 64);
+      acc1[r] += __shfl_xor(acc1[r], o, 64);
+      acc2[r] += __shfl_xor(acc2[r], o, 64);
+      acc3[r] += __shfl_xor(acc3[r], o, 64);
+    }
+  }
+  if (li == 0) {
+    const double kx0 = 2.0 * kPi * fr.inv_box[0], ky0 = 2.0 * kPi * fr.inv_box[1], kz0 = 2.0 * kPi * fr.inv_box[2];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int a = a0 + lk + 4 * r;
+      if (a < fr.nm) {
+        double* o = fpart + ((size_t)kc * cap_mm + fr.moff + a) * 4;
+        o[0] = acc0[r];
+        o[1] = kx0 * acc1[r];
+        o[2] = ky0 * acc2[r];
+        o[3] = kz0 * acc3[r];
+      }
+    }
+  }
+}
+
 // Warp-specialised matrix-core adjoint: in a block of eight waves, waves 0-3
 // (one 16-atom tile each) only issue the contraction (B operand from L2,
 // where the folded weights stay resident) and write their four accumulator
@@ -1451,7 +1563,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const double* __restrict__ pt = &psh[cur ^ 1][wt][0][lane];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          const double2* __restrict__ row = tab + (size_t)arow[r] * g.R;
+          const double2* __restrict__ row = tab + (size_t)arow[r] * g.NXY;
           const double2 c = cconj(cmul(row[nx], row[g.NX + iy]));
           const double pr = pt[(0 + r) * 64], pi = pt[(4 + r) * 64];
           const double zr = pt[(8 + r) * 64], zi = pt[(12 + r) * 64];
@@ -1502,11 +1614,23 @@ static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const Fra
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
+  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 atoms per block
+    dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
+    const size_t lds = (size_t)64 * (g.NY + 1) * sizeof(double2);
+#define FE(N)                                                                                                    \
+  case N:                                                                                                        \
+    hipLaunchKernelGGL((k_force_mm_eyl<N>), grid, dim3(256), lds, s, g, fa, t.kc, cap_mm, w.mm_xy, w.mm_ztab, \
+                       w.wfrag, w.wk0, w.fpart);                                                                 \
+    break;
+    switch (g.NK2) { FE(2) FE(4) FE(6) FE(8) FE(10) FE(12) FE(14) FE(16) default: return hipErrorInvalidValue; }
+#undef FE
+    return hipGetLastError();
+  }
   if (t.bwd_ilp == 5 && mfma_bwd_ok(g)) {  // warp-specialised matrix-core path: 64 atoms per 512-thread block
     dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
 #define FW(N)                                                                                                 \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_force_mm_ws<N>), grid, dim3(512), 0, s, g, fa, t.kc, cap_mm, w.mm_tab, w.mm_ztab, \
+    hipLaunchKernelGGL((k_force_mm_ws<N>), grid, dim3(512), 0, s, g, fa, t.kc, cap_mm, w.mm_xy, w.mm_ztab, \
                        w.wfrag, w.wk0, w.fpart);                                                              \
     break;
     switch (g.NK2) { FW(2) FW(4) FW(6) FW(8) FW(10) FW(12) FW(14) FW(16) default: return hipErrorInvalidValue; }
@@ -1517,7 +1641,7 @@ hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, i
     const int at = t.bwd_ilp == 4 ? 2 : 1;
     dim3 grid((max_nm + 64 * at - 1) / (64 * at), t.kc, fa.n_frames);
 #define FM(N, AT)                                                                                          \
-  hipLaunchKernelGGL((k_force_mm_mfma<N, AT>), grid, dim3(256), 0, s, g, fa, t.kc, cap_mm, w.mm_tab, w.mm_ztab, \
+  hipLaunchKernelGGL((k_force_mm_mfma<N, AT>), grid, dim3(256), 0, s, g, fa, t.kc, cap_mm, w.mm_xy, w.mm_ztab, \
                      w.wfrag, w.wk0, w.fpart)
 #define FMC(N)              \
   case N:                   \
@@ -2369,12 +2493,12 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
     if (e != hipSuccess) return e;
   }
   if (max_nm > 0 && mm_tables && (parts & PREP_MM_TAB)) {
-    launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, s);
+    launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, w.mm_xy, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (max_nq > 0 && (parts & PREP_QM_TAB)) {
-    launch_tab(g, fa, 1, 1, max_nq, w.qm4, cap_qm, w.qm_tab, (double*)nullptr, s);
+    launch_tab(g, fa, 1, 1, max_nq, w.qm4, cap_qm, w.qm_tab, (double*)nullptr, (double2*)nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

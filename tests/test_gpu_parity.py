@@ -77,7 +77,7 @@ def test_fp32_real_space_error_report():
     assert max(errs.values()) < 1e-3
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5"])
+@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5", "6"])
 def test_backward_kernel_variants(variant, monkeypatch):
     """Every backward kernel variant (VALU Horner with 1 or 2 atoms per lane,
     folded matrix-core contraction with 16 or 32 atoms per wave) meets the
