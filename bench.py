@@ -174,6 +174,7 @@ def main():
     fplan.close()
 
     if not args.no_extras:
+        extra["scf_moments_update"] = _scf_update(make_plan(False), inputs, s, ms)
         extra["plain_path"] = _plain_path(s, dev, nh)
         extra["batch_c4"] = _batch_c4(dev)
 
@@ -193,6 +194,24 @@ def main():
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def _scf_update(plan, inputs, s, step_ms, calls=20):
+    """Moments-only update at fixed geometry (one SCF iteration): energy and
+    dE/d(moments) for new moments, reusing the MM field of one forward call."""
+    import torch
+    x = [t.detach() for t in inputs]
+    _, _, _, _, ctx = plan.forward(*x, want_ctx=True)
+    Q2, mu2, th2 = x[1] * 0.9, x[2] * 1.1, x[3] * 0.95
+    plan.update_moments(ctx, x[0], Q2, mu2, th2, s.nm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        plan.update_moments(ctx, x[0], Q2, mu2, th2, s.nm)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / calls
+    plan.close()
+    return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
 
 
 def _plain_path(s, dev, nh, steps=5):

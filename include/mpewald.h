@@ -138,6 +138,21 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
                               const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
                               double* g_mm_xyz, double* g_mm_q, void* stream);
 
+/* Moments-only update for self-consistent-field iterations (paper: Electronic
+ * Mean-Field Theory: the SCF iterates the QM density, hence the moments, at
+ * fixed geometry, and needs E and the Fock-coupling potential v = dE/d(moments)
+ * each iteration).  ctx must have been filled by ewald_forward with the same
+ * plan, the same QM and MM positions and the same MM charges; only Q, mu and
+ * theta may differ.  The MM field at the QM sites stored in ctx is reused and
+ * only the QM-QM image terms (all k and real space, order-2 truncated) are
+ * recomputed.  Outputs: energy (1, device), and, each may be null, g_Q (Nq),
+ * g_mu (Nq,3), g_theta (Nq,6) = dE/d(moments) as in ewald_backward with gE = 1.
+ * n_mm is the MM count of the forward call (it fixes the ctx layout).
+ * Forces are not produced (positions are fixed). */
+ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz,
+                                    const double* Q, const double* mu, const double* theta, int n_mm,
+                                    double* energy, double* g_Q, double* g_mu, double* g_theta, void* stream);
+
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
  * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or

@@ -876,12 +876,21 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   plan->t.a_chunk = saved.a_chunk;
   use.a_chunk = choose_a_chunk(plan, nms);
   use.kc = choose_kc(plan, total_nm);
-  // frame descriptors with partial-sum slots
+  // frame descriptors with partial-sum slots, largest frames first: the grid
+  // dimension that runs over frames is dispatched in order, so the longest
+  // work starts first and the small frames fill in at the end
+  std::vector<int> order(n_frames);
+  for (int f = 0; f < n_frames; f++) order[f] = f;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long)frames[a].n_mm * 64 + frames[a].n_qm > (long)frames[b].n_mm * 64 + frames[b].n_qm;
+  });
   std::vector<FrameDev> hf(n_frames);
   int slot = 0;
-  for (int f = 0; f < n_frames; f++) {
-    hf[f] = make_frame(frames[f].box, frames[f].n_qm, frames[f].n_mm, frames[f].qm_offset, frames[f].mm_offset, slot);
-    slot += (frames[f].n_mm + use.a_chunk - 1) / use.a_chunk;
+  for (int i = 0; i < n_frames; i++) {
+    const ewald_frame_t& fr = frames[order[i]];
+    hf[i] = make_frame(fr.box, fr.n_qm, fr.n_mm, fr.qm_offset, fr.mm_offset, slot);
+    hf[i].orig = order[i];
+    slot += (fr.n_mm + use.a_chunk - 1) / use.a_chunk;
   }
   const int cells = assign_cells(plan, hf.data(), n_frames) ? 1 : 0;
   // graph key: frames, pointers, mode, stream, tiles
@@ -936,6 +945,53 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   HIPCHK(hipGraphLaunch(plan->gexec, plan->gstream));
   HIPCHK(hipEventRecord(plan->ev_out, plan->gstream));
   HIPCHK(hipStreamWaitEvent(s, plan->ev_out, 0));
+  return EWALD_OK;
+}
+
+// ---------------------------------------------------------------- moments-only update (SCF reuse)
+extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz,
+                                               const double* Q, const double* mu, const double* theta, int n_mm,
+                                               double* energy, double* g_Q, double* g_mu, double* g_theta,
+                                               void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  if (!ctx) return fail(EWALD_ERR_ARG, "null ctx: run ewald_forward with a ctx buffer first");
+  if (!energy) return fail(EWALD_ERR_ARG, "null energy output");
+  if (n_mm < 0) return fail(EWALD_ERR_ARG, "negative atom count");
+  ewald_status_t st = check_arrays(n_qm, 0, qm_xyz, Q, mu, theta, nullptr, nullptr);
+  if (st != EWALD_OK) return st;
+  if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
+    return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  hipStream_t s = (hipStream_t)stream;
+  // QM-side kernels only: a frame without MM atoms makes S_MM and every QM-MM
+  // sum vanish, leaving the QM-QM image terms of the new moments
+  Seq q;
+  q.pl = plan;
+  q.s = s;
+  q.plain = 0;
+  q.fp32 = 0;
+  q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
+  q.cells = 0;
+  q.max_nq = q.total_nq = n_qm;
+  q.max_nm = q.total_nm = 0;
+  q.fa.frames = nullptr;
+  q.fa.f0 = make_frame(plan->p.box, n_qm, 0, 0, 0, 0);
+  q.fa.n_frames = 1;
+  const CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
+  Work& w = plan->w;
+  const Grid& g = plan->g;
+  ewald_plan* pl = plan;
+  st = seq_begin(q, qm_xyz, Q, mu, theta, nullptr, nullptr, 0, 1);
+  if (st != EWALD_OK) return st;
+  LCHK(launch_sfac_qm(g, q.fa, n_qm, Q, mu, theta, w.qeff, nullptr, 0, w, s));
+  if (q.qmqm && n_qm > 0) {
+    Tuning tq = plan->t;
+    tq.a_chunk = 64;  // no MM atoms: no partial-sum slots to read
+    LCHK(launch_reduce_smm(g, tq, q.fa, 0, w.smm, g.KF, w, s));
+    LCHK(launch_project_qm(g, q.fa, n_qm, n_qm, w.smm, g.KF, Q, mu, theta, 1, 1, w, s));
+    LCHK(launch_qmqm(g, q.fa, n_qm, plan->cap_qm, Q, mu, theta, w, s));
+  }
+  LCHK(launch_finalize_moments(q.fa, Q, mu, theta, q.qmqm, cv.site, energy, g_Q, g_mu, g_theta, w, s));
   return EWALD_OK;
 }
 

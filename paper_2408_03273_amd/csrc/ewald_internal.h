@@ -16,6 +16,7 @@ struct FrameDev {
   int slot_base;     // first partial-sum slot of the forward structure-factor kernel
   int nc[3];         // real-space cells per axis (edge >= rcut); 0 = no cell list
   int cell_base;     // first entry of this frame in the cell arrays
+  int orig;          // index of the frame in the caller's list (per-frame outputs)
 };
 
 // Frames are either one descriptor passed by value (single-frame calls) or
@@ -191,6 +192,10 @@ hipError_t launch_finish_fused(const Grid& g, const Tuning& t, const FrameArg& f
                                double* phi, double* efield, double* efgrad, double* site, double* g_mm_xyz,
                                double* g_mm_q, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
                                Work& w, hipStream_t s);
+// moments-only update: energy and dE/d(moments) from the stored MM field and this call's QM-QM sums
+hipError_t launch_finalize_moments(const FrameArg& fa, const double* Q, const double* mu, const double* theta,
+                                   int qmqm, const double* site, double* energy, double* g_Q, double* g_mu,
+                                   double* g_theta, Work& w, hipStream_t s);
 hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* site, const double* gE, int qmqm,
                                double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta, Work& w, hipStream_t s);
 

@@ -43,6 +43,7 @@ DEV FrameDev get_frame(const FrameArg& fa, int f) {
   r.slot_base = uniform_int(r.slot_base);
   for (int a = 0; a < 3; a++) r.nc[a] = uniform_int(r.nc[a]);
   r.cell_base = uniform_int(r.cell_base);
+  r.orig = uniform_int(r.orig);
   return r;
 }
 
@@ -2227,7 +2228,7 @@ __global__ __launch_bounds__(256) void k_finalize_fwd(Grid g, FrameArg fa, const
   if (threadIdx.x == 0) {
     double e = tot[0];
     if (qmqm) e += facc[f * FA_COUNT + FA_E_QQ_LR] + facc[f * FA_COUNT + FA_E_QQ_SR];
-    energy[f] = e;
+    energy[fr.orig] = e;
   }
 }
 
@@ -2423,7 +2424,7 @@ __global__ __launch_bounds__(256) void k_finish_fused(Grid g, FrameArg fa, int n
   if (threadIdx.x == 0) {
     double e = tot[0];
     if (qmqm) e += facc[f * FA_COUNT + FA_E_QQ_LR] + facc[f * FA_COUNT + FA_E_QQ_SR];
-    energy[f] = e;
+    energy[fr.orig] = e;
   }
 }
 
@@ -2437,6 +2438,55 @@ hipError_t launch_finish_fused(const Grid& g, const Tuning& t, const FrameArg& f
   hipLaunchKernelGGL(k_finish_fused, grid, dim3(256), 0, s, g, fa, nb, t.kc, cap_mm, w.mm4, w.fpart, w.rpart, Q, mu,
                      theta, qmqm, w.qacc, w.facc, energy, phi, efield, efgrad, site, g_mm_xyz, g_mm_q, g_qm_xyz, g_Q,
                      g_mu, g_theta);
+  return hipGetLastError();
+}
+
+// Moments-only update at fixed geometry (self-consistent-field reuse): the MM
+// field at each QM site (phi, grad phi, 1/2 grad grad phi, stored by the
+// forward call) is contracted with the new moments; the QM-QM image terms
+// come from the accumulators of this call.  One block per frame.
+__global__ __launch_bounds__(256) void k_finalize_moments(FrameArg fa, const double* __restrict__ Q,
+                                                          const double* __restrict__ mu,
+                                                          const double* __restrict__ theta, int qmqm,
+                                                          const double* __restrict__ site,
+                                                          const double* __restrict__ qacc,
+                                                          const double* __restrict__ facc, double* __restrict__ energy,
+                                                          double* __restrict__ g_Q, double* __restrict__ g_mu,
+                                                          double* __restrict__ g_theta) {
+  const int f = blockIdx.x;
+  const FrameDev fr = get_frame(fa, f);
+  const double w = qmqm ? 1.0 : 0.0;
+  const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
+  double esum = 0.0;
+  for (int j = threadIdx.x; j < fr.nq; j += 256) {
+    const int r = fr.qoff + j;
+    const double* qa = qacc + (size_t)r * QA_STRIDE;
+    const double* st = site + 10 * (size_t)r;
+    const double* m = mu + 3 * (size_t)r;
+    const double* th = theta + 6 * (size_t)r;
+    esum += Q[r] * st[0] + m[0] * st[1] + m[1] * st[2] + m[2] * st[3] + th[0] * st[4] + th[3] * st[7] +
+            th[5] * st[9] + 2.0 * (th[1] * st[5] + th[2] * st[6] + th[4] * st[8]);
+    if (g_Q) g_Q[r] = st[0] + w * (qa[QA_DQ_QQ_LR] + qa[QA_DQ_QQ_SR]);
+    if (g_mu)
+      for (int t = 0; t < 3; t++) g_mu[3 * (size_t)r + t] = st[1 + t] + w * (qa[QA_DMU_QQ_LR + t] + qa[QA_DMU_QQ_SR + t]);
+    if (g_theta)
+      for (int t = 0; t < 6; t++)
+        g_theta[6 * (size_t)r + t] = mult[t] * (st[4 + t] + w * (qa[QA_DTH_QQ_LR + t] + qa[QA_DTH_QQ_SR + t]));
+  }
+  double v[1] = {esum}, tot[1];
+  block_sum256<1>(v, tot);
+  if (threadIdx.x == 0) {
+    double e = tot[0];
+    if (qmqm) e += facc[f * FA_COUNT + FA_E_QQ_LR] + facc[f * FA_COUNT + FA_E_QQ_SR];
+    energy[fr.orig] = e;
+  }
+}
+
+hipError_t launch_finalize_moments(const FrameArg& fa, const double* Q, const double* mu, const double* theta,
+                                   int qmqm, const double* site, double* energy, double* g_Q, double* g_mu,
+                                   double* g_theta, Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_moments, dim3(fa.n_frames), dim3(256), 0, s, fa, Q, mu, theta, qmqm, site, w.qacc,
+                     w.facc, energy, g_Q, g_mu, g_theta);
   return hipGetLastError();
 }
 

@@ -164,6 +164,27 @@ class Plan:
                                           _ptr(g_mm), _ptr(g_q), _stream_ptr(dev)))
         return g_qm, g_Q, g_mu, g_th, g_mm, g_q
 
+    def update_moments(self, ctx, qm_pos, Q, mu, theta, n_mm):
+        """Energy and dE/d(Q, mu, theta) for new QM moments at the geometry of the
+        forward call that filled ctx (self-consistent-field iterations): the
+        stored MM field is reused, only the QM-QM image terms are recomputed."""
+        dev = self.device
+        nq = int(Q.shape[0])
+        f64 = dict(dtype=torch.float64, device=dev)
+        qm_pos = _req(qm_pos, (nq, 3), "qm_pos", dev)
+        Q = _req(Q, (nq,), "Q", dev)
+        mu = _req(mu, (nq, 3), "mu", dev)
+        theta = _req(theta, (nq, 6), "theta", dev)
+        energy = torch.empty((), **f64)
+        g_Q = torch.empty((nq,), **f64)
+        g_mu = torch.empty((nq, 3), **f64)
+        g_th = torch.empty((nq, 6), **f64)
+        with torch.cuda.device(dev):
+            check(self.lib.ewald_moments_update(self.handle, _ptr(ctx), nq, _ptr(qm_pos), _ptr(Q), _ptr(mu),
+                                                _ptr(theta), int(n_mm), _ptr(energy), _ptr(g_Q), _ptr(g_mu),
+                                                _ptr(g_th), _stream_ptr(dev)))
+        return energy, g_Q, g_mu, g_th
+
     def batch(self, frames, qm_pos, Q, mu, theta, mm_pos, mm_q, with_grad=True, out=None):
         """frames: list of dicts with box, n_qm, n_mm, qm_offset, mm_offset over packed arrays.
 
