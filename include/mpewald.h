@@ -27,8 +27,10 @@
  *   - Gradients are dE/dx (forces are minus these).  g_theta is the
  *     derivative with respect to the six stored numbers, so each stored
  *     off-diagonal number receives twice the full-matrix derivative.
- *   - Box: orthorhombic edges; the real-space cutoff must satisfy
- *     rcut <= min(box)/2 (minimum image), reciprocal vectors are
+ *   - Box: orthorhombic edges.  Real space sums every lattice image with
+ *     |r| < rcut: only the minimum image when rcut <= min(box)/2, otherwise
+ *     up to 3 images per direction (rcut below about 3.5 min(box); the
+ *     paper's regime of a cutoff near the box length).  Reciprocal vectors are
  *     k = 2 pi (nx/Lx, ny/Ly, nz/Lz) for every |n_a| <= kmax[a], n != 0.
  *   - Boundary: tin-foil (no surface dipole term); uniform neutralising
  *     background for charged subsystems.
@@ -54,7 +56,7 @@ extern "C" {
 typedef enum {
   EWALD_OK = 0,
   EWALD_ERR_ARG = -1,      /* null pointer, bad size or bad parameter */
-  EWALD_ERR_CUTOFF = -2,   /* rcut > min(box)/2 */
+  EWALD_ERR_CUTOFF = -2,   /* rcut needs more than 3 lattice images per direction */
   EWALD_ERR_CAPACITY = -3, /* more atoms/frames than the plan was set up for */
   EWALD_ERR_HIP = -4,      /* a HIP runtime call failed */
   EWALD_ERR_OOM = -5       /* workspace allocation failed */
@@ -82,7 +84,7 @@ enum {
 typedef struct {
   double box[3];   /* orthorhombic edges */
   double alpha;    /* Ewald splitting parameter (1/length), > 0 */
-  double rcut;     /* real-space cutoff, pairs with |r| < rcut, <= min(box)/2 */
+  double rcut;     /* real-space cutoff: pairs and lattice images with |r| < rcut */
   int kmax[3];     /* reciprocal cube |n_a| <= kmax[a], each >= 1 */
   int precision;   /* EWALD_FP64 or EWALD_FP32_REAL */
   int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT */

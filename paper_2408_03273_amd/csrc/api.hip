@@ -113,12 +113,24 @@ struct ProfScope {
   }
 };
 
+// images per direction beyond the minimum image that the real-space sums must
+// visit: after minimum imaging |d| <= L/2, so |d + nL| < rc needs |n| < rc/L + 1/2
+int real_images(const double box[3], double rcut) {
+  const double mn = std::min(box[0], std::min(box[1], box[2]));
+  return rcut > 0.5 * mn ? (int)std::floor(rcut / mn + 0.5) : 0;
+}
+
+// real space visits up to kMaxImages lattice images per direction (rc up to ~3.5 L)
+constexpr int kMaxImages = 3;
+
 ewald_status_t validate_box(const double box[3], double rcut) {
   for (int a = 0; a < 3; a++)
     if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(EWALD_ERR_ARG, "box[%d] must be positive", a);
-  const double mn = std::min(box[0], std::min(box[1], box[2]));
-  if (rcut > 0.5 * mn)
-    return fail(EWALD_ERR_CUTOFF, "rcut %.6g exceeds half the smallest box edge %.6g", rcut, 0.5 * mn);
+  if (real_images(box, rcut) > kMaxImages) {
+    const double mn = std::min(box[0], std::min(box[1], box[2]));
+    return fail(EWALD_ERR_CUTOFF, "rcut %.6g needs more than %d lattice images of the smallest box edge %.6g", rcut,
+                kMaxImages, mn);
+  }
   return EWALD_OK;
 }
 
@@ -213,7 +225,7 @@ void set_describe(ewald_plan* pl) {
   pl->describe = buf;
 }
 
-FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int slot_base) {
+FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int slot_base, double rcut) {
   FrameDev f;
   memset(&f, 0, sizeof(f));
   for (int a = 0; a < 3; a++) {
@@ -225,6 +237,7 @@ FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int
   f.qoff = qoff;
   f.moff = moff;
   f.slot_base = slot_base;
+  f.nimg = real_images(box, rcut);
   return f;
 }
 
@@ -666,7 +679,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   Tuning saved = plan->t;
   plan->t.a_chunk = q.plain ? 1 << 30 : choose_a_chunk(plan, {n_mm});
   q.fa.frames = nullptr;
-  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
+  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
   if (ctx && !q.plain) {
@@ -734,7 +747,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   Tuning saved = plan->t;
   plan->t.kc = choose_kc(plan, n_mm);
   q.fa.frames = nullptr;
-  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0);
+  q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
   CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
@@ -888,7 +901,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   int slot = 0;
   for (int i = 0; i < n_frames; i++) {
     const ewald_frame_t& fr = frames[order[i]];
-    hf[i] = make_frame(fr.box, fr.n_qm, fr.n_mm, fr.qm_offset, fr.mm_offset, slot);
+    hf[i] = make_frame(fr.box, fr.n_qm, fr.n_mm, fr.qm_offset, fr.mm_offset, slot, plan->p.rcut);
     hf[i].orig = order[i];
     slot += (fr.n_mm + use.a_chunk - 1) / use.a_chunk;
   }
@@ -975,7 +988,7 @@ extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx
   q.max_nq = q.total_nq = n_qm;
   q.max_nm = q.total_nm = 0;
   q.fa.frames = nullptr;
-  q.fa.f0 = make_frame(plan->p.box, n_qm, 0, 0, 0, 0);
+  q.fa.f0 = make_frame(plan->p.box, n_qm, 0, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   const CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
   Work& w = plan->w;
@@ -1161,7 +1174,7 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     q.max_nq = q.total_nq = nq;
     q.max_nm = q.total_nm = n_mm;
     q.fa.frames = nullptr;
-    q.fa.f0 = make_frame(plan->p.box, nq, n_mm, 0, 0, 0);
+    q.fa.f0 = make_frame(plan->p.box, nq, n_mm, 0, 0, 0, plan->p.rcut);
     q.fa.n_frames = 1;
     st = seq_begin(q, dqp, dQ, dmu, dth, dm, dq, 2, 1);
     if (st != EWALD_OK) goto done;

@@ -17,6 +17,7 @@ struct FrameDev {
   int nc[3];         // real-space cells per axis (edge >= rcut); 0 = no cell list
   int cell_base;     // first entry of this frame in the cell arrays
   int orig;          // index of the frame in the caller's list (per-frame outputs)
+  int nimg;          // real-space lattice images per direction beyond the minimum image (rc > L/2)
 };
 
 // Frames are either one descriptor passed by value (single-frame calls) or

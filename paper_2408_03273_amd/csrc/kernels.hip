@@ -44,6 +44,7 @@ DEV FrameDev get_frame(const FrameArg& fa, int f) {
   for (int a = 0; a < 3; a++) r.nc[a] = uniform_int(r.nc[a]);
   r.cell_base = uniform_int(r.cell_base);
   r.orig = uniform_int(r.orig);
+  r.nimg = uniform_int(r.nimg);
   return r;
 }
 
@@ -1740,47 +1741,53 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
   const double* mz_ = mm4 + (size_t)2 * cap_mm + fr.moff;
   const double* mq_ = mm4 + (size_t)3 * cap_mm + fr.moff;
   for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-    double dx = X - mx_[i], dy = Y - my_[i], dz = Zc - mz_[i];
-    min_image(dx, dy, dz, fr);
-    const double r2d = dx * dx + dy * dy + dz * dz;
-    if (!(r2d < rc2) || r2d == 0.0) continue;
-    const T x = (T)dx, y = (T)dy, z = (T)dz;
-    const Radial<T> R = radial<T>((T)r2d, a);
-    const T q = (T)mq_[i];
-    if (BWD != 1) {
-      acc[0] += (double)(q * R.f1);
-      acc[1] += (double)(-q * x * R.f3);
-      acc[2] += (double)(-q * y * R.f3);
-      acc[3] += (double)(-q * z * R.f3);
-      const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
-      acc[4] += (double)(h5 * x * x - h3);
-      acc[5] += (double)(h5 * x * y);
-      acc[6] += (double)(h5 * x * z);
-      acc[7] += (double)(h5 * y * y - h3);
-      acc[8] += (double)(h5 * y * z);
-      acc[9] += (double)(h5 * z * z - h3);
-    }
-    if (BWD != 0) {
-      // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
-      const T md = m0 * x + m1 * y + m2 * z;
-      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
-      const T dtd = x * thx + y * thy + z * thz;
-      const T tr = t0 + t3 + t5;
-      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
-      const T s2 = -R.f3;
-      const T s3 = T(3) * R.f5;
-      const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
-                   gz = (double)(s1 * z + s2 * m2 + s3 * thz);
-      acc[OB + 0] += (double)q * gx;
-      acc[OB + 1] += (double)q * gy;
-      acc[OB + 2] += (double)q * gz;
-      if (rpart) {
-        // MM side: potential of the effective moments per unit charge, and -q g
-        double* o = rpart + (size_t)(fr.moff + i) * 4;
-        atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
-        atomicAdd(&o[1], -(double)q * gx);
-        atomicAdd(&o[2], -(double)q * gy);
-        atomicAdd(&o[3], -(double)q * gz);
+    double bx = X - mx_[i], by = Y - my_[i], bz = Zc - mz_[i];
+    min_image(bx, by, bz, fr);
+    const int n1_ = 2 * fr.nimg + 1;
+    for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
+      // lattice images within the cutoff (only the minimum image when rc <= L/2)
+      const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
+      const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
+      const double r2d = dx * dx + dy * dy + dz * dz;
+      if (!(r2d < rc2) || r2d == 0.0) continue;
+      const T x = (T)dx, y = (T)dy, z = (T)dz;
+      const Radial<T> R = radial<T>((T)r2d, a);
+      const T q = (T)mq_[i];
+      if (BWD != 1) {
+        acc[0] += (double)(q * R.f1);
+        acc[1] += (double)(-q * x * R.f3);
+        acc[2] += (double)(-q * y * R.f3);
+        acc[3] += (double)(-q * z * R.f3);
+        const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
+        acc[4] += (double)(h5 * x * x - h3);
+        acc[5] += (double)(h5 * x * y);
+        acc[6] += (double)(h5 * x * z);
+        acc[7] += (double)(h5 * y * y - h3);
+        acc[8] += (double)(h5 * y * z);
+        acc[9] += (double)(h5 * z * z - h3);
+      }
+      if (BWD != 0) {
+        // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
+        const T md = m0 * x + m1 * y + m2 * z;
+        const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+        const T dtd = x * thx + y * thy + z * thz;
+        const T tr = t0 + t3 + t5;
+        const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+        const T s2 = -R.f3;
+        const T s3 = T(3) * R.f5;
+        const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
+                     gz = (double)(s1 * z + s2 * m2 + s3 * thz);
+        acc[OB + 0] += (double)q * gx;
+        acc[OB + 1] += (double)q * gy;
+        acc[OB + 2] += (double)q * gz;
+        if (rpart) {
+          // MM side: potential of the effective moments per unit charge, and -q g
+          double* o = rpart + (size_t)(fr.moff + i) * 4;
+          atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
+          atomicAdd(&o[1], -(double)q * gx);
+          atomicAdd(&o[2], -(double)q * gy);
+          atomicAdd(&o[3], -(double)q * gz);
+        }
       }
     }
   }
@@ -1834,28 +1841,34 @@ __global__ __launch_bounds__(256) void k_real_mm(Grid g, FrameArg fa, const doub
   double aphi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
   for (int j = 0; j < fr.nq; j++) {
     const int r = fr.qoff + j;
-    double dx = qm4[r] - X, dy = qm4[(size_t)cap_qm + r] - Y, dz = qm4[(size_t)2 * cap_qm + r] - Zc;
-    min_image(dx, dy, dz, fr);
-    const double r2d = dx * dx + dy * dy + dz * dz;
-    if (!(r2d < rc2) || r2d == 0.0) continue;
-    const T x = (T)dx, y = (T)dy, z = (T)dz;
-    const Radial<T> R = radial<T>((T)r2d, a);
-    const double* qe = qeff + 10 * (size_t)r;
-    const T Qe = (T)qe[0], m0 = (T)qe[1], m1 = (T)qe[2], m2 = (T)qe[3];
-    const T t0 = (T)qe[4], t1 = (T)qe[5], t2 = (T)qe[6], t3 = (T)qe[7], t4 = (T)qe[8], t5 = (T)qe[9];
-    const T md = m0 * x + m1 * y + m2 * z;
-    const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
-    const T dtd = x * thx + y * thy + z * thz;
-    const T tr = t0 + t3 + t5;
-    // energy per unit MM charge: Q psi0 + mu.psi1 + theta:psi2
-    aphi += (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
-    const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
-    const T s2 = -R.f3;
-    const T s3 = T(3) * R.f5;
-    // r depends on -R_mm
-    gx -= (double)(s1 * x + s2 * m0 + s3 * thx);
-    gy -= (double)(s1 * y + s2 * m1 + s3 * thy);
-    gz -= (double)(s1 * z + s2 * m2 + s3 * thz);
+    double bx = qm4[r] - X, by = qm4[(size_t)cap_qm + r] - Y, bz = qm4[(size_t)2 * cap_qm + r] - Zc;
+    min_image(bx, by, bz, fr);
+    const int n1_ = 2 * fr.nimg + 1;
+    for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
+      // lattice images within the cutoff (only the minimum image when rc <= L/2)
+      const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
+      const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
+      const double r2d = dx * dx + dy * dy + dz * dz;
+      if (!(r2d < rc2) || r2d == 0.0) continue;
+      const T x = (T)dx, y = (T)dy, z = (T)dz;
+      const Radial<T> R = radial<T>((T)r2d, a);
+      const double* qe = qeff + 10 * (size_t)r;
+      const T Qe = (T)qe[0], m0 = (T)qe[1], m1 = (T)qe[2], m2 = (T)qe[3];
+      const T t0 = (T)qe[4], t1 = (T)qe[5], t2 = (T)qe[6], t3 = (T)qe[7], t4 = (T)qe[8], t5 = (T)qe[9];
+      const T md = m0 * x + m1 * y + m2 * z;
+      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+      const T dtd = x * thx + y * thy + z * thz;
+      const T tr = t0 + t3 + t5;
+      // energy per unit MM charge: Q psi0 + mu.psi1 + theta:psi2
+      aphi += (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
+      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+      const T s2 = -R.f3;
+      const T s3 = T(3) * R.f5;
+      // r depends on -R_mm
+      gx -= (double)(s1 * x + s2 * m0 + s3 * thx);
+      gy -= (double)(s1 * y + s2 * m1 + s3 * thy);
+      gz -= (double)(s1 * z + s2 * m2 + s3 * thz);
+    }
   }
   double* o = rpart + (size_t)row * 4;
   o[0] = aphi;
@@ -2115,49 +2128,56 @@ __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double*
   double v[14];
   for (int t = 0; t < 14; t++) v[t] = 0.0;
   for (int b = threadIdx.x; b < fr.nq; b += 256) {
-    if (b == a) continue;
+    // a site's own images count when the cutoff exceeds the box (r = 0 is excluded below)
+    if (b == a && fr.nimg == 0) continue;
     const int rb = fr.qoff + b;
-    double x = Xa - qm4[rb], y = Ya - qm4[(size_t)cap_qm + rb], z = Za - qm4[(size_t)2 * cap_qm + rb];
-    min_image(x, y, z, fr);
-    const double r2 = x * x + y * y + z * z;
-    if (!(r2 < rc2) || r2 == 0.0) continue;
-    const Radial<double> R = radial<double>(r2, al);
-    const double Qb = Q[rb];
-    const double mb0 = mu[3 * (size_t)rb], mb1 = mu[3 * (size_t)rb + 1], mb2 = mu[3 * (size_t)rb + 2];
-    const double* thb = theta + 6 * (size_t)rb;
-    const double c0 = Qb * ma0 - Qa * mb0, c1 = Qb * ma1 - Qa * mb1, c2 = Qb * ma2 - Qa * mb2;
-    double sm[6];
-    for (int t = 0; t < 6; t++) sm[t] = Qb * tha[t] + Qa * thb[t];
-    const double cd = c0 * x + c1 * y + c2 * z;
-    const double sx = sm[0] * x + sm[1] * y + sm[2] * z, sy = sm[1] * x + sm[3] * y + sm[4] * z,
-                 sz = sm[2] * x + sm[4] * y + sm[5] * z;
-    const double dsd = x * sx + y * sy + z * sz, trs = sm[0] + sm[3] + sm[5];
-    const double mad = ma0 * x + ma1 * y + ma2 * z, mbd = mb0 * x + mb1 * y + mb2 * z;
-    const double mab = ma0 * mb0 + ma1 * mb1 + ma2 * mb2;
-    const double P = Qa * Qb * R.f1 - cd * R.f3 + (1.5 * dsd * R.f5 - 0.5 * trs * R.f3) -
-                     (3.0 * mad * mbd * R.f5 - mab * R.f3);
-    v[0] += 0.5 * P;
-    // dP/dr = QaQb psi1 + 2 c.psi2 + 3 s:psi3 - 6 mu_a.psi3.mu_b
-    const double s1 = -Qa * Qb * R.f3 + 3.0 * cd * R.f5 + 1.5 * trs * R.f5 - 7.5 * dsd * R.f7 -
-                      3.0 * (mab * R.f5 - 5.0 * mad * mbd * R.f7);
-    const double sc = -R.f3, ss = 3.0 * R.f5, smu = -3.0 * R.f5;
-    v[1] += s1 * x + sc * c0 + ss * sx + smu * (ma0 * mbd + mb0 * mad);
-    v[2] += s1 * y + sc * c1 + ss * sy + smu * (ma1 * mbd + mb1 * mad);
-    v[3] += s1 * z + sc * c2 + ss * sz + smu * (ma2 * mbd + mb2 * mad);
-    const double thbx = thb[0] * x + thb[1] * y + thb[2] * z, thby = thb[1] * x + thb[3] * y + thb[4] * z,
-                 thbz = thb[2] * x + thb[4] * y + thb[5] * z;
-    const double dtbd = x * thbx + y * thby + z * thbz, trb = thb[0] + thb[3] + thb[5];
-    v[4] += Qb * R.f1 + mbd * R.f3 + (1.5 * dtbd * R.f5 - 0.5 * trb * R.f3);
-    v[5] += -Qb * x * R.f3 - (3.0 * x * mbd * R.f5 - mb0 * R.f3);
-    v[6] += -Qb * y * R.f3 - (3.0 * y * mbd * R.f5 - mb1 * R.f3);
-    v[7] += -Qb * z * R.f3 - (3.0 * z * mbd * R.f5 - mb2 * R.f3);
-    const double h5 = 1.5 * Qb * R.f5, h3 = 0.5 * Qb * R.f3;
-    v[8] += h5 * x * x - h3;
-    v[9] += h5 * x * y;
-    v[10] += h5 * x * z;
-    v[11] += h5 * y * y - h3;
-    v[12] += h5 * y * z;
-    v[13] += h5 * z * z - h3;
+    double bx = Xa - qm4[rb], by = Ya - qm4[(size_t)cap_qm + rb], bz = Za - qm4[(size_t)2 * cap_qm + rb];
+    min_image(bx, by, bz, fr);
+    const int n1_ = 2 * fr.nimg + 1;
+    for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
+      // lattice images within the cutoff (only the minimum image when rc <= L/2)
+      const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
+      const double x = bx + ix_ * fr.box[0], y = by + iy_ * fr.box[1], z = bz + iz_ * fr.box[2];
+      const double r2 = x * x + y * y + z * z;
+      if (!(r2 < rc2) || r2 == 0.0) continue;
+      const Radial<double> R = radial<double>(r2, al);
+      const double Qb = Q[rb];
+      const double mb0 = mu[3 * (size_t)rb], mb1 = mu[3 * (size_t)rb + 1], mb2 = mu[3 * (size_t)rb + 2];
+      const double* thb = theta + 6 * (size_t)rb;
+      const double c0 = Qb * ma0 - Qa * mb0, c1 = Qb * ma1 - Qa * mb1, c2 = Qb * ma2 - Qa * mb2;
+      double sm[6];
+      for (int t = 0; t < 6; t++) sm[t] = Qb * tha[t] + Qa * thb[t];
+      const double cd = c0 * x + c1 * y + c2 * z;
+      const double sx = sm[0] * x + sm[1] * y + sm[2] * z, sy = sm[1] * x + sm[3] * y + sm[4] * z,
+                   sz = sm[2] * x + sm[4] * y + sm[5] * z;
+      const double dsd = x * sx + y * sy + z * sz, trs = sm[0] + sm[3] + sm[5];
+      const double mad = ma0 * x + ma1 * y + ma2 * z, mbd = mb0 * x + mb1 * y + mb2 * z;
+      const double mab = ma0 * mb0 + ma1 * mb1 + ma2 * mb2;
+      const double P = Qa * Qb * R.f1 - cd * R.f3 + (1.5 * dsd * R.f5 - 0.5 * trs * R.f3) -
+                       (3.0 * mad * mbd * R.f5 - mab * R.f3);
+      v[0] += 0.5 * P;
+      // dP/dr = QaQb psi1 + 2 c.psi2 + 3 s:psi3 - 6 mu_a.psi3.mu_b
+      const double s1 = -Qa * Qb * R.f3 + 3.0 * cd * R.f5 + 1.5 * trs * R.f5 - 7.5 * dsd * R.f7 -
+                        3.0 * (mab * R.f5 - 5.0 * mad * mbd * R.f7);
+      const double sc = -R.f3, ss = 3.0 * R.f5, smu = -3.0 * R.f5;
+      v[1] += s1 * x + sc * c0 + ss * sx + smu * (ma0 * mbd + mb0 * mad);
+      v[2] += s1 * y + sc * c1 + ss * sy + smu * (ma1 * mbd + mb1 * mad);
+      v[3] += s1 * z + sc * c2 + ss * sz + smu * (ma2 * mbd + mb2 * mad);
+      const double thbx = thb[0] * x + thb[1] * y + thb[2] * z, thby = thb[1] * x + thb[3] * y + thb[4] * z,
+                   thbz = thb[2] * x + thb[4] * y + thb[5] * z;
+      const double dtbd = x * thbx + y * thby + z * thbz, trb = thb[0] + thb[3] + thb[5];
+      v[4] += Qb * R.f1 + mbd * R.f3 + (1.5 * dtbd * R.f5 - 0.5 * trb * R.f3);
+      v[5] += -Qb * x * R.f3 - (3.0 * x * mbd * R.f5 - mb0 * R.f3);
+      v[6] += -Qb * y * R.f3 - (3.0 * y * mbd * R.f5 - mb1 * R.f3);
+      v[7] += -Qb * z * R.f3 - (3.0 * z * mbd * R.f5 - mb2 * R.f3);
+      const double h5 = 1.5 * Qb * R.f5, h3 = 0.5 * Qb * R.f3;
+      v[8] += h5 * x * x - h3;
+      v[9] += h5 * x * y;
+      v[10] += h5 * x * z;
+      v[11] += h5 * y * y - h3;
+      v[12] += h5 * y * z;
+      v[13] += h5 * z * z - h3;
+    }
   }
   double tot[14];
   block_sum256<14>(v, tot);

@@ -53,8 +53,9 @@ def _params(**kw):
     (dict(alpha=0.0), _lib.EWALD_ERR_ARG),
     (dict(alpha=-1.0), _lib.EWALD_ERR_ARG),
     (dict(rcut=0.0), _lib.EWALD_ERR_ARG),
-    (dict(rcut=10.5), _lib.EWALD_ERR_CUTOFF),
-    (dict(box=(20.0, 15.0, 20.0), rcut=8.0), _lib.EWALD_ERR_CUTOFF),
+    # more than 3 lattice images per direction beyond the minimum image
+    (dict(rcut=75.0), _lib.EWALD_ERR_CUTOFF),
+    (dict(box=(20.0, 15.0, 20.0), rcut=55.0), _lib.EWALD_ERR_CUTOFF),
     (dict(kmax=(0, 8, 8)), _lib.EWALD_ERR_ARG),
     (dict(box=(20.0, -1.0, 20.0)), _lib.EWALD_ERR_ARG),
     (dict(precision=7), _lib.EWALD_ERR_ARG),

@@ -120,3 +120,14 @@ def test_large_kgrid_valu_kernels_and_direct_tables():
     kernel."""
     s = wl.random_system(46, 4, 420, box=(21.0, 23.0, 25.0), alpha=0.5, rcut=9.0, kmax=(30, 40, 34))
     _check(s)
+
+
+@pytest.mark.parametrize("rcut", [7.5, 11.0, 19.0])
+def test_cutoff_beyond_half_box_sums_lattice_images(rcut):
+    """The paper's regime: a real-space cutoff near or beyond the box length
+    (few k vectors).  Real space then visits every lattice image within the
+    cutoff, for QM-MM pairs, QM-QM pairs and a site's own images, as the
+    oracle does (12 A box: rcut 7.5 -> 1 image, 11 -> 1, 19 -> 2 per direction)."""
+    s = wl.random_system(47, 6, 450, box=(12.0, 12.5, 13.0), alpha=0.2, rcut=rcut, kmax=(5, 5, 6))
+    _check(s)
+    _check(s, precision="fp32_real", tol=1e-4)
