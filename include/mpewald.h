@@ -140,6 +140,16 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
                               const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
                               double* g_mm_xyz, double* g_mm_q, void* stream);
 
+/* Ewald parameters for a target accuracy (paper: Computational Details, the
+ * Ewald parameters are estimated for a given accuracy with a real-space cutoff
+ * of about the box length).  Given box and rcut, returns the smallest alpha
+ * whose real-space truncation tail at rcut is below tol, and per axis the
+ * smallest kmax whose reciprocal tail at k = 2 pi kmax / L is below tol.  The
+ * tails are those of the order-2 screened tensors relative to the unscreened
+ * term: erfc(a r) + (2/sqrt(pi)) a r e^{-a^2 r^2} (1 + 2/3 (a r)^2) and
+ * e^{-k^2/4a^2} (1 + k^2/4a^2).  tol in (0, 0.1).  Host only; no plan needed. */
+ewald_status_t ewald_suggest_params(const double box[3], double rcut, double tol, double* alpha, int kmax[3]);
+
 /* Moments-only update for self-consistent-field iterations (paper: Electronic
  * Mean-Field Theory: the SCF iterates the QM density, hence the moments, at
  * fixed geometry, and needs E and the Fock-coupling potential v = dE/d(moments)

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "EWALD_OK", -1: "EWALD_ERR_ARG", -2: "EWALD_ERR_CUTOFF", -3: 
 
 # every symbol the public header declares
 EXPORTED = ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_ctx_bytes", "ewald_forward", "ewald_backward",
-            "ewald_moments_update", "ewald_batch", "ewald_autotune", "ewald_profile_report", "ewald_plan_describe",
+            "ewald_moments_update", "ewald_suggest_params", "ewald_batch", "ewald_autotune", "ewald_profile_report", "ewald_plan_describe",
             "ewald_last_error", "ewald_version")
 
 
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_ctx_bytes.restype = ctypes.c_size_t
     lib.ewald_forward.argtypes = [vp, ip, vp, vp, vp, vp, ip, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ewald_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, ip, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ewald_suggest_params.argtypes = [ctypes.c_double * 3, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int * 3]
     lib.ewald_moments_update.argtypes = [vp, vp, ip, vp, vp, vp, vp, ip, vp, vp, vp, vp, vp]
     lib.ewald_batch.argtypes = [vp, ip, ctypes.POINTER(EwaldFrame), vp, vp, vp, vp, vp, vp, ip, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
@@ -83,7 +84,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_version.argtypes = []
     lib.ewald_version.restype = ctypes.c_char_p
     for name in ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_forward", "ewald_backward",
-                 "ewald_moments_update", "ewald_batch", "ewald_autotune", "ewald_profile_report"):
+                 "ewald_moments_update", "ewald_suggest_params", "ewald_batch", "ewald_autotune", "ewald_profile_report"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -961,6 +961,50 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   return EWALD_OK;
 }
 
+// ---------------------------------------------------------------- parameter suggestion
+// Truncation tails of the screened sums, relative to the unscreened term at
+// the same distance or wave number.  Real space: the order-2 screened tensor
+// at r = rcut carries erfc(a r) + (2/sqrt(pi)) a r e^{-a^2 r^2} (1 + 2/3 (a r)^2);
+// reciprocal space: the order-2 contraction k.theta.k multiplies the
+// Gaussian weight e^{-k^2/4a^2} by (k/2a)^2 relative to the charge term.
+namespace {
+double real_tail(double a, double rc) {
+  const double x = a * rc;
+  return std::erfc(x) + 1.1283791670955126 * x * std::exp(-x * x) * (1.0 + 2.0 / 3.0 * x * x);
+}
+double recip_tail(double a, double k) {
+  const double y = k / (2.0 * a);
+  return std::exp(-y * y) * (1.0 + y * y);
+}
+}  // namespace
+
+extern "C" ewald_status_t ewald_suggest_params(const double box[3], double rcut, double tol, double* alpha,
+                                               int kmax[3]) {
+  g_last_error.clear();
+  if (!box || !alpha || !kmax) return fail(EWALD_ERR_ARG, "null argument");
+  for (int a = 0; a < 3; a++)
+    if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(EWALD_ERR_ARG, "box[%d] must be positive", a);
+  if (!(rcut > 0.0) || !std::isfinite(rcut)) return fail(EWALD_ERR_ARG, "rcut must be positive");
+  if (!(tol > 0.0) || !(tol < 0.1)) return fail(EWALD_ERR_ARG, "tol must be in (0, 0.1)");
+  // smallest alpha whose real-space tail at rcut is below tol (the tail falls with alpha)
+  double lo = 1e-6 / rcut, hi = 50.0 / rcut;
+  if (real_tail(hi, rcut) > tol) return fail(EWALD_ERR_ARG, "tol %.3g below what FP64 real space resolves", tol);
+  for (int it = 0; it < 200; it++) {
+    const double mid = 0.5 * (lo + hi);
+    (real_tail(mid, rcut) > tol ? lo : hi) = mid;
+  }
+  *alpha = hi;
+  // per axis the smallest cube edge whose reciprocal tail at k = 2 pi m / L is below tol
+  for (int a = 0; a < 3; a++) {
+    int m = 1;
+    while (recip_tail(hi, 2.0 * M_PI * m / box[a]) > tol && m < 256) m++;
+    if (m >= 256 && recip_tail(hi, 2.0 * M_PI * m / box[a]) > tol)
+      return fail(EWALD_ERR_ARG, "box[%d] needs more than 256 reciprocal vectors per direction at tol %.3g", a, tol);
+    kmax[a] = m;
+  }
+  return EWALD_OK;
+}
+
 // ---------------------------------------------------------------- moments-only update (SCF reuse)
 extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz,
                                                const double* Q, const double* mu, const double* theta, int n_mm,

@@ -62,6 +62,17 @@ class EwaldConfig:
     cell_list: bool = True    # real space over cells of edge >= rcut when the box has >= 3 per axis
 
 
+def suggest_params(box, rcut: float, tol: float):
+    """(alpha, (mx, my, mz)) for a target truncation accuracy tol at this
+    real-space cutoff (host-side estimate of the library; no GPU needed)."""
+    lib = _lib.load()
+    b = (ctypes.c_double * 3)(*[float(x) for x in box])
+    alpha = ctypes.c_double()
+    km = (ctypes.c_int * 3)()
+    check(lib.ewald_suggest_params(b, float(rcut), float(tol), ctypes.byref(alpha), km))
+    return alpha.value, tuple(km)
+
+
 class Plan:
     """Owns a library plan (workspace on one device)."""
 
