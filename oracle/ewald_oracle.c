@@ -45,6 +45,10 @@
  *    the half-space nx>0 | (nx=0 & ny>0) | (nx=ny=0 & nz>0) with weight 2.
  *  - Real space: every lattice image with |r| < rcut (strict), all images.
  *
+ * oracle_region (end of file) adds the region-I / region-II split: the bare
+ * direct sums over region I that the SCF quantities subtract from the Ewald
+ * sums, and the Gaussian-smeared MM charge correction.
+ *
  * Summation uses long double accumulators.  Phases e^{i k.R} are formed as
  * the product of three per-axis factors, each evaluated directly with
  * cos/sin of n*2*pi*x/L (no recurrences).
@@ -644,4 +648,253 @@ int oracle_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ======================================================================
+ * Region-I / region-II split (main text: periodic QM/MM multipole energy,
+ * the Gaussian-charge correction; SI: bare tensors T, T_a, T_ab, T_abc and
+ * the screened T-hat(kappa_i) with f1, f3, f5, f7).
+ *
+ * The Ewald sums above run over the whole lattice.  The quantities the SCF
+ * consumes are those of region II only, obtained by subtracting the finite
+ * direct sums over region I:
+ *
+ *   E_qq_bare = -1/2 sum_{a != b in QM} P_T(a, b)         unit-cell QM pairs,
+ *               same pair form as the Ewald QM-QM term with bare tensors
+ *   E_mm_bare = - sum_{(i,n) in MM(I)} sum_j q_i [Q_j T + mu_j.T_a + theta_j:T_ab]
+ *   E_gauss   = - sum_{(i,n) in MM(II), kappa_i > 0, |r| < r_gauss} sum_j
+ *                 q_i [Q_j That + mu_j.That_a + theta_j:That_ab]   (kappa = kappa_i)
+ *
+ * with r = R_j - (R_i + n L), C = arithmetic mean of the QM positions, and
+ * MM(I) = { (i, n) : |R_i + n L - C| < r_region }, every lattice translate n
+ * of every MM atom (the sphere may be larger than the cell), MM(II) its
+ * complement.  The bare tensors are those of erfc(kappa r)/r at kappa = 0.
+ * Readings frozen here: QM positions are used as passed (the QM subsystem
+ * is one piece, QM-QM pair vectors and C are not wrapped); kappa_i <= 0 marks
+ * a point charge, which has no Gaussian correction; r_gauss is one pair
+ * cutoff for every Gaussian charge (the correction decays like erfc).
+ *
+ * Outputs (overwritten): energy[3] = {E_qq_bare, E_mm_bare, E_gauss};
+ * phi, dphi, hphi: the correction to the MM potential, its gradient and
+ * half Hessian at the QM sites (the MM(I) and Gaussian terms); g_*: the
+ * gradient of E_qq_bare + E_mm_bare + E_gauss; counts[2] = {region-I images,
+ * Gaussian (QM, MM image) pairs}.
+ * ====================================================================== */
+typedef struct {
+  double box[3];
+  double r_region;
+  double r_gauss;
+} oracle_region_t;
+
+/* accumulate one (QM site j, MM image) pair with tensors of erfc(kappa r)/r,
+ * scaled by s (= -1 for the subtractions) */
+static void region_pair(const double r[3], double kappa, double s, double qi, double Qj, const double* mj,
+                        double th[3][3], long double* phi10, long double* gq3, long double* gm4, long double* e) {
+  double p0, p1[3], p2[3][3], p3[3][3][3];
+  real_tensors(r, kappa, &p0, p1, p2, p3);
+  phi10[0] += s * qi * p0;
+  for (int a = 0; a < 3; a++) phi10[1 + a] += s * qi * p1[a];
+  for (int a = 0; a < 3; a++)
+    for (int b = a; b < 3; b++) phi10[4 + sym6(a, b)] += s * qi * p2[a][b];
+  double en = Qj * p0;
+  for (int a = 0; a < 3; a++) en += mj[a] * p1[a];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) en += th[a][b] * p2[a][b];
+  *e += s * qi * en;
+  for (int c = 0; c < 3; c++) {
+    double g = Qj * p1[c];
+    for (int a = 0; a < 3; a++) g += mj[a] * 2.0 * p2[a][c];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) g += th[a][b] * 3.0 * p3[a][b][c];
+    gq3[c] += s * qi * g;   /* d/dR_j */
+    gm4[c] -= s * qi * g;   /* d/dR_i: r depends on -R_i */
+  }
+  gm4[3] += s * en;         /* d/dq_i */
+}
+
+static double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+int oracle_region(const oracle_region_t* P, int nq, const double* qm_pos, const double* Q, const double* mu,
+                  const double* theta, int nm, const double* mm_pos, const double* q, const double* kappa,
+                  double* energy, double* phi, double* dphi, double* hphi, double* g_qm_pos, double* g_Q,
+                  double* g_mu, double* g_theta, double* g_mm_pos, double* g_mm_q, long* counts) {
+  const double* L = P->box;
+  if (nq < 0 || nm < 0 || L[0] <= 0.0 || L[1] <= 0.0 || L[2] <= 0.0 || P->r_region < 0.0 || P->r_gauss < 0.0)
+    return -1;
+  const double R1 = P->r_region, RG = P->r_gauss;
+  double C[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < nq; j++)
+    for (int a = 0; a < 3; a++) C[a] += qm_pos[3 * j + a];
+  for (int a = 0; a < 3; a++) C[a] = nq > 0 ? C[a] / nq : 0.0;
+
+  long double* aphi = calloc((size_t)(nq > 0 ? nq : 1) * 10, sizeof(long double));
+  long double* agq = calloc((size_t)(nq > 0 ? nq : 1) * 3, sizeof(long double));
+  long double* agm = calloc((size_t)(nq > 0 ? nq : 1) * 10, sizeof(long double));
+  long double* agmm = calloc((size_t)(nm > 0 ? nm : 1) * 4, sizeof(long double));
+  long double e_qq = 0.0L, e_mm = 0.0L, e_g = 0.0L;
+  long n_img = 0, n_gp = 0;
+
+  /* 1. MM(I) and the Gaussian correction, one MM atom at a time */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_img, n_gp)
+  for (int i = 0; i < nm; i++) {
+    const double* Ri = mm_pos + 3 * i;
+    long double lgm[4] = {0, 0, 0, 0}, lemm = 0.0L, leg = 0.0L;
+    long double* lphi = calloc((size_t)(nq > 0 ? nq : 1) * 10, sizeof(long double));
+    long double* lgq = calloc((size_t)(nq > 0 ? nq : 1) * 3, sizeof(long double));
+    /* every lattice translate within r_region of C: a generous box of n, then the test */
+    int N[3];
+    for (int a = 0; a < 3; a++) N[a] = (int)ceil((R1 + fabs(Ri[a] - C[a])) / L[a]) + 1;
+    for (int nx = -N[0]; nx <= N[0]; nx++)
+      for (int ny = -N[1]; ny <= N[1]; ny++)
+        for (int nz = -N[2]; nz <= N[2]; nz++) {
+          double Ri_n[3] = {Ri[0] + nx * L[0], Ri[1] + ny * L[1], Ri[2] + nz * L[2]};
+          double dC[3] = {Ri_n[0] - C[0], Ri_n[1] - C[1], Ri_n[2] - C[2]};
+          if (!(norm3(dC) < R1)) continue;
+          n_img++;
+          for (int j = 0; j < nq; j++) {
+            double th[3][3];
+            unpack_sym(theta + 6 * j, th);
+            double r[3] = {qm_pos[3 * j] - Ri_n[0], qm_pos[3 * j + 1] - Ri_n[1], qm_pos[3 * j + 2] - Ri_n[2]};
+            region_pair(r, 0.0, -1.0, q[i], Q[j], mu + 3 * j, th, lphi + 10 * j, lgq + 3 * j, lgm, &lemm);
+          }
+        }
+    /* Gaussian charges: region-II translates within r_gauss of a QM site */
+    if (kappa && kappa[i] > 0.0) {
+      for (int j = 0; j < nq; j++) {
+        double th[3][3];
+        unpack_sym(theta + 6 * j, th);
+        const double* Rj = qm_pos + 3 * j;
+        int M[3];
+        for (int a = 0; a < 3; a++) M[a] = (int)ceil((RG + fabs(Rj[a] - Ri[a])) / L[a]) + 1;
+        for (int nx = -M[0]; nx <= M[0]; nx++)
+          for (int ny = -M[1]; ny <= M[1]; ny++)
+            for (int nz = -M[2]; nz <= M[2]; nz++) {
+              double Ri_n[3] = {Ri[0] + nx * L[0], Ri[1] + ny * L[1], Ri[2] + nz * L[2]};
+              double dC[3] = {Ri_n[0] - C[0], Ri_n[1] - C[1], Ri_n[2] - C[2]};
+              if (norm3(dC) < R1) continue; /* region I: already direct */
+              double r[3] = {Rj[0] - Ri_n[0], Rj[1] - Ri_n[1], Rj[2] - Ri_n[2]};
+              if (!(norm3(r) < RG)) continue;
+              n_gp++;
+              region_pair(r, kappa[i], -1.0, q[i], Q[j], mu + 3 * j, th, lphi + 10 * j, lgq + 3 * j, lgm, &leg);
+            }
+      }
+    }
+    for (int t = 0; t < 4; t++) agmm[4 * i + t] += lgm[t];
+#pragma omp critical
+    {
+      for (int t = 0; t < 10 * nq; t++) aphi[t] += lphi[t];
+      for (int t = 0; t < 3 * nq; t++) agq[t] += lgq[t];
+      e_mm += lemm;
+      e_g += leg;
+    }
+    free(lphi);
+    free(lgq);
+  }
+
+  /* 2. unit-cell QM-QM pairs with bare tensors: -1/2 sum over ordered pairs a != b */
+  for (int a = 0; a < nq; a++) {
+    double tha[3][3];
+    unpack_sym(theta + 6 * a, tha);
+    for (int b = 0; b < nq; b++) {
+      if (a == b) continue;
+      double thb[3][3];
+      unpack_sym(theta + 6 * b, thb);
+      double r[3] = {qm_pos[3 * a] - qm_pos[3 * b], qm_pos[3 * a + 1] - qm_pos[3 * b + 1],
+                     qm_pos[3 * a + 2] - qm_pos[3 * b + 2]};
+      double p0, p1[3], p2[3][3], p3[3][3][3];
+      real_tensors(r, 0.0, &p0, p1, p2, p3);
+      const double Qa = Q[a], Qb = Q[b];
+      const double* ma = mu + 3 * a;
+      const double* mb = mu + 3 * b;
+      double Pv = Qa * Qb * p0;
+      for (int c = 0; c < 3; c++) Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];
+      for (int c = 0; c < 3; c++)
+        for (int d = 0; d < 3; d++) {
+          Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];
+          Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];
+        }
+      e_qq += -0.5L * Pv;
+      for (int g = 0; g < 3; g++) {
+        double dg = Qa * Qb * p1[g];
+        for (int c = 0; c < 3; c++) dg += (Qb * ma[c] - Qa * mb[c]) * 2.0 * p2[c][g];
+        for (int c = 0; c < 3; c++)
+          for (int d = 0; d < 3; d++) {
+            dg += (Qb * tha[c][d] + Qa * thb[c][d]) * 3.0 * p3[c][d][g];
+            dg -= 2.0 * ma[c] * 3.0 * p3[c][d][g] * mb[d];
+          }
+        agq[3 * a + g] += -0.5L * dg;
+        agq[3 * b + g] -= -0.5L * dg;
+      }
+      double dQa = Qb * p0, dQb = Qa * p0;
+      for (int c = 0; c < 3; c++) {
+        dQa += -mb[c] * p1[c];
+        dQb += ma[c] * p1[c];
+      }
+      for (int c = 0; c < 3; c++)
+        for (int d = 0; d < 3; d++) {
+          dQa += thb[c][d] * p2[c][d];
+          dQb += tha[c][d] * p2[c][d];
+        }
+      agm[10 * a] += -0.5L * dQa;
+      agm[10 * b] += -0.5L * dQb;
+      for (int c = 0; c < 3; c++) {
+        double dma = Qb * p1[c], dmb = -Qa * p1[c];
+        for (int d = 0; d < 3; d++) {
+          dma -= 2.0 * p2[c][d] * mb[d];
+          dmb -= 2.0 * ma[d] * p2[d][c];
+        }
+        agm[10 * a + 1 + c] += -0.5L * dma;
+        agm[10 * b + 1 + c] += -0.5L * dmb;
+      }
+      /* full-matrix theta derivatives, stored by sym6 index (each element of
+       * the symmetric pair is visited, so off-diagonals collect both) */
+      for (int c = 0; c < 3; c++)
+        for (int d = 0; d < 3; d++) {
+          agm[10 * a + 4 + sym6(c, d)] += -0.5L * Qb * p2[c][d];
+          agm[10 * b + 4 + sym6(c, d)] += -0.5L * Qa * p2[c][d];
+        }
+    }
+  }
+
+  /* 3. outputs */
+  if (energy) {
+    energy[0] = (double)e_qq;
+    energy[1] = (double)e_mm;
+    energy[2] = (double)e_g;
+  }
+  for (int j = 0; j < nq; j++) {
+    if (phi) phi[j] = (double)aphi[10 * j];
+    if (dphi)
+      for (int a = 0; a < 3; a++) dphi[3 * j + a] = (double)aphi[10 * j + 1 + a];
+    if (hphi)
+      for (int t = 0; t < 6; t++) hphi[6 * j + t] = (double)aphi[10 * j + 4 + t];
+    if (g_qm_pos)
+      for (int g = 0; g < 3; g++) g_qm_pos[3 * j + g] = (double)agq[3 * j + g];
+    if (g_Q) g_Q[j] = (double)(aphi[10 * j] + agm[10 * j]);
+    if (g_mu)
+      for (int a = 0; a < 3; a++) g_mu[3 * j + a] = (double)(aphi[10 * j + 1 + a] + agm[10 * j + 1 + a]);
+    if (g_theta) {
+      /* MM field part: dE/dtheta_ab (full) = half Hessian; stored numbers take
+       * both off-diagonal elements.  QM-QM part is already per stored number. */
+      double full[3][3];
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) full[a][b] = (double)aphi[10 * j + 4 + sym6(a, b)];
+      for (int t = 0; t < 6; t++) g_theta[6 * j + t] = (double)agm[10 * j + 4 + t];
+      add_theta_grad(g_theta + 6 * j, full, 1.0);
+    }
+  }
+  for (int i = 0; i < nm; i++) {
+    if (g_mm_pos)
+      for (int g = 0; g < 3; g++) g_mm_pos[3 * i + g] = (double)agmm[4 * i + g];
+    if (g_mm_q) g_mm_q[i] = (double)agmm[4 * i + 3];
+  }
+  if (counts) {
+    counts[0] = n_img;
+    counts[1] = n_gp;
+  }
+  free(aphi);
+  free(agq);
+  free(agm);
+  free(agmm);
+  return 0;
 }

@@ -2,7 +2,8 @@
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this module.  It compiles ``ewald_oracle.c`` with gcc (no code shared
-with the HIP library) and exposes :func:`oracle_ewald`.
+with the HIP library) and exposes :func:`oracle_ewald` (the Ewald sums) and
+:func:`oracle_region` (the region-I subtraction and Gaussian-charge correction).
 
 Conventions (paper: SI "Multipolar Ewald"; main text, periodic QM/MM energy):
   * positions in length units (Angstrom in the workloads), charges in e,
@@ -65,6 +66,9 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     lib.oracle_ewald.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp,
                                  dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_region.restype = ctypes.c_int
+    lib.oracle_region.argtypes = [ctypes.POINTER(_RegionParams), ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp,
+                                  dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     _lib_cache[path] = lib
     return lib
 
@@ -166,3 +170,80 @@ def oracle_ewald(box, alpha, rcut, kmax, qm_pos, Q, mu, theta, mm_pos, q, qmqm=T
     return OracleResult(energy=dict(zip(ENERGY_NAMES, energy.tolist())), phi=phi, dphi=dphi, hphi=hphi,
                         g_qm_pos=gq, g_Q=gQ, g_mu=gmu, g_theta=gth, g_mm_pos=gm, g_mm_q=gmq,
                         mm_sel=None if mm_sel is None else np.asarray(mm_sel))
+
+
+class _RegionParams(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double * 3),
+        ("r_region", ctypes.c_double),
+        ("r_gauss", ctypes.c_double),
+    ]
+
+
+REGION_ENERGY_NAMES = ("qq_bare", "mm_bare", "gauss")
+
+
+@dataclass
+class OracleRegionResult:
+    energy: dict           # qq_bare, mm_bare, gauss and their sum under "total"
+    phi: np.ndarray        # (nq,)   correction to the MM potential at the QM sites
+    dphi: np.ndarray       # (nq,3)  its gradient
+    hphi: np.ndarray       # (nq,6)  one half of its Hessian
+    g_qm_pos: np.ndarray   # (nq,3)  gradient of the correction energy
+    g_Q: np.ndarray
+    g_mu: np.ndarray
+    g_theta: np.ndarray    # (nq,6)  w.r.t. stored numbers
+    g_mm_pos: np.ndarray   # (nm,3)
+    g_mm_q: np.ndarray     # (nm,)
+    n_region_images: int   # MM lattice translates inside the region-I sphere
+    n_gauss_pairs: int     # (QM site, region-II MM translate) pairs of the Gaussian correction
+
+    @property
+    def E(self) -> float:
+        return self.energy["total"]
+
+
+def oracle_region(box, r_region, r_gauss, qm_pos, Q, mu, theta, mm_pos, q, kappa=None,
+                  lib_path: str | None = None) -> OracleRegionResult:
+    """Region-I subtraction and Gaussian-charge correction terms.
+
+    Adding them to :func:`oracle_ewald`'s outputs gives the region-II energy,
+    site field and gradients (paper: periodic QM/MM multipole energy and the
+    Gaussian-charge correction).  kappa: (nm,) Gaussian exponents, <= 0 or
+    None for point charges.
+    """
+    lib = load(lib_path) if lib_path else load()
+    qm_pos = _c(qm_pos).reshape(-1, 3)
+    nq = qm_pos.shape[0]
+    Q = _c(Q, (nq,))
+    mu = _c(mu, (nq, 3))
+    theta = _c(theta, (nq, 6))
+    mm_pos = _c(mm_pos).reshape(-1, 3)
+    nm = mm_pos.shape[0]
+    q = _c(q, (nm,))
+    kap = None if kappa is None else _c(kappa, (nm,))
+    p = _RegionParams()
+    p.box[:] = [float(b) for b in box]
+    p.r_region = float(r_region)
+    p.r_gauss = float(r_gauss)
+    energy = np.zeros(3)
+    phi = np.zeros(nq)
+    dphi = np.zeros((nq, 3))
+    hphi = np.zeros((nq, 6))
+    gq = np.zeros((nq, 3))
+    gQ = np.zeros(nq)
+    gmu = np.zeros((nq, 3))
+    gth = np.zeros((nq, 6))
+    gm = np.zeros((nm, 3))
+    gmq = np.zeros(nm)
+    counts = np.zeros(2, dtype=np.int64)
+    rc = lib.oracle_region(ctypes.byref(p), nq, _ptr(qm_pos), _ptr(Q), _ptr(mu), _ptr(theta), nm, _ptr(mm_pos),
+                           _ptr(q), None if kap is None else _ptr(kap), _ptr(energy), _ptr(phi), _ptr(dphi),
+                           _ptr(hphi), _ptr(gq), _ptr(gQ), _ptr(gmu), _ptr(gth), _ptr(gm), _ptr(gmq),
+                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    if rc != 0:
+        raise ValueError(f"oracle_region rejected its arguments (status {rc})")
+    en = dict(zip(REGION_ENERGY_NAMES, energy.tolist()))
+    en["total"] = float(sum(energy))
+    return OracleRegionResult(energy=en, phi=phi, dphi=dphi, hphi=hphi, g_qm_pos=gq, g_Q=gQ, g_mu=gmu, g_theta=gth,
+                              g_mm_pos=gm, g_mm_q=gmq, n_region_images=int(counts[0]), n_gauss_pairs=int(counts[1]))

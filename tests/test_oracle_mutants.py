@@ -8,7 +8,7 @@ import tempfile
 import pytest
 
 from oracle import oracle as orc
-from tests import _pins
+from tests import _pins, _region_pins
 
 # (description, exact text in the oracle source, replacement[, which occurrence])
 MUTANTS = [
@@ -20,9 +20,9 @@ MUTANTS = [
     ("quadrupole structure factor 1/2", "cr_ += -0.5 * kthk * er;", "cr_ += -1.0 * kthk * er;"),
     ("dipole self-energy sign", "- 2.0 * al * al * al / (3.0 * sp) * mm2", "+ 2.0 * al * al * al / (3.0 * sp) * mm2"),
     ("charge-quadrupole self term dropped", "+ 2.0 * al * al * al / (3.0 * sp) * Q[j] * tr;", ";"),
-    ("dipole-dipole pair sign", "Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];", "Pv += 2.0 * ma[c] * p2[c][d] * mb[d];"),
-    ("charge-dipole operands swapped", "Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];", "Pv += (Qa * ma[c] - Qb * mb[c]) * p1[c];"),
-    ("charge-quadrupole pair half", "Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", "Pv += 0.5 * (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];"),
+    ("dipole-dipole pair sign", "Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];", "Pv += 2.0 * ma[c] * p2[c][d] * mb[d];", 0),
+    ("charge-dipole operands swapped", "Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];", "Pv += (Qa * ma[c] - Qb * mb[c]) * p1[c];", 0),
+    ("charge-quadrupole pair half", "Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", "Pv += 0.5 * (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", 0),
     ("background factor", "const double bgc = -PI / (al * al * V);", "const double bgc = -PI / (2.0 * al * al * V);"),
     ("f5 coefficient", "f[2] = (f[1] + 4.0 / 3.0 * kappa", "f[2] = (f[1] + 2.0 / 3.0 * kappa"),
     ("f7 coefficient", "f[3] = (f[2] + 8.0 / 15.0 * pow(kappa, 5)", "f[3] = (f[2] + 4.0 / 15.0 * pow(kappa, 5)"),
@@ -32,6 +32,26 @@ MUTANTS = [
     ("half-space weight", "const double pref = 8.0 * PI / V;", "const double pref = 4.0 * PI / V;"),
     ("reciprocal MM force component", "for (int g = 0; g < 3; g++) lg[g] += w * q[i] * kk[g] * vi;", "for (int g = 0; g < 3; g++) lg[g] += w * q[i] * kk[(g + 1) % 3] * vi;"),
     ("QM-QM LR gradient sign", "for (int g = 0; g < 3; g++) lg[g] += w * kk[g] * (-zi);", "for (int g = 0; g < 3; g++) lg[g] += w * kk[g] * (zi);"),
+]
+
+# mistakes in the region-I subtraction and the Gaussian-charge correction
+REGION_MUTANTS = [
+    ("region-I subtraction sign", "region_pair(r, 0.0, -1.0, q[i]", "region_pair(r, 0.0, 1.0, q[i]"),
+    ("region MM force sign", "gm4[c] -= s * qi * g;", "gm4[c] += s * qi * g;"),
+    ("region dE/dq sign", "gm4[3] += s * en;", "gm4[3] += en;"),
+    ("region dipole force factor", "g += mj[a] * 2.0 * p2[a][c];", "g += mj[a] * p2[a][c];"),
+    ("region-I minimum image only", "N[a] = (int)ceil((R1 + fabs(Ri[a] - C[a])) / L[a]) + 1;", "N[a] = 0;"),
+    ("Gaussian pairs not excluded from region I", "if (norm3(dC) < R1) continue; /* region I: already direct */", ";"),
+    ("Gaussian exponent doubled", "region_pair(r, kappa[i], -1.0", "region_pair(r, 2.0 * kappa[i], -1.0"),
+    ("region centre at the origin", "C[a] = nq > 0 ? C[a] / nq : 0.0;", "C[a] = 0.0;"),
+    ("bare QM-QM half", "e_qq += -0.5L * Pv;", "e_qq += -1.0L * Pv;"),
+    ("bare QM-QM dipole-dipole sign", "Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];", "Pv += 2.0 * ma[c] * p2[c][d] * mb[d];", 1),
+    ("bare QM-QM charge-dipole operands swapped", "Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];",
+     "Pv += (Qa * ma[c] - Qb * mb[c]) * p1[c];", 1),
+    ("bare QM-QM charge-quadrupole half", "Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];",
+     "Pv += 0.5 * (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", 1),
+    ("bare QM-QM theta gradient", "agm[10 * a + 4 + sym6(c, d)] += -0.5L * Qb * p2[c][d];",
+     "agm[10 * a + 4 + sym6(c, d)] += -0.25L * Qb * p2[c][d];"),
 ]
 
 FAST_PINS = ["nacl_potential", "sc_charge_quadrupole", "dipole_lattice", "alpha_independence", "fd_positions",
@@ -49,6 +69,35 @@ def _apply(text, old, new, occurrence):
     for _ in range(occurrence + 1):
         pos = text.index(old, pos + 1)
     return text[:pos] + new + text[pos + len(old):]
+
+
+def _region_pins_caught(so):
+    for name, (fn, tol) in _region_pins.REGION_PINS.items():
+        try:
+            err = fn(lib=so)
+        except Exception as e:  # a crash or a rejected input also counts as caught
+            return f"{name}: {type(e).__name__}"
+        if not (err <= tol):
+            return f"{name}: {err:.2e}"
+    return None
+
+
+@pytest.mark.parametrize("mut", REGION_MUTANTS, ids=[m[0] for m in REGION_MUTANTS])
+def test_region_mutant_is_caught(mut, src_text, tmp_path):
+    desc, old, new = mut[:3]
+    occurrence = mut[3] if len(mut) > 3 else None
+    n = src_text.count(old)
+    if occurrence is None:
+        assert n == 1, f"mutation anchor not unique/found: {old!r}"
+        occurrence = 0
+    else:
+        assert n > occurrence, f"mutation anchor occurrence {occurrence} missing: {old!r}"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(_apply(src_text, old, new, occurrence))
+    so = str(tmp_path / "libmutant.so")
+    orc.build(src=str(msrc), out=so)
+    caught = _region_pins_caught(so)
+    assert caught, f"mutant '{desc}' passed every region pin"
 
 
 @pytest.mark.parametrize("mut", MUTANTS, ids=[m[0] for m in MUTANTS])
