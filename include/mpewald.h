@@ -165,6 +165,50 @@ ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm,
                                     const double* Q, const double* mu, const double* theta, int n_mm,
                                     double* energy, double* g_Q, double* g_mu, double* g_theta, void* stream);
 
+/* Region-I / region-II split (paper: Methods, the periodic QM/MM multipole
+ * energy as whole-lattice Ewald sums minus direct sums over region I, and the
+ * correction for Gaussian-smeared MM charges; SI: bare tensors T..T_abc and
+ * screened ones with f1, f3, f5, f7 at kappa_i).  Region I is the sphere of
+ * radius r_region around the arithmetic mean C of the QM positions; the QM
+ * atoms of the cell belong to it, their periodic images do not.  The added
+ * terms turn the outputs of ewald_forward into the region-II quantities that
+ * the SCF uses (energy E^II and the potential v^II = dE^II/d(moments)):
+ *   - the bare unit-cell QM-QM pairs: -1/2 sum_{a != b} P_T(a, b), the pair
+ *     form of the QM-QM image terms with bare tensors, r = R_a - R_b with the
+ *     QM positions as passed (not wrapped);
+ *   - every lattice translate R_i + n L of every MM charge with
+ *     |R_i + n L - C| < r_region: -q_i [Q T + mu.T_a + theta:T_ab] at each QM
+ *     site (the sphere may exceed the cell; several translates of one atom
+ *     may take part);
+ *   - for MM charges with mm_kappa[i] > 0 (Gaussian charges of exponent
+ *     kappa_i; mm_kappa null or <= 0: point charges): every translate outside
+ *     the sphere within r_gauss of a QM site: -q_i [Q That + mu.That_a +
+ *     theta:That_ab] with the tensors of erfc(kappa_i r)/r.
+ * Box: the plan's.  r_region, r_gauss: >= 0 and at most 4 box lengths
+ * (EWALD_ERR_CUTOFF otherwise).  Arrays as in ewald_forward, plus mm_kappa
+ * (Nm) on the device.  n_qm may not exceed the plan's max_qm; n_mm is not
+ * limited by the plan.
+ *
+ * ewald_region_forward ADDS the region terms to energy (required), phi,
+ * efield and efgrad (each may be null), e.g. to the outputs of an
+ * ewald_forward call on the same stream.  ewald_region_backward ADDS the
+ * gradient of L = gE E_r + g_phi.phi_r + g_efield.efield_r + g_efgrad.efgrad_r
+ * of the region terms (gE device scalar, null = 1; the g_* may be null = 0) to
+ * g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz (required when the count is > 0) and
+ * g_mm_q (may be null), e.g. after an ewald_backward call with the same
+ * upstream gradients.  No gradient with respect to mm_kappa.  Calls on one
+ * plan share a workspace: do not overlap them on different streams. */
+ewald_status_t ewald_region_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
+                                    const double* mu, const double* theta, int n_mm, const double* mm_xyz,
+                                    const double* mm_q, const double* mm_kappa, double r_region, double r_gauss,
+                                    double* energy, double* phi, double* efield, double* efgrad, void* stream);
+ewald_status_t ewald_region_backward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
+                                     const double* mu, const double* theta, int n_mm, const double* mm_xyz,
+                                     const double* mm_q, const double* mm_kappa, double r_region, double r_gauss,
+                                     const double* gE, const double* g_phi, const double* g_efield,
+                                     const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu,
+                                     double* g_theta, double* g_mm_xyz, double* g_mm_q, void* stream);
+
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
  * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or

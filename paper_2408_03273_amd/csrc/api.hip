@@ -122,6 +122,8 @@ int real_images(const double box[3], double rcut) {
 
 // real space visits up to kMaxImages lattice images per direction (rc up to ~3.5 L)
 constexpr int kMaxImages = 3;
+// region-I sphere and Gaussian pair cutoff: at most this many box lengths
+constexpr double kMaxRegionBoxes = 4.0;
 
 ewald_status_t validate_box(const double box[3], double rcut) {
   for (int a = 0; a < 3; a++)
@@ -609,6 +611,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.cell_start, (size_t)pl->cap_cells + 2);
   A(w.cell_atoms, cm);
   A(w.atom_cell, cm);
+  A(w.region_e, cq);
 #undef A
   const double one = 1.0;
   // padding entries of the matrix-core operands are never written by the kernels: zero them once
@@ -1049,6 +1052,76 @@ extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx
     LCHK(launch_qmqm(g, q.fa, n_qm, plan->cap_qm, Q, mu, theta, w, s));
   }
   LCHK(launch_finalize_moments(q.fa, Q, mu, theta, q.qmqm, cv.site, energy, g_Q, g_mu, g_theta, w, s));
+  return EWALD_OK;
+}
+
+// ---------------------------------------------------------------- region-I / region-II split
+static ewald_status_t region_args(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
+                                  const double* mu, const double* theta, int n_mm, const double* mm_xyz,
+                                  const double* mm_q, const double* mm_kappa, double r_region, double r_gauss,
+                                  RegionArgs& ra) {
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  ewald_status_t st = check_arrays(n_qm, n_mm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
+  if (st != EWALD_OK) return st;
+  if (n_qm > plan->cap_qm) return fail(EWALD_ERR_CAPACITY, "n_qm=%d exceeds capacity %d", n_qm, plan->cap_qm);
+  if (!std::isfinite(r_region) || !std::isfinite(r_gauss) || r_region < 0.0 || r_gauss < 0.0)
+    return fail(EWALD_ERR_ARG, "r_region=%g r_gauss=%g must be finite and >= 0", r_region, r_gauss);
+  const double lmin = std::min(plan->p.box[0], std::min(plan->p.box[1], plan->p.box[2]));
+  if (r_region > kMaxRegionBoxes * lmin || r_gauss > kMaxRegionBoxes * lmin)
+    return fail(EWALD_ERR_CUTOFF, "r_region=%g or r_gauss=%g above %g box lengths (%g)", r_region, r_gauss,
+                kMaxRegionBoxes, kMaxRegionBoxes * lmin);
+  ra.nq = n_qm;
+  ra.nm = n_mm;
+  ra.qm_xyz = qm_xyz;
+  ra.Q = Q;
+  ra.mu = mu;
+  ra.theta = theta;
+  ra.mm_xyz = mm_xyz;
+  ra.mm_q = mm_q;
+  ra.kappa = mm_kappa;
+  for (int a = 0; a < 3; a++) ra.box[a] = plan->p.box[a];
+  ra.r_region = r_region;
+  ra.r_gauss = r_gauss;
+  return EWALD_OK;
+}
+
+extern "C" ewald_status_t ewald_region_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
+                                               const double* mu, const double* theta, int n_mm,
+                                               const double* mm_xyz, const double* mm_q, const double* mm_kappa,
+                                               double r_region, double r_gauss, double* energy, double* phi,
+                                               double* efield, double* efgrad, void* stream) {
+  g_last_error.clear();
+  RegionArgs ra;
+  ewald_status_t st = region_args(plan, n_qm, qm_xyz, Q, mu, theta, n_mm, mm_xyz, mm_q, mm_kappa, r_region, r_gauss,
+                                  ra);
+  if (st != EWALD_OK) return st;
+  if (!energy) return fail(EWALD_ERR_ARG, "null energy output");
+  ewald_plan* pl = plan;
+  hipStream_t s = (hipStream_t)stream;
+  LCHK_P(pl, s, "launch_region_forward",
+         launch_region_forward(ra, plan->w.region_e, energy, phi, efield, efgrad, s));
+  return EWALD_OK;
+}
+
+extern "C" ewald_status_t ewald_region_backward(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
+                                                const double* mu, const double* theta, int n_mm,
+                                                const double* mm_xyz, const double* mm_q, const double* mm_kappa,
+                                                double r_region, double r_gauss, const double* gE,
+                                                const double* g_phi, const double* g_efield,
+                                                const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu,
+                                                double* g_theta, double* g_mm_xyz, double* g_mm_q, void* stream) {
+  g_last_error.clear();
+  RegionArgs ra;
+  ewald_status_t st = region_args(plan, n_qm, qm_xyz, Q, mu, theta, n_mm, mm_xyz, mm_q, mm_kappa, r_region, r_gauss,
+                                  ra);
+  if (st != EWALD_OK) return st;
+  if (n_qm > 0 && (!g_qm_xyz || !g_Q || !g_mu || !g_theta)) return fail(EWALD_ERR_ARG, "null QM gradient output");
+  if (n_mm > 0 && !g_mm_xyz) return fail(EWALD_ERR_ARG, "null MM gradient output");
+  ewald_plan* pl = plan;
+  hipStream_t s = (hipStream_t)stream;
+  LCHK_P(pl, s, "launch_region_backward",
+         launch_region_backward(ra, gE, g_phi, g_efield, g_efgrad, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q,
+                                s));
   return EWALD_OK;
 }
 

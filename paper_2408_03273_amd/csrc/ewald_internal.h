@@ -110,6 +110,7 @@ struct Work {
   int* cell_start;    // [cap_cells]          first sorted atom of each cell (+ end entry per frame)
   int* cell_atoms;    // [cap_mm]             frame-local MM indices sorted by cell
   int* atom_cell;     // [cap_mm]             cell of each MM atom
+  double* region_e;   // [cap_qm]             per-site energies of the region-I / Gaussian terms
 };
 
 static constexpr int kMaxCellsPerAxis = 16;
@@ -203,6 +204,28 @@ hipError_t launch_finalize_bwd(const FrameArg& fa, int max_nq, const double* sit
 hipError_t launch_scale_grads(const double* gE, int nq, int nm, const double* gq, const double* gQ, const double* gmu,
                               const double* gth, const double* gm, const double* gmq, double* o_q, double* o_Q,
                               double* o_mu, double* o_th, double* o_m, double* o_mq, hipStream_t s);
+// Region-I / region-II split: inputs of one frame (device pointers, row-major
+// as passed by the caller; kappa may be null)
+struct RegionArgs {
+  int nq, nm;
+  const double* qm_xyz;
+  const double* Q;
+  const double* mu;
+  const double* theta;
+  const double* mm_xyz;
+  const double* mm_q;
+  const double* kappa;
+  double box[3];
+  double r_region, r_gauss;
+};
+// add the region terms to energy / phi / efield / efgrad (any output but energy may be null)
+hipError_t launch_region_forward(const RegionArgs& ra, double* e_site, double* energy, double* phi, double* efield,
+                                 double* efgrad, hipStream_t s);
+// add the gradients of gE x (region terms) + upstream site gradients to the gradient outputs
+hipError_t launch_region_backward(const RegionArgs& ra, const double* gE, const double* g_phi,
+                                  const double* g_efield, const double* g_efgrad, double* g_qm_xyz, double* g_Q,
+                                  double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q, hipStream_t s);
+
 // forward kernel instances available for the nz chunk
 bool sfac_mm_has_zc(int zc);
 int pick_zc(int NZ);

@@ -1,0 +1,452 @@
+// Region-I / region-II split of the periodic multipole coupling on gfx950.
+//
+// Paper: Methods, the periodic QM/MM multipole energy written as whole-lattice
+// Ewald sums minus direct sums over region I (a sphere of radius R_cut around
+// the geometric centre of the QM atoms), and the correction for Gaussian-
+// smeared MM charges in region II; Supporting Information, the bare tensors
+// T, T_a, T_ab, T_abc and the screened ones with f1, f3, f5, f7 at kappa_i.
+//
+// The terms added to the Ewald outputs are
+//   - the bare QM-QM pairs of the unit cell, -1/2 sum_{a != b} P_T(a, b);
+//   - the bare interaction with every MM lattice translate inside the sphere;
+//   - the erfc(kappa_i r)/r interaction with every region-II translate of a
+//     Gaussian MM charge (kappa_i > 0) within r_gauss of a QM site,
+// each with a minus sign.  These are finite real-space sums over at most a
+// few thousand MM translates per QM site: plain FP64 VALU pair kernels, one
+// block per QM site (site sums) and one thread per MM atom (MM gradients).
+#include <math.h>
+
+#include "ewald_internal.h"
+
+namespace mpe {
+
+#define DEV __device__ __forceinline__
+
+struct RadialK {
+  double f1, f3, f5, f7;
+};
+
+// Radial functions of erfc(kappa r)/r (SI: f1, f3, f5, f7); kappa = 0 gives
+// the bare 1/r^(2n+1).
+DEV RadialK radial_k(double r2, double kappa) {
+  const double r = sqrt(r2);
+  const double inv2 = 1.0 / r2;
+  RadialK o;
+  if (kappa > 0.0) {
+    const double ex = exp(-kappa * kappa * r2);
+    const double c = 1.1283791670955126 * kappa;  // 2 kappa / sqrt(pi)
+    o.f1 = erfc(kappa * r) / r;
+    o.f3 = (o.f1 + c * ex) * inv2;
+    o.f5 = (o.f3 + (2.0 / 3.0) * kappa * kappa * c * ex) * inv2;
+    o.f7 = (o.f5 + (4.0 / 15.0) * kappa * kappa * kappa * kappa * c * ex) * inv2;
+  } else {
+    o.f1 = 1.0 / r;
+    o.f3 = o.f1 * inv2;
+    o.f5 = o.f3 * inv2;
+    o.f7 = o.f5 * inv2;
+  }
+  return o;
+}
+
+// Moments of one site as the pair kernels use them: Q, mu, theta (full
+// symmetric, stored order xx,xy,xz,yy,yz,zz).
+struct Site {
+  double Q, m[3], t[6];
+};
+
+// Effective moments of the adjoint: L = gE E + g_phi.phi + g_efield.efield +
+// g_efgrad.efgrad is, site by site, the energy of the moments
+// (gE Q + g_phi, gE mu - g_efield, gE theta - w g_efgrad), w = 2 on the
+// diagonal and 1 off it (efgrad = -2 x half Hessian, off-diagonal stored
+// numbers count twice in theta : H).
+DEV Site eff_site(const RegionArgs& ra, int j, double gE, const double* g_phi, const double* g_efield,
+                  const double* g_efgrad) {
+  Site s;
+  s.Q = gE * ra.Q[j] + (g_phi ? g_phi[j] : 0.0);
+  for (int a = 0; a < 3; a++) s.m[a] = gE * ra.mu[3 * j + a] - (g_efield ? g_efield[3 * j + a] : 0.0);
+  for (int t = 0; t < 6; t++) {
+    const double w = (t == 0 || t == 3 || t == 5) ? 2.0 : 1.0;
+    s.t[t] = gE * ra.theta[6 * j + t] - (g_efgrad ? w * g_efgrad[6 * j + t] : 0.0);
+  }
+  return s;
+}
+
+// Energy of the site's moments in the field of a unit charge at -r (r from
+// the charge to the site) and its gradient with respect to r:
+//   en = Q f1 - (mu.r) f3 + 3/2 (r.theta.r) f5 - 1/2 tr(theta) f3
+//   g  = d en / d r = s1 r - f3 mu + 3 f5 theta.r,
+//   s1 = -Q f3 + 3 (mu.r) f5 + 3/2 tr(theta) f5 - 15/2 (r.theta.r) f7
+DEV void pair_energy_grad(const Site& s, double x, double y, double z, const RadialK& R, double& en, double g[3]) {
+  const double md = s.m[0] * x + s.m[1] * y + s.m[2] * z;
+  const double thx = s.t[0] * x + s.t[1] * y + s.t[2] * z;
+  const double thy = s.t[1] * x + s.t[3] * y + s.t[4] * z;
+  const double thz = s.t[2] * x + s.t[4] * y + s.t[5] * z;
+  const double dtd = x * thx + y * thy + z * thz;
+  const double tr = s.t[0] + s.t[3] + s.t[5];
+  en = s.Q * R.f1 - md * R.f3 + 1.5 * dtd * R.f5 - 0.5 * tr * R.f3;
+  const double s1 = -s.Q * R.f3 + 3.0 * md * R.f5 + 1.5 * tr * R.f5 - 7.5 * dtd * R.f7;
+  const double s3 = 3.0 * R.f5;
+  g[0] = s1 * x - R.f3 * s.m[0] + s3 * thx;
+  g[1] = s1 * y - R.f3 * s.m[1] + s3 * thy;
+  g[2] = s1 * z - R.f3 * s.m[2] + s3 * thz;
+}
+
+// potential, gradient and half Hessian at the site of a charge qs at -r
+DEV void pair_field(double qs, double x, double y, double z, const RadialK& R, double* F) {
+  F[0] += qs * R.f1;
+  F[1] -= qs * x * R.f3;
+  F[2] -= qs * y * R.f3;
+  F[3] -= qs * z * R.f3;
+  const double h5 = 1.5 * qs * R.f5, h3 = 0.5 * qs * R.f3;
+  F[4] += h5 * x * x - h3;
+  F[5] += h5 * x * y;
+  F[6] += h5 * x * z;
+  F[7] += h5 * y * y - h3;
+  F[8] += h5 * y * z;
+  F[9] += h5 * z * z - h3;
+}
+
+template <int N>
+DEV void region_block_sum(double (&v)[N], double (&out)[N]) {
+  __shared__ double red[4][N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < N; t++) {
+    double s = v[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) red[wave][t] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < N; t++) out[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  __syncthreads();
+}
+
+// Geometric centre of the QM atoms (every block computes the same value in
+// the same order).  Called by all 256 threads.
+DEV void region_centre(const RegionArgs& ra, double (&C)[3]) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < ra.nq; j += 256)
+    for (int a = 0; a < 3; a++) v[a] += ra.qm_xyz[3 * j + a];
+  region_block_sum<3>(v, C);
+  for (int a = 0; a < 3; a++) C[a] /= (double)ra.nq;
+}
+
+// Offset of an MM atom from the centre, reduced to the nearest translate
+// (|d_a| <= L_a/2); every translate is then d + n L.
+DEV void centre_offset(const RegionArgs& ra, const double C[3], int i, double d[3]) {
+  for (int a = 0; a < 3; a++) {
+    const double L = ra.box[a];
+    const double v = ra.mm_xyz[3 * i + a] - C[a];
+    d[a] = v - L * rint(v / L);
+  }
+}
+
+// translate n of offset d along one axis
+DEV double tr_coord(double d, int n, double L) { return d + (double)n * L; }
+
+DEV bool in_region(const RegionArgs& ra, const double d[3], int nx, int ny, int nz) {
+  const double x = tr_coord(d[0], nx, ra.box[0]), y = tr_coord(d[1], ny, ra.box[1]), z = tr_coord(d[2], nz, ra.box[2]);
+  return x * x + y * y + z * z < ra.r_region * ra.r_region;
+}
+
+// Range of n with |c + n L| < R possible along one axis.
+DEV void n_range(double c, double R, double L, int& lo, int& hi) {
+  lo = (int)ceil((-R - c) / L);
+  hi = (int)floor((R - c) / L);
+}
+
+// Visit every (translate, kappa) pair of MM atom i with the site at offset
+// s (= R_j - C) from the centre: the region-I translates with kappa = 0, and
+// for a Gaussian charge the region-II translates within r_gauss of the site.
+// fn(x, y, z, r2, kappa) receives r = R_j - R_i,n.
+template <typename Fn>
+DEV void for_each_pair(const RegionArgs& ra, const double d[3], double kap, const double s[3], Fn&& fn) {
+  const double R1 = ra.r_region;
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; a++) n_range(d[a], R1, ra.box[a], lo[a], hi[a]);
+  for (int nx = lo[0]; nx <= hi[0]; nx++)
+    for (int ny = lo[1]; ny <= hi[1]; ny++)
+      for (int nz = lo[2]; nz <= hi[2]; nz++) {
+        if (!in_region(ra, d, nx, ny, nz)) continue;
+        const double x = s[0] - tr_coord(d[0], nx, ra.box[0]);
+        const double y = s[1] - tr_coord(d[1], ny, ra.box[1]);
+        const double z = s[2] - tr_coord(d[2], nz, ra.box[2]);
+        const double r2 = x * x + y * y + z * z;
+        if (r2 > 0.0) fn(x, y, z, r2, 0.0);
+      }
+  if (!(kap > 0.0) || !(ra.r_gauss > 0.0)) return;
+  const double RG = ra.r_gauss;
+  // r = s - (d + n L): |s_a - d_a - n L_a| < RG
+  for (int a = 0; a < 3; a++) {
+    n_range(d[a] - s[a], RG, ra.box[a], lo[a], hi[a]);
+  }
+  for (int nx = lo[0]; nx <= hi[0]; nx++)
+    for (int ny = lo[1]; ny <= hi[1]; ny++)
+      for (int nz = lo[2]; nz <= hi[2]; nz++) {
+        const double x = s[0] - tr_coord(d[0], nx, ra.box[0]);
+        const double y = s[1] - tr_coord(d[1], ny, ra.box[1]);
+        const double z = s[2] - tr_coord(d[2], nz, ra.box[2]);
+        const double r2 = x * x + y * y + z * z;
+        if (!(r2 < RG * RG) || !(r2 > 0.0) || in_region(ra, d, nx, ny, nz)) continue;
+        fn(x, y, z, r2, kap);
+      }
+}
+
+// ------------------------------------------------------------------ QM side
+// One block per QM site.  BWD = 0: potential, gradient and half Hessian of
+// the subtracted charges at the site (added to phi, efield, efgrad) and the
+// site's energy (written to e_site).  BWD = 1: the site's position gradient
+// with the effective moments and dE/d(moments) = gE x the same field, added
+// to the gradient outputs.
+template <int BWD>
+__global__ __launch_bounds__(256) void k_region_qm(RegionArgs ra, const double* __restrict__ gE_p,
+                                                   const double* __restrict__ g_phi,
+                                                   const double* __restrict__ g_efield,
+                                                   const double* __restrict__ g_efgrad, double* __restrict__ e_site,
+                                                   double* __restrict__ phi, double* __restrict__ efield,
+                                                   double* __restrict__ efgrad, double* __restrict__ g_qm_xyz,
+                                                   double* __restrict__ g_Q, double* __restrict__ g_mu,
+                                                   double* __restrict__ g_theta) {
+  double C[3];
+  region_centre(ra, C);
+  const int j = blockIdx.x;
+  const double gE = BWD ? (gE_p ? *gE_p : 1.0) : 1.0;
+  const Site st = BWD ? eff_site(ra, j, gE, g_phi, g_efield, g_efgrad) : eff_site(ra, j, 1.0, nullptr, nullptr, nullptr);
+  const double s[3] = {ra.qm_xyz[3 * j] - C[0], ra.qm_xyz[3 * j + 1] - C[1], ra.qm_xyz[3 * j + 2] - C[2]};
+  constexpr int NV = BWD ? 13 : 10;
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; t++) acc[t] = 0.0;
+  for (int i = threadIdx.x; i < ra.nm; i += 256) {
+    double d[3];
+    centre_offset(ra, C, i, d);
+    const double qs = -ra.mm_q[i];  // subtracted
+    const double kap = ra.kappa ? ra.kappa[i] : 0.0;
+    for_each_pair(ra, d, kap, s, [&](double x, double y, double z, double r2, double k) {
+      const RadialK R = radial_k(r2, k);
+      pair_field(qs, x, y, z, R, acc);
+      if (BWD) {
+        double en, g[3];
+        pair_energy_grad(st, x, y, z, R, en, g);
+        acc[10] += qs * g[0];
+        acc[11] += qs * g[1];
+        acc[12] += qs * g[2];
+      }
+    });
+  }
+  double tot[NV];
+  region_block_sum<NV>(acc, tot);
+  if (threadIdx.x != 0) return;
+  if (!BWD) {
+    if (phi) phi[j] += tot[0];
+    if (efield)
+      for (int a = 0; a < 3; a++) efield[3 * j + a] -= tot[1 + a];
+    if (efgrad)
+      for (int t = 0; t < 6; t++) efgrad[6 * j + t] -= 2.0 * tot[4 + t];
+    double e = st.Q * tot[0];
+    for (int a = 0; a < 3; a++) e += st.m[a] * tot[1 + a];
+    for (int t = 0; t < 6; t++) e += ((t == 0 || t == 3 || t == 5) ? 1.0 : 2.0) * st.t[t] * tot[4 + t];
+    e_site[j] = e;
+  } else {
+    for (int a = 0; a < 3; a++) g_qm_xyz[3 * j + a] += tot[10 + a];
+    g_Q[j] += gE * tot[0];
+    for (int a = 0; a < 3; a++) g_mu[3 * j + a] += gE * tot[1 + a];
+    for (int t = 0; t < 6; t++) g_theta[6 * j + t] += gE * ((t == 0 || t == 3 || t == 5) ? 1.0 : 2.0) * tot[4 + t];
+  }
+}
+
+// ------------------------------------------------------------------ MM side (adjoint)
+// One thread per MM atom, the QM sites staged in LDS 256 at a time:
+// dL/dR_i and dL/dq_i of the subtracted pairs with the effective moments.
+__global__ __launch_bounds__(256) void k_region_mm(RegionArgs ra, const double* __restrict__ gE_p,
+                                                   const double* __restrict__ g_phi,
+                                                   const double* __restrict__ g_efield,
+                                                   const double* __restrict__ g_efgrad, double* __restrict__ g_mm_xyz,
+                                                   double* __restrict__ g_mm_q) {
+  __shared__ double sp[256][16];  // offset from the centre (3) and effective moments (10)
+  double C[3];
+  region_centre(ra, C);
+  const double gE = gE_p ? *gE_p : 1.0;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < ra.nm;
+  double d[3] = {0.0, 0.0, 0.0};
+  double q = 0.0, kap = 0.0;
+  if (valid) {
+    centre_offset(ra, C, i, d);
+    q = ra.mm_q[i];
+    kap = ra.kappa ? ra.kappa[i] : 0.0;
+  }
+  double gx = 0.0, gy = 0.0, gz = 0.0, gq = 0.0;
+  for (int t0 = 0; t0 < ra.nq; t0 += 256) {
+    const int jl = t0 + threadIdx.x;
+    __syncthreads();
+    if (jl < ra.nq) {
+      const Site e = eff_site(ra, jl, gE, g_phi, g_efield, g_efgrad);
+      for (int a = 0; a < 3; a++) sp[threadIdx.x][a] = ra.qm_xyz[3 * jl + a] - C[a];
+      sp[threadIdx.x][3] = e.Q;
+      for (int a = 0; a < 3; a++) sp[threadIdx.x][4 + a] = e.m[a];
+      for (int t = 0; t < 6; t++) sp[threadIdx.x][7 + t] = e.t[t];
+    }
+    __syncthreads();
+    if (!valid) continue;
+    const int nt = min(256, ra.nq - t0);
+    for (int jj = 0; jj < nt; jj++) {
+      Site st;
+      const double s[3] = {sp[jj][0], sp[jj][1], sp[jj][2]};
+      st.Q = sp[jj][3];
+      for (int a = 0; a < 3; a++) st.m[a] = sp[jj][4 + a];
+      for (int t = 0; t < 6; t++) st.t[t] = sp[jj][7 + t];
+      for_each_pair(ra, d, kap, s, [&](double x, double y, double z, double r2, double k) {
+        const RadialK R = radial_k(r2, k);
+        double en, g[3];
+        pair_energy_grad(st, x, y, z, R, en, g);
+        // pair term of L: -q en(r), r = R_j - R_i: d/dR_i = +q g, d/dq = -en
+        gx += q * g[0];
+        gy += q * g[1];
+        gz += q * g[2];
+        gq -= en;
+      });
+    }
+  }
+  if (!valid) return;
+  g_mm_xyz[3 * i] += gx;
+  g_mm_xyz[3 * i + 1] += gy;
+  g_mm_xyz[3 * i + 2] += gz;
+  if (g_mm_q) g_mm_q[i] += gq;
+}
+
+// ------------------------------------------------------------------ unit-cell QM-QM pairs
+// Bare tensors up to order 3 of 1/|r|, r = R_a - R_b:
+//   p0 = 1/r, p1 = -r/r^3, p2 = 1/2 (3 r r / r^5 - I / r^3),
+//   p3_abc = 1/2 [ (d_ab r_c + d_ac r_b + d_bc r_a) / r^5 - 5 r_a r_b r_c / r^7 ]
+// The pair form (both orientations of each pair, order-2 truncated):
+//   P = Qa Qb p0 + (Qb mu_a - Qa mu_b).p1 + (Qb th_a + Qa th_b):p2 - 2 mu_a.p2.mu_b
+// One thread per site a sums -dP(a, b)/d(its own inputs) over b != a
+// (P(a,b) = P(b,a), so the ordered-pair half cancels), and -1/2 P for the energy.
+__global__ __launch_bounds__(256) void k_region_qq(RegionArgs ra, int bwd, const double* __restrict__ gE_p,
+                                                   double* __restrict__ e_site, double* __restrict__ g_qm_xyz,
+                                                   double* __restrict__ g_Q, double* __restrict__ g_mu,
+                                                   double* __restrict__ g_theta) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= ra.nq) return;
+  const double gE = bwd ? (gE_p ? *gE_p : 1.0) : 1.0;
+  const double Qa = ra.Q[a];
+  double ma[3], ta[3][3];
+  for (int c = 0; c < 3; c++) ma[c] = ra.mu[3 * a + c];
+  {
+    const double* t = ra.theta + 6 * a;
+    ta[0][0] = t[0]; ta[0][1] = ta[1][0] = t[1]; ta[0][2] = ta[2][0] = t[2];
+    ta[1][1] = t[3]; ta[1][2] = ta[2][1] = t[4]; ta[2][2] = t[5];
+  }
+  double e = 0.0, gr[3] = {0, 0, 0}, gQ = 0.0, gm[3] = {0, 0, 0}, gt[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < ra.nq; b++) {
+    if (b == a) continue;
+    double r[3];
+    for (int c = 0; c < 3; c++) r[c] = ra.qm_xyz[3 * a + c] - ra.qm_xyz[3 * b + c];
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    if (!(r2 > 0.0)) continue;
+    const RadialK R = radial_k(r2, 0.0);
+    const double Qb = ra.Q[b];
+    double mb[3], tb[3][3];
+    for (int c = 0; c < 3; c++) mb[c] = ra.mu[3 * b + c];
+    {
+      const double* t = ra.theta + 6 * b;
+      tb[0][0] = t[0]; tb[0][1] = tb[1][0] = t[1]; tb[0][2] = tb[2][0] = t[2];
+      tb[1][1] = t[3]; tb[1][2] = tb[2][1] = t[4]; tb[2][2] = t[5];
+    }
+    double p1[3], p2[3][3];
+    for (int c = 0; c < 3; c++) p1[c] = -r[c] * R.f3;
+    for (int c = 0; c < 3; c++)
+      for (int d = 0; d < 3; d++) p2[c][d] = 0.5 * (3.0 * r[c] * r[d] * R.f5 - (c == d ? R.f3 : 0.0));
+    const double p0 = R.f1;
+    double P = Qa * Qb * p0;
+    double w[3][3];  // Qb th_a + Qa th_b
+    for (int c = 0; c < 3; c++) P += (Qb * ma[c] - Qa * mb[c]) * p1[c];
+    for (int c = 0; c < 3; c++)
+      for (int d = 0; d < 3; d++) {
+        w[c][d] = Qb * ta[c][d] + Qa * tb[c][d];
+        P += w[c][d] * p2[c][d] - 2.0 * ma[c] * p2[c][d] * mb[d];
+      }
+    e -= 0.5 * P;
+    if (!bwd) continue;
+    // dP/dr_g: order-3 tensor contracted on the fly
+    for (int g = 0; g < 3; g++) {
+      double dg = Qa * Qb * p1[g];
+      for (int c = 0; c < 3; c++) dg += (Qb * ma[c] - Qa * mb[c]) * 2.0 * p2[c][g];
+      for (int c = 0; c < 3; c++)
+        for (int d = 0; d < 3; d++) {
+          double s = 0.0;
+          if (c == d) s += r[g];
+          if (c == g) s += r[d];
+          if (d == g) s += r[c];
+          const double p3 = 0.5 * (s * R.f5 - 5.0 * r[c] * r[d] * r[g] * R.f7);
+          dg += (w[c][d] - 2.0 * ma[c] * mb[d]) * 3.0 * p3;
+        }
+      gr[g] -= dg;
+    }
+    double dQ = Qb * p0;
+    for (int c = 0; c < 3; c++) dQ -= mb[c] * p1[c];
+    for (int c = 0; c < 3; c++)
+      for (int d = 0; d < 3; d++) dQ += tb[c][d] * p2[c][d];
+    gQ -= dQ;
+    for (int c = 0; c < 3; c++) {
+      double dm = Qb * p1[c];
+      for (int d = 0; d < 3; d++) dm -= 2.0 * p2[c][d] * mb[d];
+      gm[c] -= dm;
+    }
+    // stored theta numbers: off-diagonals collect both matrix elements
+    gt[0] -= Qb * p2[0][0];
+    gt[1] -= 2.0 * Qb * p2[0][1];
+    gt[2] -= 2.0 * Qb * p2[0][2];
+    gt[3] -= Qb * p2[1][1];
+    gt[4] -= 2.0 * Qb * p2[1][2];
+    gt[5] -= Qb * p2[2][2];
+  }
+  if (!bwd) {
+    e_site[a] += e;
+    return;
+  }
+  for (int c = 0; c < 3; c++) g_qm_xyz[3 * a + c] += gE * gr[c];
+  g_Q[a] += gE * gQ;
+  for (int c = 0; c < 3; c++) g_mu[3 * a + c] += gE * gm[c];
+  for (int t = 0; t < 6; t++) g_theta[6 * a + t] += gE * gt[t];
+}
+
+// energy += sum of the site energies (one block, fixed order)
+__global__ __launch_bounds__(256) void k_region_energy(int nq, const double* __restrict__ e_site,
+                                                       double* __restrict__ energy) {
+  double v[1] = {0.0};
+  for (int j = threadIdx.x; j < nq; j += 256) v[0] += e_site[j];
+  double tot[1];
+  region_block_sum<1>(v, tot);
+  if (threadIdx.x == 0) energy[0] += tot[0];
+}
+
+hipError_t launch_region_forward(const RegionArgs& ra, double* e_site, double* energy, double* phi, double* efield,
+                                 double* efgrad, hipStream_t s) {
+  if (ra.nq == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_region_qm<0>), dim3(ra.nq), dim3(256), 0, s, ra, nullptr, nullptr, nullptr, nullptr,
+                     e_site, phi, efield, efgrad, nullptr, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_region_qq, dim3((ra.nq + 255) / 256), dim3(256), 0, s, ra, 0, nullptr, e_site, nullptr,
+                     nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_region_energy, dim3(1), dim3(256), 0, s, ra.nq, (const double*)e_site, energy);
+  return hipGetLastError();
+}
+
+hipError_t launch_region_backward(const RegionArgs& ra, const double* gE, const double* g_phi,
+                                  const double* g_efield, const double* g_efgrad, double* g_qm_xyz, double* g_Q,
+                                  double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q, hipStream_t s) {
+  if (ra.nq == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_region_qm<1>), dim3(ra.nq), dim3(256), 0, s, ra, gE, g_phi, g_efield, g_efgrad, nullptr,
+                     nullptr, nullptr, nullptr, g_qm_xyz, g_Q, g_mu, g_theta);
+  hipLaunchKernelGGL(k_region_qq, dim3((ra.nq + 255) / 256), dim3(256), 0, s, ra, 1, gE, nullptr, g_qm_xyz, g_Q,
+                     g_mu, g_theta);
+  if (ra.nm > 0)
+    hipLaunchKernelGGL(k_region_mm, dim3((ra.nm + 255) / 256), dim3(256), 0, s, ra, gE, g_phi, g_efield, g_efgrad,
+                       g_mm_xyz, g_mm_q);
+  return hipGetLastError();
+}
+
+}  // namespace mpe

@@ -62,6 +62,18 @@ class EwaldConfig:
     cell_list: bool = True    # real space over cells of edge >= rcut when the box has >= 3 per axis
 
 
+@dataclass
+class Region:
+    """Region-I / region-II split (paper: periodic QM/MM multipole energy and
+    the Gaussian-charge correction): region I is the sphere of radius r_region
+    around the mean QM position; mm_kappa (Nm,) float64 on the plan's device
+    gives Gaussian exponents (<= 0: point charge), r_gauss the pair cutoff of
+    the Gaussian correction."""
+    r_region: float
+    r_gauss: float = 0.0
+    mm_kappa: object = None
+
+
 def suggest_params(box, rcut: float, tol: float):
     """(alpha, (mx, my, mz)) for a target truncation accuracy tol at this
     real-space cutoff (host-side estimate of the library; no GPU needed)."""
@@ -196,6 +208,38 @@ class Plan:
                                                 _ptr(g_th), _stream_ptr(dev)))
         return energy, g_Q, g_mu, g_th
 
+    # ------------------------------------------------------------------ region I / region II
+    def _region_args(self, region, qm_pos, Q, mu, theta, mm_pos, mm_q):
+        dev = self.device
+        nq, nm = int(Q.shape[0]), int(mm_q.shape[0])
+        kap = region.mm_kappa
+        if kap is not None:
+            kap = _req(kap, (nm,), "mm_kappa", dev)
+        return (nq, _ptr(_req(qm_pos, (nq, 3), "qm_pos", dev)), _ptr(_req(Q, (nq,), "Q", dev)),
+                _ptr(_req(mu, (nq, 3), "mu", dev)), _ptr(_req(theta, (nq, 6), "theta", dev)), nm,
+                _ptr(_req(mm_pos, (nm, 3), "mm_pos", dev)), _ptr(_req(mm_q, (nm,), "mm_q", dev)), _ptr(kap),
+                float(region.r_region), float(region.r_gauss))
+
+    def region_forward(self, region, qm_pos, Q, mu, theta, mm_pos, mm_q, energy, phi=None, efield=None,
+                       efgrad=None):
+        """Add the region-I subtraction and the Gaussian-charge correction
+        (:class:`Region`) to energy, phi, efield, efgrad in place."""
+        args = self._region_args(region, qm_pos, Q, mu, theta, mm_pos, mm_q)
+        with torch.cuda.device(self.device):
+            check(self.lib.ewald_region_forward(self.handle, *args, _ptr(energy), _ptr(phi), _ptr(efield),
+                                                _ptr(efgrad), _stream_ptr(self.device)))
+
+    def region_backward(self, region, qm_pos, Q, mu, theta, mm_pos, mm_q, grads, gE=None, g_phi=None, g_efield=None,
+                        g_efgrad=None):
+        """Add the gradients of the region terms to grads = (g_qm, g_Q, g_mu,
+        g_theta, g_mm, g_q) in place (g_q may be None)."""
+        args = self._region_args(region, qm_pos, Q, mu, theta, mm_pos, mm_q)
+        g_qm, g_Q, g_mu, g_th, g_mm, g_q = grads
+        with torch.cuda.device(self.device):
+            check(self.lib.ewald_region_backward(self.handle, *args, _ptr(gE), _ptr(g_phi), _ptr(g_efield),
+                                                 _ptr(g_efgrad), _ptr(g_qm), _ptr(g_Q), _ptr(g_mu), _ptr(g_th),
+                                                 _ptr(g_mm), _ptr(g_q), _stream_ptr(self.device)))
+
     def batch(self, frames, qm_pos, Q, mu, theta, mm_pos, mm_q, with_grad=True, out=None):
         """frames: list of dicts with box, n_qm, n_mm, qm_offset, mm_offset over packed arrays.
 
@@ -253,12 +297,15 @@ class EwaldFunction(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, plan, qm_pos, Q, mu, theta, mm_pos, mm_q):
+    def forward(ctx, plan, qm_pos, Q, mu, theta, mm_pos, mm_q, region=None):
         energy, phi, efield, efgrad, cbuf = plan.forward(qm_pos, Q, mu, theta, mm_pos, mm_q, want_ctx=True)
+        if region is not None:
+            plan.region_forward(region, qm_pos, Q, mu, theta, mm_pos, mm_q, energy, phi, efield, efgrad)
         # unused outputs get no upstream gradient (None) instead of zeros, so the
         # library can take its energy-only adjoint
         ctx.set_materialize_grads(False)
         ctx.plan = plan
+        ctx.region = region
         ctx.save_for_backward(qm_pos, Q, mu, theta, mm_pos, mm_q, cbuf)
         return energy, phi, efield, efgrad
 
@@ -274,13 +321,22 @@ class EwaldFunction(torch.autograd.Function):
             mm_q.contiguous(), gE=gE, g_phi=None if g_phi is None else g_phi.contiguous(),
             g_efield=None if g_efield is None else g_efield.contiguous(),
             g_efgrad=None if g_efgrad is None else g_efgrad.contiguous(), want_g_mm_q=bool(need[6]))
+        if ctx.region is not None:
+            plan.region_backward(ctx.region, qm_pos.contiguous(), Q.contiguous(), mu.contiguous(),
+                                 theta.contiguous(), mm_pos.contiguous(), mm_q.contiguous(),
+                                 (g_qm, g_Q, g_mu, g_th, g_mm, g_q), gE=gE,
+                                 g_phi=None if g_phi is None else g_phi.contiguous(),
+                                 g_efield=None if g_efield is None else g_efield.contiguous(),
+                                 g_efgrad=None if g_efgrad is None else g_efgrad.contiguous())
         return (None, g_qm if need[1] else None, g_Q if need[2] else None, g_mu if need[3] else None,
-                g_th if need[4] else None, g_mm if need[5] else None, g_q if need[6] else None)
+                g_th if need[4] else None, g_mm if need[5] else None, g_q if need[6] else None, None)
 
 
-def ewald(plan: Plan, qm_pos, Q, mu, theta, mm_pos, mm_q):
-    """Differentiable forward pass: returns (energy, phi, efield, efgrad)."""
-    return EwaldFunction.apply(plan, qm_pos, Q, mu, theta, mm_pos, mm_q)
+def ewald(plan: Plan, qm_pos, Q, mu, theta, mm_pos, mm_q, region: Region | None = None):
+    """Differentiable forward pass: returns (energy, phi, efield, efgrad).
+    With a :class:`Region` the outputs are the region-II quantities (the
+    region-I subtraction and the Gaussian-charge correction added)."""
+    return EwaldFunction.apply(plan, qm_pos, Q, mu, theta, mm_pos, mm_q, region)
 
 
-__all__ = ["EwaldConfig", "Plan", "EwaldFunction", "ewald", "EwaldError"]
+__all__ = ["EwaldConfig", "Plan", "Region", "EwaldFunction", "ewald", "EwaldError"]

@@ -256,6 +256,21 @@ def make_config(cfg: int, frame: int = 0, n_mm_override: int | None = None) -> S
     return s
 
 
+# covalent radii (Angstrom) of H, C, N, O; a Gaussian MM charge takes the
+# exponent 1 / r_cov of its element
+COVALENT_RADII = (0.31, 0.76, 0.71, 0.66)
+
+
+def gaussian_exponents(seed: int, nm: int, point_fraction: float = 0.0) -> np.ndarray:
+    """Seeded Gaussian exponents kappa_i = 1/r_cov for nm MM charges, element
+    drawn uniformly from H, C, N, O; a fraction of them stays point charges
+    (kappa = 0)."""
+    rng = np.random.default_rng(seed)
+    k = 1.0 / np.asarray(COVALENT_RADII)[rng.integers(0, len(COVALENT_RADII), nm)]
+    k[rng.random(nm) < point_fraction] = 0.0
+    return k
+
+
 def random_system(seed: int, nq: int, nm: int, box=(20.0, 20.0, 20.0), alpha: float = 0.35, rcut: float = 8.0,
                   kmax=10, neutral: bool = True, traceless: bool = False, s_mu: float = 0.2, s_th: float = 0.1,
                   min_qm_mm: float = 1.0) -> System:

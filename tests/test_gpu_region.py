@@ -1,0 +1,164 @@
+"""Region-I subtraction and Gaussian-charge correction on the GPU against
+the oracle (Ewald sums plus region terms), element by element: forward
+outputs, gradients with respect to every input, upstream gradients of the
+field outputs, a sphere larger than the box, and gradcheck."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import oracle_ewald, oracle_region
+from paper_2408_03273_amd import workloads as wl
+from paper_2408_03273_amd.ewald import Region, ewald
+from tests import _harness as H
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _leaves(s):
+    dev = torch.device("cuda", 0)
+    return [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev, requires_grad=True)
+            for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+
+
+def _oracle_total(s, r_region, r_gauss, kappa):
+    ew = H.oracle_outputs(s)
+    rg = oracle_region(s.box, r_region, r_gauss, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q, kappa)
+    ref = dict(energy=np.array(ew["energy"] + rg.E), phi=ew["phi"] + rg.phi, efield=ew["efield"] - rg.dphi,
+               efgrad=ew["efgrad"] - 2.0 * rg.hphi, g_qm_pos=ew["g_qm_pos"] + rg.g_qm_pos, g_Q=ew["g_Q"] + rg.g_Q,
+               g_mu=ew["g_mu"] + rg.g_mu, g_theta=ew["g_theta"] + rg.g_theta, g_mm_pos=ew["g_mm_pos"] + rg.g_mm_pos,
+               g_mm_q=ew["g_mm_q"] + rg.g_mm_q)
+    return ref, rg
+
+
+def _gpu_total(s, r_region, r_gauss, kappa):
+    x = _leaves(s)
+    plan = H.make_plan(s)
+    kap = None if kappa is None else torch.tensor(kappa, dtype=torch.float64, device=x[0].device)
+    E, phi, efield, efgrad = ewald(plan, *x, region=Region(r_region, r_gauss, kap))
+    E.backward()
+    torch.cuda.synchronize()
+    out = dict(energy=E, phi=phi, efield=efield, efgrad=efgrad, g_qm_pos=x[0].grad, g_Q=x[1].grad, g_mu=x[2].grad,
+               g_theta=x[3].grad, g_mm_pos=x[4].grad, g_mm_q=x[5].grad)
+    return {k: v.detach().cpu().numpy() for k, v in out.items()}
+
+
+CASES = [
+    # seed, nq, nm, box, alpha, rcut, kmax, r_region, r_gauss, point fraction
+    (61, 9, 1500, (21.0, 22.0, 23.0), 0.33, 9.0, 8, 8.0, 4.0, 0.3),      # sphere inside the cell
+    (62, 12, 2600, (21.0, 22.0, 23.0), 0.33, 9.0, 8, 14.0, 6.0, 0.0),    # sphere beyond half the box
+    (63, 5, 700, (12.4, 12.4, 12.4), 0.45, 6.0, 7, 20.0, 5.0, 0.5),      # sphere of 1.6 box lengths
+    (64, 30, 5000, (30.0, 30.0, 30.0), 0.3, 10.0, 9, 15.5, 0.0, 1.0),    # point charges only, 20 blocks
+    (65, 1, 300, (15.0, 16.0, 17.0), 0.4, 7.0, 6, 0.0, 8.0, 0.0),        # no region I: Gaussian only
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"seed{c[0]}" for c in CASES])
+def test_region_parity(case):
+    seed, nq, nm, box, alpha, rcut, kmax, rr, rg, pf = case
+    s = wl.random_system(seed, nq, nm, box=box, alpha=alpha, rcut=rcut, kmax=kmax, neutral=False)
+    kappa = wl.gaussian_exponents(seed, nm, pf) * 0.4  # wider Gaussians than atoms, so that r_gauss matters
+    print(f"[region] seed={seed} nq={nq} nm={nm} r_region={rr} r_gauss={rg}", flush=True)
+    ref, orr = _oracle_total(s, rr, rg, kappa)
+    got = _gpu_total(s, rr, rg, kappa)
+    print(f"[region] images={orr.n_region_images} gauss_pairs={orr.n_gauss_pairs} E_region={orr.energy}", flush=True)
+    assert orr.n_region_images > 0 or rr == 0.0
+    errs = H.compare(got, ref, H.FWD_KEYS + H.BWD_KEYS)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_region_terms_alone_and_accumulation():
+    """The region entry points add to what the output buffers hold: applied to
+    zeroed buffers they give the region terms alone; applied twice, twice that."""
+    s = wl.random_system(66, 7, 1200, box=(18.0, 19.0, 20.0), alpha=0.35, rcut=8.0, kmax=7, neutral=False)
+    kappa = wl.gaussian_exponents(66, s.nm, 0.2) * 0.5
+    rr, rg = 11.0, 5.0
+    orr = oracle_region(s.box, rr, rg, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q, kappa)
+    plan = H.make_plan(s)
+    d = H.to_dev(s)
+    dev = d["Q"].device
+    reg = Region(rr, rg, torch.tensor(kappa, dtype=torch.float64, device=dev))
+    args = (d["qm_pos"], d["Q"], d["mu"], d["theta"], d["mm_pos"], d["mm_q"])
+    z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=dev)  # noqa: E731
+    E, phi, ef, eg = z(), z(s.nq), z(s.nq, 3), z(s.nq, 6)
+    grads = (z(s.nq, 3), z(s.nq), z(s.nq, 3), z(s.nq, 6), z(s.nm, 3), z(s.nm))
+    for rep in (1, 2):
+        plan.region_forward(reg, *args, E, phi, ef, eg)
+        plan.region_backward(reg, *args, grads)
+        torch.cuda.synchronize()
+        got = dict(energy=E.cpu().numpy(), phi=phi.cpu().numpy(), efield=ef.cpu().numpy(), efgrad=eg.cpu().numpy(),
+                   g_qm_pos=grads[0].cpu().numpy(), g_Q=grads[1].cpu().numpy(), g_mu=grads[2].cpu().numpy(),
+                   g_theta=grads[3].cpu().numpy(), g_mm_pos=grads[4].cpu().numpy(), g_mm_q=grads[5].cpu().numpy())
+        ref = dict(energy=np.array(rep * orr.E), phi=rep * orr.phi, efield=-rep * orr.dphi, efgrad=-2.0 * rep * orr.hphi,
+                   g_qm_pos=rep * orr.g_qm_pos, g_Q=rep * orr.g_Q, g_mu=rep * orr.g_mu, g_theta=rep * orr.g_theta,
+                   g_mm_pos=rep * orr.g_mm_pos, g_mm_q=rep * orr.g_mm_q)
+        errs = H.compare(got, ref, H.FWD_KEYS + H.BWD_KEYS)
+        assert max(errs.values()) <= TOL, (rep, errs)
+
+
+def test_region_upstream_gradients():
+    """L = a E + g_phi.phi + g_F.efield + g_G.efgrad with the region terms.
+    The QM-QM parts (Ewald images and bare unit-cell pairs) scale with a; the
+    QM-MM parts are linear in the moments and take the effective moments
+    (a Q + g_phi, a mu - g_F, a theta - (2,1,1,2,1,2) g_G)."""
+    s = wl.random_system(67, 8, 1700, box=(20.0, 21.0, 22.0), alpha=0.33, rcut=8.5, kmax=8, neutral=False)
+    kappa = wl.gaussian_exponents(67, s.nm, 0.3) * 0.4
+    rr, rg = 12.0, 6.0
+    x = _leaves(s)
+    dev = x[0].device
+    plan = H.make_plan(s)
+    rng = np.random.default_rng(9)
+    a = 0.6
+    gphi, gF, gG = rng.normal(size=s.nq), rng.normal(size=(s.nq, 3)), rng.normal(size=(s.nq, 6))
+    E, phi, efield, efgrad = ewald(plan, *x, region=Region(rr, rg, torch.tensor(kappa, device=dev)))
+    L = (a * E + (torch.tensor(gphi, device=dev) * phi).sum() + (torch.tensor(gF, device=dev) * efield).sum()
+         + (torch.tensor(gG, device=dev) * efgrad).sum())
+    L.backward()
+    mult = np.array([2, 1, 1, 2, 1, 2.0])
+    eQ, emu, eth = a * s.Q + gphi, a * s.mu - gF, a * s.theta - mult * gG
+    o = lambda Q, mu, th, qmqm: oracle_ewald(s.box, s.alpha, s.rcut, s.kmax, s.qm_pos, Q, mu, th, s.mm_pos, s.q,  # noqa: E731
+                                            qmqm=qmqm)
+    r = lambda Q, mu, th, mm, q: oracle_region(s.box, rr, rg, s.qm_pos, Q, mu, th, mm, q,  # noqa: E731
+                                               kappa if len(q) else None)
+    full, qmmm_only, eff = o(s.Q, s.mu, s.theta, True), o(s.Q, s.mu, s.theta, False), o(eQ, emu, eth, False)
+    no_mm = (np.zeros((0, 3)), np.zeros(0))
+    reg_full, reg_qq, reg_eff, reg_eff_qq = (r(s.Q, s.mu, s.theta, s.mm_pos, s.q), r(s.Q, s.mu, s.theta, *no_mm),
+                                             r(eQ, emu, eth, s.mm_pos, s.q), r(eQ, emu, eth, *no_mm))
+    ref = dict(g_qm_pos=a * (full.g_qm_pos - qmmm_only.g_qm_pos) + eff.g_qm_pos
+               + a * reg_qq.g_qm_pos + (reg_eff.g_qm_pos - reg_eff_qq.g_qm_pos),
+               g_Q=a * (full.g_Q + reg_full.g_Q), g_mu=a * (full.g_mu + reg_full.g_mu),
+               g_theta=a * (full.g_theta + reg_full.g_theta),
+               g_mm_pos=eff.g_mm_pos + reg_eff.g_mm_pos, g_mm_q=eff.g_mm_q + reg_eff.g_mm_q)
+    got = dict(g_qm_pos=x[0].grad, g_Q=x[1].grad, g_mu=x[2].grad, g_theta=x[3].grad, g_mm_pos=x[4].grad,
+               g_mm_q=x[5].grad)
+    errs = {k: H.relerr(v.cpu().numpy(), ref[k]) for k, v in got.items()}
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_region_gradcheck_tiny():
+    s = wl.random_system(68, 3, 9, box=(9.0, 9.0, 9.0), alpha=0.6, rcut=4.4, kmax=4, neutral=False)
+    x = _leaves(s)
+    plan = H.make_plan(s)
+    kap = torch.tensor([0.8, 0.0, 1.1, 0.9, 0.7, 0.0, 1.3, 0.6, 1.0], dtype=torch.float64, device=x[0].device)
+    reg = Region(7.0, 4.0, kap)
+
+    def f(*args):
+        return ewald(plan, *args, region=reg)
+
+    assert torch.autograd.gradcheck(f, tuple(x), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_region_rejects_bad_radii():
+    s = wl.random_system(69, 2, 10, box=(9.0, 9.0, 9.0), alpha=0.6, rcut=4.4, kmax=3)
+    plan = H.make_plan(s)
+    d = H.to_dev(s)
+    args = (d["qm_pos"], d["Q"], d["mu"], d["theta"], d["mm_pos"], d["mm_q"])
+    E = torch.zeros((), dtype=torch.float64, device=d["Q"].device)
+    from paper_2408_03273_amd import _lib
+    for rr, rg, code in ((-1.0, 0.0, "EWALD_ERR_ARG"), (float("nan"), 0.0, "EWALD_ERR_ARG"),
+                         (40.0, 0.0, "EWALD_ERR_CUTOFF"), (5.0, 37.0, "EWALD_ERR_CUTOFF")):
+        with pytest.raises(_lib.EwaldError) as ei:
+            plan.region_forward(Region(rr, rg), *args, E)
+        assert code in str(ei.value), (rr, rg, str(ei.value))
+    torch.cuda.synchronize()
+    assert E.item() == 0.0
