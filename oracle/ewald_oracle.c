@@ -898,3 +898,92 @@ int oracle_region(const oracle_region_t* P, int nq, const double* qm_pos, const 
   free(agmm);
   return 0;
 }
+
+/* ======================================================================
+ * Charge-octupole error estimate (main text, Error Control: the leading
+ * error of the quadrupole-truncated expansion is the interaction of the
+ * region-II charges with the QM octupoles; SI: T_abc = 1/3 d/dR_c T_ab).
+ *
+ *   Err(R_cut) = sum_{(i,n): R_cut <= |R_i + n L - C| < r_outer} sum_j
+ *                q_i sum_{abc} Omega_j,abc T_abc(R_j - R_i - n L)
+ *   T_abc(r) = -[5 r_a r_b r_c - r^2 (r_a d_bc + r_b d_ac + r_c d_ab)] / (2 r^7)
+ *
+ * Omega_j is the raw (not traceless) third moment of site j, stored as its
+ * ten distinct components xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz.
+ * Readings frozen here: the site index of the octupole is the QM site j (the
+ * printed formula carries the MM index on Omega); the region-II sum, which
+ * converges absolutely, is truncated at the outer radius r_outer around C;
+ * the same centre C and translate rule as oracle_region.  Every candidate
+ * R_cut is summed from scratch.
+ * ====================================================================== */
+static int oct_index(int a, int b, int c) {
+  /* sort the three indices, then position in xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz */
+  int s[3] = {a, b, c};
+  for (int i = 0; i < 2; i++)
+    for (int k = 0; k < 2 - i; k++)
+      if (s[k] > s[k + 1]) {
+        int t = s[k];
+        s[k] = s[k + 1];
+        s[k + 1] = t;
+      }
+  static const int table[3][3][3] = {
+      {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}},
+      {{1, 3, 4}, {3, 6, 7}, {4, 7, 8}},
+      {{2, 4, 5}, {4, 7, 8}, {5, 8, 9}}};
+  return table[s[0]][s[1]][s[2]];
+}
+
+int oracle_octupole_error(const double box[3], int nq, const double* qm_pos, const double* omega, int nm,
+                          const double* mm_pos, const double* q, int n_r, const double* r_cut, double r_outer,
+                          double* err) {
+  if (nq < 0 || nm < 0 || n_r < 0 || box[0] <= 0.0 || box[1] <= 0.0 || box[2] <= 0.0 || r_outer < 0.0) return -1;
+  double C[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < nq; j++)
+    for (int a = 0; a < 3; a++) C[a] += qm_pos[3 * j + a];
+  for (int a = 0; a < 3; a++) C[a] = nq > 0 ? C[a] / nq : 0.0;
+  for (int k = 0; k < n_r; k++) {
+    long double s = 0.0L;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : s)
+    for (int i = 0; i < nm; i++) {
+      const double* Ri = mm_pos + 3 * i;
+      int N[3];
+      for (int a = 0; a < 3; a++) N[a] = (int)ceil((r_outer + fabs(Ri[a] - C[a])) / box[a]) + 1;
+      for (int nx = -N[0]; nx <= N[0]; nx++)
+        for (int ny = -N[1]; ny <= N[1]; ny++)
+          for (int nz = -N[2]; nz <= N[2]; nz++) {
+            double Ri_n[3] = {Ri[0] + nx * box[0], Ri[1] + ny * box[1], Ri[2] + nz * box[2]};
+            double dC[3] = {Ri_n[0] - C[0], Ri_n[1] - C[1], Ri_n[2] - C[2]};
+            double D = norm3(dC);
+            if (!(D >= r_cut[k] && D < r_outer)) continue;
+            for (int j = 0; j < nq; j++) {
+              double r[3] = {qm_pos[3 * j] - Ri_n[0], qm_pos[3 * j + 1] - Ri_n[1], qm_pos[3 * j + 2] - Ri_n[2]};
+              double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+              double r7 = r2 * r2 * r2 * sqrt(r2);
+              double e = 0.0;
+              for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++)
+                  for (int c = 0; c < 3; c++) {
+                    double dd = 0.0;
+                    if (b == c) dd += r[a];
+                    if (a == c) dd += r[b];
+                    if (a == b) dd += r[c];
+                    double T = -(5.0 * r[a] * r[b] * r[c] - r2 * dd) / (2.0 * r7);
+                    e += omega[10 * j + oct_index(a, b, c)] * T;
+                  }
+              s += q[i] * e;
+            }
+          }
+    }
+    err[k] = (double)s;
+  }
+  return 0;
+}
+
+/* The smallest candidate whose estimate and the next candidate's are both
+ * below eps in magnitude (main text: R_cut is raised in fixed steps from a
+ * lower bound until two consecutive values pass); -1 if no such pair. */
+double oracle_rcut_pick(int n_r, const double* r_cut, const double* err, double eps) {
+  for (int k = 0; k + 1 < n_r; k++)
+    if (fabs(err[k]) < eps && fabs(err[k + 1]) < eps) return r_cut[k];
+  return -1.0;
+}

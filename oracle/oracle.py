@@ -67,6 +67,11 @@ def load(path: str = _LIB) -> ctypes.CDLL:
                                  dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_region.restype = ctypes.c_int
+    lib.oracle_octupole_error.restype = ctypes.c_int
+    lib.oracle_octupole_error.argtypes = [dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp,
+                                          ctypes.c_double, dp]
+    lib.oracle_rcut_pick.restype = ctypes.c_double
+    lib.oracle_rcut_pick.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
     lib.oracle_region.argtypes = [ctypes.POINTER(_RegionParams), ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp,
                                   dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     _lib_cache[path] = lib
@@ -247,3 +252,35 @@ def oracle_region(box, r_region, r_gauss, qm_pos, Q, mu, theta, mm_pos, q, kappa
     en["total"] = float(sum(energy))
     return OracleRegionResult(energy=en, phi=phi, dphi=dphi, hphi=hphi, g_qm_pos=gq, g_Q=gQ, g_mu=gmu, g_theta=gth,
                               g_mm_pos=gm, g_mm_q=gmq, n_region_images=int(counts[0]), n_gauss_pairs=int(counts[1]))
+
+
+OCTUPOLE_COMPONENTS = ("xxx", "xxy", "xxz", "xyy", "xyz", "xzz", "yyy", "yyz", "yzz", "zzz")
+
+
+def oracle_octupole_error(box, qm_pos, omega, mm_pos, q, r_cut, r_outer, lib_path: str | None = None) -> np.ndarray:
+    """Charge-octupole error estimate Err(R_cut) for each candidate R_cut
+    (paper: Error Control).  omega (nq,10): raw third moments in the order of
+    OCTUPOLE_COMPONENTS; region II is R_cut <= |R - C| < r_outer."""
+    lib = load(lib_path) if lib_path else load()
+    qm_pos = _c(qm_pos).reshape(-1, 3)
+    nq = qm_pos.shape[0]
+    om = _c(omega, (nq, 10))
+    mm_pos = _c(mm_pos).reshape(-1, 3)
+    nm = mm_pos.shape[0]
+    q = _c(q, (nm,))
+    rc = _c(np.atleast_1d(r_cut))
+    b = _c(box, (3,))
+    err = np.zeros(rc.size)
+    st = lib.oracle_octupole_error(_ptr(b), nq, _ptr(qm_pos), _ptr(om), nm, _ptr(mm_pos), _ptr(q), rc.size, _ptr(rc),
+                                   float(r_outer), _ptr(err))
+    if st != 0:
+        raise ValueError(f"oracle_octupole_error rejected its arguments (status {st})")
+    return err
+
+
+def oracle_rcut_pick(r_cut, err, eps, lib_path: str | None = None) -> float:
+    """First candidate whose estimate and the next one's are below eps; -1 if none."""
+    lib = load(lib_path) if lib_path else load()
+    rc = _c(np.atleast_1d(r_cut))
+    e = _c(np.atleast_1d(err))
+    return float(lib.oracle_rcut_pick(rc.size, _ptr(rc), _ptr(e), float(eps)))

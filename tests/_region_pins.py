@@ -15,7 +15,7 @@ import math
 
 import numpy as np
 
-from oracle.oracle import oracle_ewald, oracle_region
+from oracle.oracle import oracle_ewald, oracle_octupole_error, oracle_rcut_pick, oracle_region
 
 
 def _z(n, m):
@@ -264,7 +264,71 @@ def region_gauss_limits(lib=None):
     return max(e_tight, e_wide, e_field)
 
 
+# ---------------------------------------------------------------- octupole error estimate
+def octupole_hand(lib=None):
+    """One site at the centre with a single octupole component w and one
+    charge q at offset (a, b, c) from it (r = site - charge = -(a, b, c)).
+    The octupole tensor is one sixth of the third derivative of 1/r:
+      xxx only, charge on the x axis at distance d:  Err = q w / d^4;
+      xyz only (six index orders): Err = 15 q w a b c / r^7.
+    Candidates beyond the charge, or an outer radius inside it, give 0."""
+    L, q, w = 40.0, 0.7, 0.3
+    qm = np.array([[20.0, 20.0, 20.0]])
+    errs = []
+    d = 3.0
+    om = np.zeros((1, 10)); om[0, 0] = w  # noqa: E702
+    e = oracle_octupole_error([L] * 3, qm, om, [[23.0, 20.0, 20.0]], [q], [0.0, 2.9, 3.1], 15.0, lib_path=lib)
+    errs += [abs(e[0] - q * w / d ** 4) / (q * w / d ** 4), abs(e[1] - e[0]) / abs(e[0]), abs(e[2])]
+    a, b, c = 1.2, -0.7, 2.1
+    r = math.sqrt(a * a + b * b + c * c)
+    om = np.zeros((1, 10)); om[0, 4] = w  # noqa: E702
+    e = oracle_octupole_error([L] * 3, qm, om, [[20.0 + a, 20.0 + b, 20.0 + c]], [q], [0.0], 15.0, lib_path=lib)
+    ref = 15.0 * q * w * a * b * c / r ** 7
+    errs.append(abs(e[0] - ref) / abs(ref))
+    e = oracle_octupole_error([L] * 3, qm, om, [[20.0 + a, 20.0 + b, 20.0 + c]], [q], [0.0], 0.5 * r, lib_path=lib)
+    errs.append(abs(e[0]))
+    return max(errs)
+
+
+def octupole_cluster(lib=None):
+    """Point-charge clusters again: exact Coulomb energy minus the multipole
+    energy through quadrupoles is, to leading order, the charge-octupole
+    estimate; what remains is O(h^4), so halving h divides it by 16 (a wrong
+    octupole tensor leaves O(h^3): ratio 8).  Returns |log2(ratio) - 4|."""
+    L, qm, mm, q, kappa, ck, uk = _cluster_system(seed=23)
+    d = []
+    for h in (0.08, 0.04):
+        Q, mu, th = _cluster_moments(ck, uk, h)
+        om = np.einsum("jk,jka,jkb,jkc->jabc", ck, h * uk, h * uk, h * uk)
+        idx = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
+               (2, 2, 2)]
+        om10 = np.stack([om[:, a, b, c] for a, b, c in idx], axis=1)
+        mult2 = -oracle_region([L] * 3, 12.0, 0.0, qm, Q, mu, th, mm, q, lib_path=lib).energy["mm_bare"]
+        oct_ = oracle_octupole_error([L] * 3, qm, om10, mm, q, [0.0], 12.0, lib_path=lib)[0]
+        exact = -_cluster_exact(qm, mm, q, kappa, ck, uk, h, False)
+        d.append(exact - mult2 - oct_)
+    return abs(math.log2(abs(d[0] / d[1])) - 4.0)
+
+
+def rcut_pick(lib=None):
+    """The search takes the first candidate whose estimate and the next one's
+    are both below eps in magnitude."""
+    rc = [13.0, 14.0, 15.0, 16.0, 17.0, 18.0]
+    cases = [([5e-4, 1e-4, 3e-4, 1e-4, 5e-5, 1e-5], 2e-4, 16.0),
+             ([-5e-4, -1e-4, -1.5e-4, 1e-4, 5e-5, 1e-5], 2e-4, 14.0),
+             ([5e-4, 4e-4, 3e-4, 3e-4, 1e-4, 3e-4], 2e-4, -1.0),
+             ([1e-6] * 6, 2e-4, 13.0)]
+    bad = 0
+    for err, eps, want in cases:
+        if oracle_rcut_pick(rc, err, eps, lib_path=lib) != want:
+            bad += 1
+    return float(bad)
+
+
 REGION_PINS = {
+    "octupole_hand": (octupole_hand, 1e-13),
+    "octupole_cluster": (octupole_cluster, 0.15),
+    "rcut_pick": (rcut_pick, 0.0),
     "region_hand": (region_hand, 1e-13),
     "region_cluster": (region_cluster, 0.15),
     "region_qq_sphere": (region_qq_sphere, 1e-2),

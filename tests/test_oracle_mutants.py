@@ -50,6 +50,15 @@ REGION_MUTANTS = [
      "Pv += (Qa * ma[c] - Qb * mb[c]) * p1[c];", 1),
     ("bare QM-QM charge-quadrupole half", "Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];",
      "Pv += 0.5 * (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", 1),
+    ("octupole tensor sign", "double T = -(5.0 * r[a] * r[b] * r[c] - r2 * dd) / (2.0 * r7);",
+     "double T = (5.0 * r[a] * r[b] * r[c] - r2 * dd) / (2.0 * r7);"),
+    ("octupole tensor trace term", "double T = -(5.0 * r[a] * r[b] * r[c] - r2 * dd) / (2.0 * r7);",
+     "double T = -(5.0 * r[a] * r[b] * r[c] - 3.0 * r2 * dd) / (2.0 * r7);"),
+    ("octupole component order", "{{1, 3, 4}, {3, 6, 7}, {4, 7, 8}},", "{{1, 3, 4}, {3, 6, 8}, {4, 8, 7}},"),
+    ("octupole region-II inner bound", "if (!(D >= r_cut[k] && D < r_outer)) continue;",
+     "if (!(D < r_outer)) continue;"),
+    ("R_cut search takes one passing value", "if (fabs(err[k]) < eps && fabs(err[k + 1]) < eps) return r_cut[k];",
+     "if (fabs(err[k]) < eps) return r_cut[k];"),
     ("bare QM-QM theta gradient", "agm[10 * a + 4 + sym6(c, d)] += -0.5L * Qb * p2[c][d];",
      "agm[10 * a + 4 + sym6(c, d)] += -0.25L * Qb * p2[c][d];"),
 ]
