@@ -209,6 +209,27 @@ ewald_status_t ewald_region_backward(ewald_plan* plan, int n_qm, const double* q
                                      const double* g_efgrad, double* g_qm_xyz, double* g_Q, double* g_mu,
                                      double* g_theta, double* g_mm_xyz, double* g_mm_q, void* stream);
 
+/* Charge-octupole error estimate and R_cut search (paper: Error Control:
+ * the leading error of the quadrupole-truncated multipole expansion is the
+ * interaction of the region-II charges with the QM octupoles; R_cut is raised
+ * in fixed steps from a lower bound until two consecutive values give an
+ * estimate below the target accuracy; SI: T_abc = 1/3 d/dR_c T_ab).
+ * For the candidates R_k = r_first + k r_step, k < n_r (1 <= n_r <= 256):
+ *   err[k] = sum over MM translates R_i + n L with R_k <= |R_i + n L - C| < r_outer
+ *            of q_i sum_j sum_abc Omega_j,abc T_abc(R_j - R_i - n L),
+ * C the mean QM position.  omega (Nq,10): raw (not traceless) third moments
+ * of the QM sites, xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz.  The sum
+ * over region II converges absolutely and is truncated at r_outer (at most 4
+ * box lengths, EWALD_ERR_CUTOFF otherwise).  r_cut (device scalar, may be
+ * null) receives the first R_k with |err[k]| < eps and |err[k+1]| < eps, or -1
+ * if no two consecutive candidates pass.  eps is in the energy unit of the
+ * library (Coulomb constant 1: e^2/length).  n_mm may not exceed the plan's
+ * max_mm.  err and r_cut are overwritten; device arrays. */
+ewald_status_t ewald_octupole_error(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* omega,
+                                    int n_mm, const double* mm_xyz, const double* mm_q, int n_r, double r_first,
+                                    double r_step, double r_outer, double eps, double* err, double* r_cut,
+                                    void* stream);
+
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
  * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or

@@ -111,6 +111,7 @@ struct Work {
   int* cell_atoms;    // [cap_mm]             frame-local MM indices sorted by cell
   int* atom_cell;     // [cap_mm]             cell of each MM atom
   double* region_e;   // [cap_qm]             per-site energies of the region-I / Gaussian terms
+  double* oct_part;   // [kMaxOctCandidates][ceil(cap_mm/256)] block partials of the octupole estimate
 };
 
 static constexpr int kMaxCellsPerAxis = 16;
@@ -225,6 +226,21 @@ hipError_t launch_region_forward(const RegionArgs& ra, double* e_site, double* e
 hipError_t launch_region_backward(const RegionArgs& ra, const double* gE, const double* g_phi,
                                   const double* g_efield, const double* g_efgrad, double* g_qm_xyz, double* g_Q,
                                   double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q, hipStream_t s);
+
+// charge-octupole error estimate of region II for candidates r_first + k r_step
+static constexpr int kMaxOctCandidates = 256;
+struct OctArgs {
+  int nq, nm;
+  const double* qm_xyz;
+  const double* omega;  // (nq,10) xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz
+  const double* mm_xyz;
+  const double* mm_q;
+  double box[3];
+  double r_first, r_step, r_outer;
+  int n_r;
+};
+// part: n_r x ceil(nm/256) doubles of workspace; err (n_r) and r_cut (1, may be null) on the device
+hipError_t launch_octupole(const OctArgs& oa, double* part, double eps, double* err, double* r_cut, hipStream_t s);
 
 // forward kernel instances available for the nz chunk
 bool sfac_mm_has_zc(int zc);

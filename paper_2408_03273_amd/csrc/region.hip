@@ -125,13 +125,15 @@ DEV void region_block_sum(double (&v)[N], double (&out)[N]) {
 
 // Geometric centre of the QM atoms (every block computes the same value in
 // the same order).  Called by all 256 threads.
-DEV void region_centre(const RegionArgs& ra, double (&C)[3]) {
+DEV void qm_centre(int nq, const double* __restrict__ qm_xyz, double (&C)[3]) {
   double v[3] = {0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < ra.nq; j += 256)
-    for (int a = 0; a < 3; a++) v[a] += ra.qm_xyz[3 * j + a];
+  for (int j = threadIdx.x; j < nq; j += 256)
+    for (int a = 0; a < 3; a++) v[a] += qm_xyz[3 * j + a];
   region_block_sum<3>(v, C);
-  for (int a = 0; a < 3; a++) C[a] /= (double)ra.nq;
+  for (int a = 0; a < 3; a++) C[a] /= (double)nq;
 }
+
+DEV void region_centre(const RegionArgs& ra, double (&C)[3]) { qm_centre(ra.nq, ra.qm_xyz, C); }
 
 // Offset of an MM atom from the centre, reduced to the nearest translate
 // (|d_a| <= L_a/2); every translate is then d + n L.
@@ -446,6 +448,130 @@ hipError_t launch_region_backward(const RegionArgs& ra, const double* gE, const 
   if (ra.nm > 0)
     hipLaunchKernelGGL(k_region_mm, dim3((ra.nm + 255) / 256), dim3(256), 0, s, ra, gE, g_phi, g_efield, g_efgrad,
                        g_mm_xyz, g_mm_q);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_part(double* __restrict__ p, int n) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0.0;
+}
+
+// ------------------------------------------------------------------ charge-octupole error estimate
+// Err(R_k) = sum over MM translates with R_k <= |R_i,n - C| < r_outer of
+// q_i sum_j Omega_j : T_abc(R_j - R_i,n), for R_k = r_first + k r_step
+// (main text, Error Control; SI, T_abc = 1/3 d T_ab).  With the raw third
+// moment Omega (symmetric; ten stored components) and its trace vector
+// t_a = sum_b Omega_abb:
+//   Omega : T(r) = -[5 Omega(r,r,r) - 3 r^2 (t.r)] / (2 r^7).
+// Grid (MM blocks, candidate chunks of kOctBins): each thread takes one MM
+// atom, visits its translates inside r_outer with the QM sites staged in LDS,
+// and adds each translate's term to the candidates it lies beyond; per-block
+// partial sums go to part[k][block], reduced in a fixed order afterwards.
+static constexpr int kOctBins = 16;
+
+DEV double octupole_energy(const double* om, double x, double y, double z) {
+  const double r2 = x * x + y * y + z * z;
+  const double rrr = om[0] * x * x * x + 3.0 * om[1] * x * x * y + 3.0 * om[2] * x * x * z + 3.0 * om[3] * x * y * y +
+                     6.0 * om[4] * x * y * z + 3.0 * om[5] * x * z * z + om[6] * y * y * y + 3.0 * om[7] * y * y * z +
+                     3.0 * om[8] * y * z * z + om[9] * z * z * z;
+  const double tr = (om[0] + om[3] + om[5]) * x + (om[1] + om[6] + om[8]) * y + (om[2] + om[7] + om[9]) * z;
+  const double r7 = r2 * r2 * r2 * sqrt(r2);
+  return -(5.0 * rrr - 3.0 * r2 * tr) / (2.0 * r7);
+}
+
+__global__ __launch_bounds__(256) void k_octupole(OctArgs oa, double* __restrict__ part) {
+  __shared__ double sp[256][13];  // site offset from the centre (3), Omega (10)
+  double C[3];
+  qm_centre(oa.nq, oa.qm_xyz, C);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = i < oa.nm;
+  const int k0 = blockIdx.y * kOctBins;
+  double d[3] = {0.0, 0.0, 0.0};
+  double q = 0.0;
+  if (valid) {
+    for (int a = 0; a < 3; a++) {
+      const double L = oa.box[a];
+      const double v = oa.mm_xyz[3 * i + a] - C[a];
+      d[a] = v - L * rint(v / L);
+    }
+    q = oa.mm_q[i];
+  }
+  double acc[kOctBins];
+#pragma unroll
+  for (int t = 0; t < kOctBins; t++) acc[t] = 0.0;
+  const double Ro = oa.r_outer;
+  for (int t0 = 0; t0 < oa.nq; t0 += 256) {
+    const int jl = t0 + threadIdx.x;
+    __syncthreads();
+    if (jl < oa.nq) {
+      for (int a = 0; a < 3; a++) sp[threadIdx.x][a] = oa.qm_xyz[3 * jl + a] - C[a];
+      for (int c = 0; c < 10; c++) sp[threadIdx.x][3 + c] = oa.omega[10 * jl + c];
+    }
+    __syncthreads();
+    if (!valid) continue;
+    const int nt = min(256, oa.nq - t0);
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) n_range(d[a], Ro, oa.box[a], lo[a], hi[a]);
+    for (int nx = lo[0]; nx <= hi[0]; nx++)
+      for (int ny = lo[1]; ny <= hi[1]; ny++)
+        for (int nz = lo[2]; nz <= hi[2]; nz++) {
+          const double tx = tr_coord(d[0], nx, oa.box[0]), ty = tr_coord(d[1], ny, oa.box[1]),
+                       tz = tr_coord(d[2], nz, oa.box[2]);
+          const double D2 = tx * tx + ty * ty + tz * tz;
+          if (!(D2 < Ro * Ro)) continue;
+          const double D = sqrt(D2);
+          double e = 0.0;
+          for (int jj = 0; jj < nt; jj++) {
+            const double x = sp[jj][0] - tx, y = sp[jj][1] - ty, z = sp[jj][2] - tz;
+            if (x * x + y * y + z * z > 0.0) e += octupole_energy(&sp[jj][3], x, y, z);
+          }
+          e *= q;
+#pragma unroll
+          for (int kk = 0; kk < kOctBins; kk++) {
+            const int k = k0 + kk;
+            if (k < oa.n_r && D >= oa.r_first + (double)k * oa.r_step) acc[kk] += e;
+          }
+        }
+  }
+  double tot[kOctBins];
+  region_block_sum<kOctBins>(acc, tot);
+  if (threadIdx.x == 0)
+    for (int kk = 0; kk < kOctBins; kk++)
+      if (k0 + kk < oa.n_r) part[(size_t)(k0 + kk) * gridDim.x + blockIdx.x] = tot[kk];
+}
+
+// err[k] = sum of the block partials (fixed order); r_cut = the first R_k
+// whose estimate and the next one's are below eps in magnitude, -1 if none
+__global__ __launch_bounds__(256) void k_octupole_final(OctArgs oa, int nblocks, const double* __restrict__ part,
+                                                        double eps, double* __restrict__ err,
+                                                        double* __restrict__ r_cut) {
+  __shared__ double se[kMaxOctCandidates];
+  for (int k = threadIdx.x; k < oa.n_r; k += 256) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += part[(size_t)k * nblocks + b];
+    se[k] = s;
+    err[k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0 || !r_cut) return;
+  double pick = -1.0;
+  for (int k = 0; k + 1 < oa.n_r; k++)
+    if (fabs(se[k]) < eps && fabs(se[k + 1]) < eps) {
+      pick = oa.r_first + (double)k * oa.r_step;
+      break;
+    }
+  r_cut[0] = pick;
+}
+
+hipError_t launch_octupole(const OctArgs& oa, double* part, double eps, double* err, double* r_cut, hipStream_t s) {
+  const int nb = oa.nm > 0 ? (oa.nm + 255) / 256 : 0;
+  if (nb > 0 && oa.nq > 0) {
+    hipLaunchKernelGGL(k_octupole, dim3(nb, (oa.n_r + kOctBins - 1) / kOctBins), dim3(256), 0, s, oa, part);
+  } else {
+    // no pairs: every estimate is zero
+    hipLaunchKernelGGL(k_zero_part, dim3(1), dim3(256), 0, s, part, oa.n_r);
+  }
+  hipLaunchKernelGGL(k_octupole_final, dim3(1), dim3(256), 0, s, oa, (nb > 0 && oa.nq > 0) ? nb : 1,
+                     (const double*)part, eps, err, r_cut);
   return hipGetLastError();
 }
 

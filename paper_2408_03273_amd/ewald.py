@@ -240,6 +240,27 @@ class Plan:
                                                  _ptr(g_efgrad), _ptr(g_qm), _ptr(g_Q), _ptr(g_mu), _ptr(g_th),
                                                  _ptr(g_mm), _ptr(g_q), _stream_ptr(self.device)))
 
+    def octupole_error(self, qm_pos, omega, mm_pos, mm_q, r_first: float, r_step: float, n_r: int, r_outer: float,
+                       eps: float):
+        """Charge-octupole error estimate of region II for R_cut = r_first +
+        k r_step (k < n_r) and the R_cut the search picks (-1: none); omega
+        (Nq,10) raw third moments xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz,
+        zzz.  Returns (err (n_r,), r_cut ()) as device tensors."""
+        dev = self.device
+        nq, nm = int(qm_pos.shape[0]), int(mm_q.shape[0])
+        qm_pos = _req(qm_pos, (nq, 3), "qm_pos", dev)
+        omega = _req(omega, (nq, 10), "omega", dev)
+        mm_pos = _req(mm_pos, (nm, 3), "mm_pos", dev)
+        mm_q = _req(mm_q, (nm,), "mm_q", dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        err = torch.empty((int(n_r),), **f64)
+        r_cut = torch.empty((), **f64)
+        with torch.cuda.device(dev):
+            check(self.lib.ewald_octupole_error(self.handle, nq, _ptr(qm_pos), _ptr(omega), nm, _ptr(mm_pos),
+                                                _ptr(mm_q), int(n_r), float(r_first), float(r_step), float(r_outer),
+                                                float(eps), _ptr(err), _ptr(r_cut), _stream_ptr(dev)))
+        return err, r_cut
+
     def batch(self, frames, qm_pos, Q, mu, theta, mm_pos, mm_q, with_grad=True, out=None):
         """frames: list of dicts with box, n_qm, n_mm, qm_offset, mm_offset over packed arrays.
 
