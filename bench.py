@@ -177,6 +177,7 @@ def main():
         extra["scf_moments_update"] = _scf_update(make_plan(False), inputs, s, ms)
         extra["plain_path"] = _plain_path(s, dev, nh)
         extra["batch_c4"] = _batch_c4(dev)
+        extra["region_c3"] = _region_c3(make_plan(True), inputs, s)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -212,6 +213,53 @@ def _scf_update(plan, inputs, s, step_ms, calls=20):
     us = (time.perf_counter() - t0) * 1e6 / calls
     plan.close()
     return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
+
+
+def _region_c3(plan, inputs, s, calls=20):
+    """Region-II quantities on the c3 frame: the region-I subtraction (sphere
+    of 16 A around the QM centre) and the Gaussian-charge correction (kappa =
+    1/r_cov, pairs within 5 A), forward and adjoint; and the charge-octupole
+    error estimate for 16 candidate radii 13..28 A (outer radius 35 A)."""
+    import numpy as np
+    import torch
+
+    from paper_2408_03273_amd import workloads as wl
+    from paper_2408_03273_amd.ewald import Region
+    x = [t.detach() for t in inputs]
+    dev = x[0].device
+    reg = Region(16.0, 5.0, torch.tensor(wl.gaussian_exponents(3, s.nm), dtype=torch.float64, device=dev))
+    E = torch.zeros((), dtype=torch.float64, device=dev)
+    phi, ef, eg = (torch.zeros((s.nq,) + sh, dtype=torch.float64, device=dev) for sh in ((), (3,), (6,)))
+    grads = tuple(torch.zeros_like(t) for t in (x[0], x[1], x[2], x[3], x[4], x[5]))
+    omega = torch.tensor(np.random.default_rng(3).normal(0.0, 0.05, (s.nq, 10)), dtype=torch.float64, device=dev)
+
+    def fwd_bwd():
+        plan.region_forward(reg, *x, E, phi, ef, eg)
+        plan.region_backward(reg, *x, grads)
+
+    def octupole():
+        plan.octupole_error(x[0], omega, x[4], x[5], 13.0, 1.0, 16, 35.0, 1e-4)
+
+    out = {}
+    for name, fn in (("fwd_bwd_wall_us", fwd_bwd), ("octupole_wall_us", octupole)):
+        fn()
+        torch.cuda.synchronize()
+        plan.profile_report()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = round((time.perf_counter() - t0) * 1e6 / calls, 1)
+        # GPU time of each entry point's launch sequence (events around it on the stream)
+        for k, v in plan.profile_report().items():
+            out[k + "_gpu_us"] = round(1e3 * v["total_ms"] / max(v["count"], 1), 1)
+    c = s.qm_pos.mean(0)
+    d = s.mm_pos - c
+    d -= s.box * np.rint(d / s.box)
+    out.update(r_region=16.0, r_gauss=5.0, region_translates=int(np.sum(np.sum(d * d, 1) < 16.0 ** 2)),
+               octupole_candidates=16)
+    plan.close()
+    return out
 
 
 def _plain_path(s, dev, nh, steps=5):

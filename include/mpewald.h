@@ -186,8 +186,8 @@ ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm,
  *     theta:That_ab] with the tensors of erfc(kappa_i r)/r.
  * Box: the plan's.  r_region, r_gauss: >= 0 and at most 4 box lengths
  * (EWALD_ERR_CUTOFF otherwise).  Arrays as in ewald_forward, plus mm_kappa
- * (Nm) on the device.  n_qm may not exceed the plan's max_qm; n_mm is not
- * limited by the plan.
+ * (Nm) on the device.  n_qm and n_mm may not exceed the plan's max_qm and
+ * max_mm.
  *
  * ewald_region_forward ADDS the region terms to energy (required), phi,
  * efield and efgrad (each may be null), e.g. to the outputs of an

@@ -612,6 +612,12 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.cell_atoms, cm);
   A(w.atom_cell, cm);
   A(w.region_e, cq);
+  A(w.region_cen, 4);
+  A(w.region_site, cq * kRegionSite);
+  A(w.region_rd, cm);
+  A(w.region_rk, cm);
+  A(w.region_rf, cm);
+  A(w.region_part, cq * kRegionMaxChunks * kRegionNV);
   A(w.oct_part, (size_t)kMaxOctCandidates * ((cm + 255) / 256));
 #undef A
   const double one = 1.0;
@@ -1057,6 +1063,17 @@ extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx
 }
 
 // ---------------------------------------------------------------- region-I / region-II split
+static RegionWork region_work(ewald_plan* plan) {
+  RegionWork rw;
+  rw.cen = plan->w.region_cen;
+  rw.site = plan->w.region_site;
+  rw.rd = plan->w.region_rd;
+  rw.rk = plan->w.region_rk;
+  rw.rf = plan->w.region_rf;
+  rw.part = plan->w.region_part;
+  return rw;
+}
+
 static ewald_status_t region_args(ewald_plan* plan, int n_qm, const double* qm_xyz, const double* Q,
                                   const double* mu, const double* theta, int n_mm, const double* mm_xyz,
                                   const double* mm_q, const double* mm_kappa, double r_region, double r_gauss,
@@ -1064,7 +1081,8 @@ static ewald_status_t region_args(ewald_plan* plan, int n_qm, const double* qm_x
   if (!plan) return fail(EWALD_ERR_ARG, "null plan");
   ewald_status_t st = check_arrays(n_qm, n_mm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
   if (st != EWALD_OK) return st;
-  if (n_qm > plan->cap_qm) return fail(EWALD_ERR_CAPACITY, "n_qm=%d exceeds capacity %d", n_qm, plan->cap_qm);
+  if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
+    return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
   if (!std::isfinite(r_region) || !std::isfinite(r_gauss) || r_region < 0.0 || r_gauss < 0.0)
     return fail(EWALD_ERR_ARG, "r_region=%g r_gauss=%g must be finite and >= 0", r_region, r_gauss);
   const double lmin = std::min(plan->p.box[0], std::min(plan->p.box[1], plan->p.box[2]));
@@ -1080,7 +1098,11 @@ static ewald_status_t region_args(ewald_plan* plan, int n_qm, const double* qm_x
   ra.mm_xyz = mm_xyz;
   ra.mm_q = mm_q;
   ra.kappa = mm_kappa;
-  for (int a = 0; a < 3; a++) ra.box[a] = plan->p.box[a];
+  for (int a = 0; a < 3; a++) {
+    ra.box[a] = plan->p.box[a];
+    ra.inv_box[a] = 1.0 / plan->p.box[a];
+  }
+  ra.half_min = 0.5 * lmin;
   ra.r_region = r_region;
   ra.r_gauss = r_gauss;
   return EWALD_OK;
@@ -1100,7 +1122,7 @@ extern "C" ewald_status_t ewald_region_forward(ewald_plan* plan, int n_qm, const
   ewald_plan* pl = plan;
   hipStream_t s = (hipStream_t)stream;
   LCHK_P(pl, s, "launch_region_forward",
-         launch_region_forward(ra, plan->w.region_e, energy, phi, efield, efgrad, s));
+         launch_region_forward(ra, region_work(plan), plan->w.region_e, energy, phi, efield, efgrad, s));
   return EWALD_OK;
 }
 
@@ -1121,8 +1143,8 @@ extern "C" ewald_status_t ewald_region_backward(ewald_plan* plan, int n_qm, cons
   ewald_plan* pl = plan;
   hipStream_t s = (hipStream_t)stream;
   LCHK_P(pl, s, "launch_region_backward",
-         launch_region_backward(ra, gE, g_phi, g_efield, g_efgrad, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q,
-                                s));
+         launch_region_backward(ra, region_work(plan), gE, g_phi, g_efield, g_efgrad, g_qm_xyz, g_Q, g_mu, g_theta,
+                                g_mm_xyz, g_mm_q, s));
   return EWALD_OK;
 }
 

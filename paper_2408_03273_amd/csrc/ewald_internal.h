@@ -111,6 +111,12 @@ struct Work {
   int* cell_atoms;    // [cap_mm]             frame-local MM indices sorted by cell
   int* atom_cell;     // [cap_mm]             cell of each MM atom
   double* region_e;   // [cap_qm]             per-site energies of the region-I / Gaussian terms
+  double* region_cen;  // [4]
+  double* region_site; // [cap_qm][kRegionSite]
+  double4* region_rd;  // [cap_mm]
+  double* region_rk;   // [cap_mm]
+  int* region_rf;      // [cap_mm]
+  double* region_part; // [cap_qm][kRegionMaxChunks][kRegionNV]
   double* oct_part;   // [kMaxOctCandidates][ceil(cap_mm/256)] block partials of the octupole estimate
 };
 
@@ -217,13 +223,28 @@ struct RegionArgs {
   const double* mm_q;
   const double* kappa;
   double box[3];
+  double inv_box[3];
+  double half_min;  // half the smallest box edge
   double r_region, r_gauss;
 };
+// workspace of one region call (device): centre and QM extent, per-MM-atom
+// offsets, exponents and flags, per-(site, chunk) partial sums
+static constexpr int kRegionMaxChunks = 32;
+static constexpr int kRegionNV = 13;
+static constexpr int kRegionSite = 16;
+struct RegionWork {
+  double* cen;    // [4]
+  double* site;   // [cap_qm][kRegionSite]: offset from the centre (3), (effective) Q, mu, theta
+  double4* rd;    // [cap_mm]
+  double* rk;     // [cap_mm]
+  int* rf;        // [cap_mm]
+  double* part;   // [cap_qm][kRegionMaxChunks][kRegionNV]
+};
 // add the region terms to energy / phi / efield / efgrad (any output but energy may be null)
-hipError_t launch_region_forward(const RegionArgs& ra, double* e_site, double* energy, double* phi, double* efield,
-                                 double* efgrad, hipStream_t s);
+hipError_t launch_region_forward(const RegionArgs& ra, const RegionWork& rw, double* e_site, double* energy,
+                                 double* phi, double* efield, double* efgrad, hipStream_t s);
 // add the gradients of gE x (region terms) + upstream site gradients to the gradient outputs
-hipError_t launch_region_backward(const RegionArgs& ra, const double* gE, const double* g_phi,
+hipError_t launch_region_backward(const RegionArgs& ra, const RegionWork& rw, const double* gE, const double* g_phi,
                                   const double* g_efield, const double* g_efgrad, double* g_qm_xyz, double* g_Q,
                                   double* g_mu, double* g_theta, double* g_mm_xyz, double* g_mm_q, hipStream_t s);
 
