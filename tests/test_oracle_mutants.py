@@ -43,7 +43,8 @@ REGION_MUTANTS = [
     ("region-I minimum image only", "N[a] = (int)ceil((R1 + fabs(Ri[a] - C[a])) / L[a]) + 1;", "N[a] = 0;"),
     ("Gaussian pairs not excluded from region I", "if (norm3(dC) < R1) continue; /* region I: already direct */", ";"),
     ("Gaussian exponent doubled", "region_pair(r, kappa[i], -1.0", "region_pair(r, 2.0 * kappa[i], -1.0"),
-    ("region centre at the origin", "C[a] = nq > 0 ? C[a] / nq : 0.0;", "C[a] = 0.0;"),
+    ("region centre at the origin", "C[a] = nq > 0 ? C[a] / nq : 0.0;", "C[a] = 0.0;", 0),
+    ("octupole centre at the origin", "C[a] = nq > 0 ? C[a] / nq : 0.0;", "C[a] = 0.0;", 1),
     ("bare QM-QM half", "e_qq += -0.5L * Pv;", "e_qq += -1.0L * Pv;"),
     ("bare QM-QM dipole-dipole sign", "Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];", "Pv += 2.0 * ma[c] * p2[c][d] * mb[d];", 1),
     ("bare QM-QM charge-dipole operands swapped", "Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];",
