@@ -178,6 +178,7 @@ def main():
         extra["plain_path"] = _plain_path(s, dev, nh)
         extra["batch_c4"] = _batch_c4(dev)
         extra["region_c3"] = _region_c3(make_plan(True), inputs, s)
+        extra["fp32_recip"] = _fp32_recip(make_plan(False), s, inputs, cache, args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -213,6 +214,47 @@ def _scf_update(plan, inputs, s, step_ms, calls=20):
     us = (time.perf_counter() - t0) * 1e6 / calls
     plan.close()
     return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
+
+
+def _fp32_recip(plan64, s, inputs, cache, no_autotune, steps=20):
+    """The same c3 step with the two reciprocal hot loops on FP32 matrix cores
+    (mixed-precision variant); its deviation from the FP64 path is reported
+    (normwise relative, per output)."""
+    import torch
+
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan, ewald
+
+    def run(plan):
+        x = [t.detach().clone().requires_grad_(True) for t in inputs]
+        E, phi, ef, eg = ewald(plan, *x)
+        E.backward()
+        return [E.detach(), phi.detach(), ef.detach(), eg.detach()] + [t.grad for t in x]
+
+    ref = run(plan64)
+    plan64.close()
+    plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                            precision="fp32_recip"))
+    if not no_autotune:
+        plan.autotune(s.nm, cache)
+    got = run(plan)
+    names = ("energy", "phi", "efield", "efgrad", "g_qm_pos", "g_Q", "g_mu", "g_theta", "g_mm_pos", "g_mm_q")
+    err = {n: float((a - b).abs().max() / b.abs().max()) for n, a, b in zip(names, got, ref)}
+    x = [t.detach().clone().requires_grad_(True) for t in inputs]
+    for _ in range(3):
+        ewald(plan, *x)[0].backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for t in x:
+            t.grad = None
+        ewald(plan, *x)[0].backward()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    desc = plan.describe()
+    plan.close()
+    return dict(frames_per_s=round(1e3 / ms, 1), ms_per_step=round(ms, 4), plan=desc,
+                rel_err_vs_fp64={k: float(f"{v:.2e}") for k, v in err.items()},
+                max_rel_err=float(f"{max(err.values()):.2e}"), dtype="f32 matrix cores, f64 sums")
 
 
 def _region_c3(plan, inputs, s, calls=20):

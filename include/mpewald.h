@@ -62,11 +62,17 @@ typedef enum {
   EWALD_ERR_OOM = -5       /* workspace allocation failed */
 } ewald_status_t;
 
-/* precision of the real-space pair kernel */
+/* precision (bit set; 0 = everything in FP64) */
 enum {
   EWALD_FP64 = 0,          /* everything in FP64 */
-  EWALD_FP32_REAL = 1      /* real-space distances, erfc, exp and tensors in FP32,
-                              accumulated in FP64; reciprocal space stays FP64 */
+  EWALD_FP32_REAL = 1,     /* real-space distances, erfc, exp and tensors in FP32,
+                              accumulated in FP64 */
+  EWALD_FP32_RECIP = 2     /* the two reciprocal-space hot loops (MM structure factor
+                              and MM gradients) on FP32 matrix cores: phase tables and
+                              folded weights rounded to FP32, FP32 accumulation inside
+                              a block, FP64 sums across blocks and everything after;
+                              needs kmax[2] <= 32 and kmax[1] <= 31.  The error against
+                              FP64 is of the order of 1e-6 relative (mixed precision) */
 };
 
 /* flags */
@@ -86,7 +92,7 @@ typedef struct {
   double alpha;    /* Ewald splitting parameter (1/length), > 0 */
   double rcut;     /* real-space cutoff: pairs and lattice images with |r| < rcut */
   int kmax[3];     /* reciprocal cube |n_a| <= kmax[a], each >= 1 */
-  int precision;   /* EWALD_FP64 or EWALD_FP32_REAL */
+  int precision;   /* EWALD_FP64, or EWALD_FP32_REAL and/or EWALD_FP32_RECIP */
   int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT */
   int max_qm;      /* capacity: QM sites per call (sum over frames in a batch) */
   int max_mm;      /* capacity: MM charges per call (sum over frames in a batch) */

@@ -16,6 +16,7 @@ EWALD_ERR_OOM = -5
 
 EWALD_FP64 = 0
 EWALD_FP32_REAL = 1
+EWALD_FP32_RECIP = 2
 
 EWALD_QMQM = 1
 EWALD_PLAIN = 2

@@ -212,6 +212,15 @@ void free_plan(ewald_plan* pl) {
   pl->allocs.clear();
 }
 
+const char* precision_name(int p) {
+  switch (p) {
+    case EWALD_FP32_REAL: return "fp32-real";
+    case EWALD_FP32_RECIP: return "fp32-recip";
+    case EWALD_FP32_REAL | EWALD_FP32_RECIP: return "fp32-real+recip";
+    default: return "fp64";
+  }
+}
+
 void set_describe(ewald_plan* pl) {
   char buf[256];
   static const char* bwd[] = {"",           "valu-horner-1", "valu-horner-2", "mfma-fold-16",
@@ -223,7 +232,7 @@ void set_describe(ewald_plan* pl) {
     snprintf(fwd, sizeof(fwd), "valu zc=%d nzp=%d", pl->g.Zc, pl->g.NZP);
   snprintf(buf, sizeof(buf), "fwd=%s blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", fwd, pl->t.fwd_target,
            bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY,
-           pl->g.NZ, pl->p.precision == EWALD_FP32_REAL ? "fp32-real" : "fp64");
+           pl->g.NZ, precision_name(pl->p.precision));
   pl->describe = buf;
 }
 
@@ -519,7 +528,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     if (p.kmax[a] < 1 || p.kmax[a] > 256) return fail(EWALD_ERR_ARG, "kmax[%d] must be in [1,256]", a);
   ewald_status_t st = validate_box(p.box, p.rcut);
   if (st != EWALD_OK) return st;
-  if (p.precision != EWALD_FP64 && p.precision != EWALD_FP32_REAL) return fail(EWALD_ERR_ARG, "unknown precision");
+  if (p.precision < 0 || p.precision > (EWALD_FP32_REAL | EWALD_FP32_RECIP))
+    return fail(EWALD_ERR_ARG, "unknown precision %d", p.precision);
   if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT))
     return fail(EWALD_ERR_ARG, "unknown flags");
   if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
@@ -564,6 +574,17 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     if (mfma_fwd_ct_ok(pl->g, v)) pl->t.fwd_ct = v;
   }
   if (const char* e = getenv("MPEWALD_FWD_PF")) pl->t.fwd_pf = atoi(e) ? 1 : 0;
+  if (p.precision & EWALD_FP32_RECIP) {
+    // both hot loops on the FP32 matrix cores: matrix-core forward, LDS-y adjoint
+    if (!fp32r_ok(pl->g)) {
+      delete pl;
+      return fail(EWALD_ERR_ARG, "EWALD_FP32_RECIP needs kmax[2] <= 32 and kmax[1] <= 31");
+    }
+    pl->t.fp32r = 1;
+    pl->t.fwd_mode = 1;
+    pl->t.bwd_ilp = 6;
+    if (!fp32r_ct_ok(pl->g, pl->t.fwd_ct)) pl->t.fwd_ct = 1;
+  }
   if (const char* e = getenv("MPEWALD_FWD_TARGET")) {
     const int v = atoi(e);
     if (v >= 64 && v <= 65536) pl->t.fwd_target = v;
@@ -619,12 +640,19 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.region_rf, cm);
   A(w.region_part, cq * kRegionMaxChunks * kRegionNV);
   A(w.oct_part, (size_t)kMaxOctCandidates * ((cm + 255) / 256));
+  if (pl->t.fp32r) {
+    A(w.mm_xy32, cm * g.NXY);
+    A(w.mm_ztab32, cm * g.ZKP);
+    A(w.wfrag32, cf * (size_t)g.NG * g.NK2 * 256);
+  }
 #undef A
   const double one = 1.0;
   // padding entries of the matrix-core operands are never written by the kernels: zero them once
   if (hipMemset(w.wfrag, 0, sizeof(double) * cf * (size_t)g.NG * g.NK2 * 256) != hipSuccess ||
       hipMemset(w.wk0, 0, sizeof(double2) * cf * (size_t)g.NG * 16) != hipSuccess ||
       hipMemset(w.mm_ztab, 0, sizeof(double) * cm * g.ZKP) != hipSuccess ||
+      (w.wfrag32 && hipMemset(w.wfrag32, 0, sizeof(float) * cf * (size_t)g.NG * g.NK2 * 256) != hipSuccess) ||
+      (w.mm_ztab32 && hipMemset(w.mm_ztab32, 0, sizeof(float) * cm * g.ZKP) != hipSuccess) ||
       hipMemcpy(w.one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     free_plan(pl);
     delete pl;
@@ -682,7 +710,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.pl = plan;
   q.s = s;
   q.plain = (plan->p.flags & EWALD_PLAIN) ? 1 : 0;
-  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.fp32 = (plan->p.precision & EWALD_FP32_REAL) != 0;
   q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
   q.max_nq = q.total_nq = n_qm;
   q.max_nm = q.total_nm = n_mm;
@@ -750,7 +778,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   q.pl = plan;
   q.s = s;
   q.plain = 0;
-  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.fp32 = (plan->p.precision & EWALD_FP32_REAL) != 0;
   q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
   q.max_nq = q.total_nq = n_qm;
   q.max_nm = q.total_nm = n_mm;
@@ -826,7 +854,7 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   q.pl = plan;
   q.s = s;
   q.plain = 0;
-  q.fp32 = plan->p.precision == EWALD_FP32_REAL;
+  q.fp32 = (plan->p.precision & EWALD_FP32_REAL) != 0;
   q.qmqm = (plan->p.flags & EWALD_QMQM) ? 1 : 0;
   q.max_nq = max_nq;
   q.max_nm = max_nm;
@@ -1239,7 +1267,8 @@ std::string tune_key(const ewald_plan* pl, int n_mm) {
   const size_t cut = arch.find(':');
   if (cut != std::string::npos) arch = arch.substr(0, cut);
   char buf[160];
-  snprintf(buf, sizeof(buf), "%s k%dx%dx%d zc%d nm%d", arch.c_str(), pl->g.NX, pl->g.NY, pl->g.NZ, pl->g.Zc, bucket);
+  snprintf(buf, sizeof(buf), "%s k%dx%dx%d zc%d nm%d%s", arch.c_str(), pl->g.NX, pl->g.NY, pl->g.NZ, pl->g.Zc, bucket,
+           pl->t.fp32r ? " fp32r" : "");
   return buf;
 }
 
@@ -1378,10 +1407,11 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     std::vector<FwdCand> fc;
     if (mfma_fwd_ok(plan->g))
       for (int ct : {1, 2, 4})
-        if (mfma_fwd_ct_ok(plan->g, ct))
+        if (saved.fp32r ? fp32r_ct_ok(plan->g, ct) : mfma_fwd_ct_ok(plan->g, ct))
           for (int ft : {512, 768, 1024, 1536, 2304})
             for (int xcd : {0, 1}) fc.push_back({1, ct, ft, xcd});
-    for (int ft : {4096, 8192, 16384}) fc.push_back({0, 0, ft, 0});
+    if (!saved.fp32r)  // the FP32 variant has only the matrix-core forward
+      for (int ft : {4096, 8192, 16384}) fc.push_back({0, 0, ft, 0});
     for (const FwdCand& c : fc) {
       plan->t = saved;
       plan->t.fwd_mode = c.mode;
@@ -1412,6 +1442,7 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     for (int bw : {2, 3, 4, 5, 6}) {
       if (bw >= 3 && !mfma_bwd_ok(plan->g)) continue;
       if (bw == 6 && !mfma_bwd_eyl_ok(plan->g)) continue;
+      if (saved.fp32r && bw != 6) continue;  // the FP32 variant has only the LDS-y adjoint
       for (int kc : {0, 1, 2, 4, 8, 16}) {
         if (kc > plan->cap_kc) continue;
         plan->t = saved;

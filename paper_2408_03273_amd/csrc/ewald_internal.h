@@ -118,6 +118,10 @@ struct Work {
   int* region_rf;      // [cap_mm]
   double* region_part; // [cap_qm][kRegionMaxChunks][kRegionNV]
   double* oct_part;   // [kMaxOctCandidates][ceil(cap_mm/256)] block partials of the octupole estimate
+  // FP32 reciprocal variant only (null otherwise): FP32 copies of the matrix-core operands
+  float2* mm_xy32;    // [cap_mm][NXY]
+  float* mm_ztab32;   // [cap_mm][ZKP]
+  float* wfrag32;     // [cap_frames][NG][NK2][4][64]
 };
 
 static constexpr int kMaxCellsPerAxis = 16;
@@ -135,6 +139,7 @@ struct Tuning {
   int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
   int fwd_ct;     // matrix-core forward: 16-column tiles per wave
   int fwd_xcd;    // matrix-core forward: XCD-aware block order (single-frame calls)
+  int fp32r;      // both hot loops on the FP32 matrix cores (mixed-precision variant)
 };
 
 // matrix-core kernels are instantiated for mz <= 32
@@ -262,6 +267,18 @@ struct OctArgs {
 };
 // part: n_r x ceil(nm/256) doubles of workspace; err (n_r) and r_cut (1, may be null) on the device
 hipError_t launch_octupole(const OctArgs& oa, double* part, double eps, double* err, double* r_cut, hipStream_t s);
+
+// FP32 reciprocal variant: operand copies and the two hot loops (matrix-core
+// forward with the plan's tile choice, adjoint with the y phases in LDS)
+hipError_t launch_tab32(const Grid& g, const FrameArg& fa, int max_nm, int cap_mm, Work& w, hipStream_t s);
+hipError_t launch_wfrag32(const Grid& g, const FrameArg& fa, Work& w, hipStream_t s);
+hipError_t launch_sfac_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                            hipStream_t s);
+hipError_t launch_force_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
+                             hipStream_t s);
+inline bool fp32r_ok(const Grid& g) { return mfma_fwd_ok(g) && mfma_bwd_eyl_ok(g); }
+// FP32 forward tiles per wave: the block reduction in FP32 takes half the LDS
+inline bool fp32r_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 12; }
 
 // forward kernel instances available for the nz chunk
 bool sfac_mm_has_zc(int zc);

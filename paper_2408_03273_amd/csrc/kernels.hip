@@ -457,6 +457,7 @@ hipError_t launch_sfac_qm(const Grid& g, const FrameArg& fa, int max_nq, const d
   dim3 grid((g.NCOL * (g.mz + 1) + 63) / 64, fa.n_frames);
   hipLaunchKernelGGL(k_sfac_qm, grid, dim3(256), 0, s, g, fa, Q, mu, theta, qeff, w.qm_tab, with_w, w.sabc, w.wk,
                      w.kw, w.wfrag, w.wk0);
+  if (with_w && w.wfrag32) return launch_wfrag32(g, fa, w, s);
   return hipGetLastError();
 }
 
@@ -625,6 +626,7 @@ static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const Fram
 
 hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                           hipStream_t s) {
+  if (t.fp32r) return launch_sfac_mm32(g, t, fa, max_nm, cap_mm, w, s);
   if (t.fwd_mode == 1) return launch_sfac_mm_mfma(g, t, fa, max_nm, cap_mm, w, s);
   switch (g.Zc) {
     case 7: return launch_sfac_mm_z<7>(g, t, fa, max_nm, cap_mm, w, s);
@@ -1616,6 +1618,7 @@ static void launch_force_mm_t(dim3 grid, hipStream_t s, const Grid& g, const Fra
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
+  if (t.fp32r) return launch_force_mm32(g, t, fa, max_nm, cap_mm, w, s);
   if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 atoms per block
     dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
     const size_t lds = (size_t)64 * (g.NY + 1) * sizeof(double2);
@@ -2566,6 +2569,10 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
     launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, w.mm_xy, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (w.mm_xy32) {
+      e = launch_tab32(g, fa, max_nm, cap_mm, w, s);
+      if (e != hipSuccess) return e;
+    }
   }
   if (max_nq > 0 && (parts & PREP_QM_TAB)) {
     launch_tab(g, fa, 1, 1, max_nq, w.qm4, cap_qm, w.qm_tab, (double*)nullptr, (double2*)nullptr, s);

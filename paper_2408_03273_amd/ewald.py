@@ -56,7 +56,7 @@ class EwaldConfig:
     max_mm: int
     max_frames: int = 1
     qmqm: bool = True
-    precision: str = "fp64"   # or "fp32_real"
+    precision: str = "fp64"   # or "fp32_real", "fp32_recip" (reciprocal hot loops), "fp32_all"
     plain: bool = False       # unoptimised reference GPU path for the forward pass
     profile: object = False   # True: bracket every launch with HIP events; "hot": only the two hot loops
     cell_list: bool = True    # real space over cells of edge >= rcut when the box has >= 3 per axis
@@ -100,7 +100,9 @@ class Plan:
         p.rcut = float(cfg.rcut)
         km = (int(cfg.kmax),) * 3 if isinstance(cfg.kmax, int) else tuple(int(k) for k in cfg.kmax)
         p.kmax[:] = km
-        p.precision = {"fp64": _lib.EWALD_FP64, "fp32_real": _lib.EWALD_FP32_REAL}[cfg.precision]
+        p.precision = {"fp64": _lib.EWALD_FP64, "fp32_real": _lib.EWALD_FP32_REAL,
+                       "fp32_recip": _lib.EWALD_FP32_RECIP,
+                       "fp32_all": _lib.EWALD_FP32_REAL | _lib.EWALD_FP32_RECIP}[cfg.precision]
         p.flags = ((_lib.EWALD_QMQM if cfg.qmqm else 0) | (_lib.EWALD_PLAIN if cfg.plain else 0)
                    | (_lib.EWALD_PROFILE_HOT if cfg.profile == "hot" else _lib.EWALD_PROFILE if cfg.profile else 0)
                    | (_lib.EWALD_CELL_LIST if cfg.cell_list else 0))
