@@ -59,6 +59,8 @@ def _params(**kw):
     (dict(kmax=(0, 8, 8)), _lib.EWALD_ERR_ARG),
     (dict(box=(20.0, -1.0, 20.0)), _lib.EWALD_ERR_ARG),
     (dict(precision=7), _lib.EWALD_ERR_ARG),
+    (dict(precision=4), _lib.EWALD_ERR_ARG),
+    (dict(precision=-1), _lib.EWALD_ERR_ARG),
     (dict(flags=1 << 10), _lib.EWALD_ERR_ARG),
     (dict(caps=(10, 100, 0)), _lib.EWALD_ERR_ARG),
 ])

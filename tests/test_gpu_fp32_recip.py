@@ -96,3 +96,13 @@ def test_fp32_recip_batch_against_oracle():
         errs = {k: H.relerr(np.asarray(got[k]), np.asarray(g[k])) for k in H.FWD_KEYS + H.BWD_KEYS}
         print(f"[fp32-recip] c4 frame {i}:", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
         assert max(errs.values()) <= TOL32, (i, errs)
+
+
+def test_fp32_recip_rejects_grids_without_its_kernels():
+    from paper_2408_03273_amd import _lib
+    with pytest.raises(_lib.EwaldError) as ei:
+        Plan(EwaldConfig(box=(40.0, 40.0, 40.0), alpha=0.3, rcut=9.0, kmax=(8, 8, 40), max_qm=4, max_mm=10,
+                         precision="fp32_recip"))
+    assert "EWALD_ERR_ARG" in str(ei.value)
+    # the FP64 path takes the same grid (VALU kernels)
+    Plan(EwaldConfig(box=(40.0, 40.0, 40.0), alpha=0.3, rcut=9.0, kmax=(8, 8, 40), max_qm=4, max_mm=10)).close()
