@@ -325,7 +325,45 @@ def rcut_pick(lib=None):
     return float(bad)
 
 
+def region_boundary_jump(lib=None):
+    """An MM charge crossing the region-I sphere.  Inside, the QM code treats
+    it exactly (here: QM sites made of point charges, exact Coulomb) and the
+    library subtracts its bare multipole term; outside, it is part of the
+    multipole Ewald sum only.  The Ewald sums are continuous in the position,
+    so the jump of the total energy across the boundary is minus (exact -
+    quadrupole-truncated multipole) of that charge: to leading order minus
+    its charge-octupole term, i.e. minus the error estimate (paper: Error
+    Control, and the smoothness of the energy surface across R_cut).
+    Returns |jump + Err| / |Err|."""
+    L, qm, mm, q, kappa, ck, uk = _cluster_system(seed=31)
+    h = 0.3
+    Q, mu, th = _cluster_moments(ck, uk, h)
+    om = np.einsum("jk,jka,jkb,jkc->jabc", ck, h * uk, h * uk, h * uk)
+    idx = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
+           (2, 2, 2)]
+    om10 = np.stack([om[:, a, b, c] for a, b, c in idx], axis=1)
+    rc = 8.0
+    C = qm.mean(0)
+    e = np.array([0.6, -0.48, 0.64])
+    qx = 0.7
+    vals = []
+    for d in (rc - 1e-7, rc + 1e-7):
+        p = C + d * e
+        exact_I = 0.0
+        if d < rc:
+            for j in range(qm.shape[0]):
+                for k in range(ck.shape[1]):
+                    exact_I += qx * ck[j, k] / float(np.linalg.norm(qm[j] + h * uk[j, k] - p))
+        bare = oracle_region([L] * 3, rc, 0.0, qm, Q, mu, th, p[None, :], [qx], lib_path=lib).energy["mm_bare"]
+        vals.append(exact_I + bare)
+    jump = vals[1] - vals[0]
+    err = oracle_octupole_error([L] * 3, qm, om10, (C + (rc + 1e-7) * e)[None, :], [qx], [rc], 20.0,
+                                lib_path=lib)[0]
+    return abs(jump + err) / abs(err)
+
+
 REGION_PINS = {
+    "region_boundary_jump": (region_boundary_jump, 0.2),
     "octupole_hand": (octupole_hand, 1e-13),
     "octupole_cluster": (octupole_cluster, 0.15),
     "rcut_pick": (rcut_pick, 0.0),

@@ -162,3 +162,35 @@ def test_region_rejects_bad_radii():
         assert code in str(ei.value), (rr, rg, str(ei.value))
     torch.cuda.synchronize()
     assert E.item() == 0.0
+
+
+@pytest.mark.parametrize("rr", [16.0, 9.0])
+def test_region_c3_size(rr):
+    """The benchmark's region measurement: the c3 frame, a 16 A sphere (all
+    MM charges within 5 A of a QM site lie inside it) and a 9 A one (QM sites
+    near the boundary have Gaussian pairs outside it), the Gaussian correction
+    within 5 A with exponents 1/r_cov; region terms alone against the oracle,
+    every output in full."""
+    s = wl.make_config(3)
+    kappa = wl.gaussian_exponents(3, s.nm)
+    orr = oracle_region(s.box, rr, 5.0, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q, kappa)
+    assert orr.n_gauss_pairs > 0 or rr > 11.0
+    print(f"[region] c3: images={orr.n_region_images} gauss_pairs={orr.n_gauss_pairs}", flush=True)
+    plan = H.make_plan(s)
+    d = H.to_dev(s)
+    dev = d["Q"].device
+    reg = Region(rr, 5.0, torch.tensor(kappa, dtype=torch.float64, device=dev))
+    args = (d["qm_pos"], d["Q"], d["mu"], d["theta"], d["mm_pos"], d["mm_q"])
+    z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=dev)  # noqa: E731
+    E, phi, ef, eg = z(), z(s.nq), z(s.nq, 3), z(s.nq, 6)
+    grads = (z(s.nq, 3), z(s.nq), z(s.nq, 3), z(s.nq, 6), z(s.nm, 3), z(s.nm))
+    plan.region_forward(reg, *args, E, phi, ef, eg)
+    plan.region_backward(reg, *args, grads)
+    torch.cuda.synchronize()
+    got = dict(energy=E.cpu().numpy(), phi=phi.cpu().numpy(), efield=ef.cpu().numpy(), efgrad=eg.cpu().numpy(),
+               g_qm_pos=grads[0].cpu().numpy(), g_Q=grads[1].cpu().numpy(), g_mu=grads[2].cpu().numpy(),
+               g_theta=grads[3].cpu().numpy(), g_mm_pos=grads[4].cpu().numpy(), g_mm_q=grads[5].cpu().numpy())
+    ref = dict(energy=np.array(orr.E), phi=orr.phi, efield=-orr.dphi, efgrad=-2.0 * orr.hphi, g_qm_pos=orr.g_qm_pos,
+               g_Q=orr.g_Q, g_mu=orr.g_mu, g_theta=orr.g_theta, g_mm_pos=orr.g_mm_pos, g_mm_q=orr.g_mm_q)
+    errs = H.compare(got, ref, H.FWD_KEYS + H.BWD_KEYS)
+    assert max(errs.values()) <= TOL, errs
