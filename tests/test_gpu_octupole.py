@@ -64,3 +64,9 @@ def test_octupole_empty_cases():
     s = wl.random_system(76, 4, 50, box=(20.0, 20.0, 20.0))
     got, rc = _run(s, _omega(76, 4), 5.0, 1.0, 1, 9.0, 1e-6)  # one candidate: no consecutive pair
     assert rc == -1.0
+
+
+def test_octupole_no_qm_sites():
+    s = wl.random_system(77, 0, 40, box=(20.0, 20.0, 20.0))
+    got, rc = _run(s, np.zeros((0, 10)), 3.0, 1.0, 4, 9.0, 1e-6)
+    assert np.all(got == 0.0) and rc == 3.0

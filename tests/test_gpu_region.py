@@ -194,3 +194,30 @@ def test_region_c3_size(rr):
                g_Q=orr.g_Q, g_mu=orr.g_mu, g_theta=orr.g_theta, g_mm_pos=orr.g_mm_pos, g_mm_q=orr.g_mm_q)
     errs = H.compare(got, ref, H.FWD_KEYS + H.BWD_KEYS)
     assert max(errs.values()) <= TOL, errs
+
+
+def test_region_edge_cases():
+    """No MM atoms: only the bare QM-QM pairs; one QM site: no pairs at all;
+    no QM sites: nothing is added."""
+    from paper_2408_03273_amd.ewald import Plan, EwaldConfig  # noqa: F401
+    dev = torch.device("cuda", 0)
+    for nq, nm in ((6, 0), (1, 50), (0, 50)):
+        s = wl.random_system(90 + nq, nq, nm, box=(16.0, 17.0, 18.0), alpha=0.4, rcut=7.0, kmax=5, neutral=False)
+        kappa = wl.gaussian_exponents(90, nm) * 0.4
+        orr = oracle_region(s.box, 9.0, 6.0, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q, kappa)
+        plan = H.make_plan(s, max_qm=max(nq, 1), max_mm=max(nm, 1))
+        d = H.to_dev(s)
+        reg = Region(9.0, 6.0, torch.tensor(kappa, dtype=torch.float64, device=dev))
+        args = (d["qm_pos"], d["Q"], d["mu"], d["theta"], d["mm_pos"], d["mm_q"])
+        z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=dev)  # noqa: E731
+        E, phi, ef, eg = z(), z(nq), z(nq, 3), z(nq, 6)
+        grads = (z(nq, 3), z(nq), z(nq, 3), z(nq, 6), z(nm, 3), z(nm))
+        plan.region_forward(reg, *args, E, phi, ef, eg)
+        plan.region_backward(reg, *args, grads)
+        torch.cuda.synchronize()
+        assert abs(E.item() - orr.E) <= 1e-10 * max(1.0, abs(orr.E)), (nq, nm, E.item(), orr.E)
+        for got, ref in ((grads[0], orr.g_qm_pos), (grads[1], orr.g_Q), (grads[2], orr.g_mu), (grads[3], orr.g_theta),
+                         (grads[4], orr.g_mm_pos), (grads[5], orr.g_mm_q), (phi, orr.phi)):
+            assert H.relerr(got.cpu().numpy(), ref) <= TOL, (nq, nm)
+        if nq == 0:
+            assert E.item() == 0.0 and float(grads[4].abs().max()) == 0.0
