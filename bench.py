@@ -179,6 +179,7 @@ def main():
         extra["batch_c4"] = _batch_c4(dev)
         extra["region_c3"] = _region_c3(make_plan(True), inputs, s)
         extra["fp32_recip"] = _fp32_recip(make_plan(False), s, inputs, cache, args.no_autotune)
+        extra["per_config"] = _per_config(dev, args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -214,6 +215,81 @@ def _scf_update(plan, inputs, s, step_ms, calls=20):
     us = (time.perf_counter() - t0) * 1e6 / calls
     plan.close()
     return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
+
+
+def _per_config(dev, no_autotune, steps=5):
+    """Every configuration against the algorithmic model (14 flops per (k, MM
+    atom) forward + adjoint, 8 forward only): c1, c2 as single frames through
+    autograd, c5 as one batched call of its 16 replicas, and the plain forward
+    path (one thread per k, sincos per term) on c1, c2, c3 and one c5 replica."""
+    import numpy as np
+    import torch
+
+    from paper_2408_03273_amd import workloads as wl
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan, ewald
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    def frac(fl, ms):
+        return round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+
+    out = {}
+    for cfg in (1, 2):
+        s = wl.make_config(cfg)
+        nh = n_half_space(s.kmax)
+        plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm))
+        if not no_autotune:
+            plan.autotune(s.nm)
+        x = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)
+             for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+
+        def step():
+            for t in x:
+                t.grad = None
+            ewald(plan, *x)[0].backward()
+
+        ms = timed(step, 4 * steps)
+        out[f"c{cfg}"] = dict(n_mm=s.nm, n_kvec_half_space=nh, ms_per_frame_fwd_bwd=round(ms, 4),
+                              frames_per_s=round(1e3 / ms, 1), frac_of_fp64_peak=frac(14.0 * nh * s.nm, ms))
+        plan.close()
+    frames = [wl.make_config(5, f) for f in range(16)]
+    qoff = np.cumsum([0] + [f.nq for f in frames])
+    moff = np.cumsum([0] + [f.nm for f in frames])
+    desc = [dict(box=f.box, n_qm=f.nq, n_mm=f.nm, qm_offset=int(qoff[i]), mm_offset=int(moff[i]))
+            for i, f in enumerate(frames)]
+    cat = lambda k: torch.tensor(np.concatenate([getattr(f, k) for f in frames]), dtype=torch.float64,  # noqa: E731
+                                 device=dev)
+    xb = [cat("qm_pos"), cat("Q"), cat("mu"), cat("theta"), cat("mm_pos"), cat("q")]
+    f0 = frames[0]
+    nh5 = n_half_space(f0.kmax)
+    plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
+                            max_mm=int(moff[-1]), max_frames=16))
+    if not no_autotune:
+        plan.autotune(f0.nm)
+    ob = plan.batch(desc, *xb)
+    ms = timed(lambda: plan.batch(desc, *xb, out=ob), steps)
+    out["c5_batch"] = dict(frames=16, total_mm=int(moff[-1]), n_kvec_half_space=nh5, ms_per_batch=round(ms, 3),
+                           frames_per_s=round(16e3 / ms, 1), frac_of_fp64_peak=frac(14.0 * nh5 * float(moff[-1]), ms))
+    plan.close()
+    plain = {}
+    for cfg in (1, 2, 3, 5):
+        s = wl.make_config(cfg)
+        nh = n_half_space(s.kmax)
+        plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                                plain=True))
+        x = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+        ms = timed(lambda: plan.forward(*x), 2 if cfg == 5 else steps)
+        plain[f"c{cfg}"] = dict(ms_per_frame_fwd=round(ms, 3), frac_of_fp64_peak=frac(8.0 * nh * s.nm, ms))
+        plan.close()
+    out["plain_forward"] = plain
+    return out
 
 
 def _fp32_recip(plan64, s, inputs, cache, no_autotune, steps=20):
