@@ -168,7 +168,9 @@ static constexpr int kTabMaxZ = 64;     // real z entries per row held in LDS
 __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, int with_ez,
                                                   const double* __restrict__ pos4, int cap, double2* __restrict__ tab,
                                                   double* __restrict__ ztab, double2* __restrict__ xy) {
-  __shared__ double2 rows[kTabAtoms][kTabMaxR + 1];
+  // complex rows in dynamic LDS, sized for the entries actually built (row
+  // stride nc + 1), so that more blocks fit a CU when the z part is not built
+  extern __shared__ double2 rowbuf[];
   __shared__ double zrows[kTabAtoms][kTabMaxZ + 1];
   __shared__ double2 base[kTabAtoms][3];
   const int f = blockIdx.y;
@@ -179,6 +181,8 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
   if (a0 >= n_atoms) return;  // uniform over the block
   const int na = min(kTabAtoms, n_atoms - a0);
   const int nc = g.NX + g.NY + (with_ez ? g.NZP : 0);  // complex entries built per row
+  const int rs = nc + 1;
+  auto rows = [&](int a, int c) -> double2& { return rowbuf[a * rs + c]; };
   const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
             rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
   const int runs = rx + ry + rz + rr;
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
         zrows[a][first + e] = v.x;
         zrows[a][g.mz + first + e] = v.y;
       } else {
-        rows[a][first + e] = e < limit ? v : make_double2(0.0, 0.0);
+        rows(a, first + e) = e < limit ? v : make_double2(0.0, 0.0);
       }
       v = cmul(v, step);
     }
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
     double2* __restrict__ o = tab + (size_t)(off + a0) * g.R;
     for (int e = threadIdx.x; e < na * g.R; e += 256) {
       const int a = e / g.R, c = e - a * g.R;
-      o[e] = rows[a][c];
+      o[e] = rows(a, c);
     }
   }
   if (xy) {
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
     double2* __restrict__ o = xy + (size_t)(off + a0) * g.NXY;
     for (int e = threadIdx.x; e < na * g.NXY; e += 256) {
       const int a = e / g.NXY, c = e - a * g.NXY;
-      o[e] = rows[a][c];
+      o[e] = rows(a, c);
     }
   }
   if (ztab) {
@@ -263,7 +267,6 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
       ztab[(size_t)(off + a0 + a) * g.ZKP + c] = zrows[a][c];
     }
   }
-  (void)nc;
 }
 
 // Grids whose rows do not fit the LDS tile: one thread per entry, each from its own sincospi.
@@ -318,7 +321,8 @@ static void launch_tab(const Grid& g, const FrameArg& fa, int qm_side, int with_
                        int cap, double2* tab, double* ztab, double2* xy, hipStream_t s) {
   if (g.R <= kTabMaxR && 2 * g.mz <= kTabMaxZ) {
     dim3 grid((max_n + kTabAtoms - 1) / kTabAtoms, fa.n_frames);
-    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), 0, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab, xy);
+    const size_t lds = (size_t)kTabAtoms * (g.NX + g.NY + (with_ez ? g.NZP : 0) + 1) * sizeof(double2);
+    hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), lds, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab, xy);
   } else {
     const long per = g.NX + g.NY + (with_ez ? g.NZP : 0) + (ztab ? g.mz : 0);
     dim3 grid((unsigned)(((long)max_n * per + 255) / 256), fa.n_frames);
