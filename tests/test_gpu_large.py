@@ -37,14 +37,21 @@ def _check(got, g, name):
     assert max(errs.values()) <= TOL, (name, errs)
 
 
-def test_c3_autograd_full_size():
+@pytest.mark.parametrize("tuned", [False, True])
+def test_c3_autograd_full_size(tuned, tmp_path):
+    """c3 as the benchmark runs it: autograd, the plan that brackets the hot
+    loops with events, and (tuned) the tiles the autotuner picks."""
     s = wl.make_config(3)
     g = _golden("c3_f0")
     assert s.sha256() == g["input_sha256"], "generator output changed"
     dev = torch.device("cuda", 0)
     x = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)
          for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
-    plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm))
+    plan = Plan(EwaldConfig(box=tuple(s.box), alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, max_qm=s.nq, max_mm=s.nm,
+                            profile="hot" if tuned else False))
+    if tuned:
+        plan.autotune(s.nm, str(tmp_path / "tune.jsonl"))
+        print("[large] c3 tuned plan:", plan.describe(), flush=True)
     E, phi, efield, efgrad = ewald(plan, *x)
     E.backward()
     got = dict(energy=E.item(), phi=phi.detach().cpu().numpy(), efield=efield.detach().cpu().numpy(),
@@ -54,7 +61,7 @@ def test_c3_autograd_full_size():
     _check(got, g, "c3")
 
 
-def _batch_config(cfg, nframes, check):
+def _batch_config(cfg, nframes, check, tune=False):
     frames = [wl.make_config(cfg, f) for f in range(nframes)]
     qoff = np.cumsum([0] + [f.nq for f in frames])
     moff = np.cumsum([0] + [f.nm for f in frames])
@@ -67,7 +74,9 @@ def _batch_config(cfg, nframes, check):
     f0 = frames[0]
     plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
                             max_mm=int(moff[-1]), max_frames=nframes))
-    print(f"[large] c{cfg}: {nframes} frames, {int(moff[-1])} MM rows", flush=True)
+    if tune:  # as the benchmark's per-configuration measurement
+        plan.autotune(f0.nm)
+    print(f"[large] c{cfg}: {nframes} frames, {int(moff[-1])} MM rows, {plan.describe()}", flush=True)
     out = plan.batch(desc, *x)
     out = plan.batch(desc, *x, out=out)   # second call replays the graph
     torch.cuda.synchronize()
@@ -86,5 +95,6 @@ def test_c4_batch_64_frames():
     _batch_config(4, 64, check=(0, 1, 2))
 
 
-def test_c5_batch_16_replicas():
-    _batch_config(5, 16, check=(0,))
+@pytest.mark.parametrize("tune", [False, True])
+def test_c5_batch_16_replicas(tune):
+    _batch_config(5, 16, check=(0,), tune=tune)
