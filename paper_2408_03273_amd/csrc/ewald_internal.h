@@ -145,8 +145,10 @@ struct Tuning {
 // matrix-core kernels are instantiated for mz <= 32
 inline bool mfma_fwd_ok(const Grid& g) { return g.NT >= 1 && g.NT <= 4; }
 inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
-// the y-phase LDS tile of 64 atoms must fit in 64 KB
-inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && 64 * (g.NY + 1) * 16 <= 65536; }
+// the y-phase LDS tile must fit in 64 KB: 64 atoms per block, or 32 when 64
+// rows of the y grid do not fit
+inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && 32 * (g.NY + 1) * 16 <= 65536; }
+inline int eyl_waves(const Grid& g) { return 64 * (g.NY + 1) * 16 <= 65536 ? 4 : 2; }
 // the forward tiles per wave are limited by the LDS of the block reduction
 inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
 inline int fwd_col_groups(const Grid& g, const Tuning& t) {

@@ -1395,20 +1395,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
 // column group, and from LDS these re-reads no longer compete for L2 with the
 // other blocks (from L2 they spilled to HBM).  The B operand (the folded
 // weights of one frame, ~2 MB at |n| <= 24) is read from L2.  The LDS tile is
-// 64 x (NY + 1) complex entries, dynamic.
-template <int NK>
+// (16 WV) x (NY + 1) complex entries, dynamic: WV = 4 waves (64 atoms) per
+// block, or 2 (32 atoms) when 64 rows of a large y grid do not fit 64 KB.
+template <int NK, int WV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
     Grid g, FrameArg fa, int kc_n, int cap_mm, const double2* __restrict__ tab, const double* __restrict__ ztab,
     const double* __restrict__ wfrag, const double2* __restrict__ wk0, double* __restrict__ fpart) {
-  extern __shared__ double2 eysh[];  // [64][NY + 1]
+  extern __shared__ double2 eysh[];  // [16 WV][NY + 1]
+  constexpr int NA = 16 * WV;        // atoms per block
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
-  const int ablk = blockIdx.x * 64;
+  const int ablk = blockIdx.x * NA;
   if (ablk >= fr.nm) return;  // uniform over the block
   const int ys = g.NY + 1;
-  for (int e = threadIdx.x; e < 64 * g.NY; e += 256) {
+  for (int e = threadIdx.x; e < NA * g.NY; e += 64 * WV) {
     const int a = e / g.NY, c = e - a * g.NY;
     eysh[a * ys + c] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
   }
@@ -1623,13 +1625,18 @@ hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, i
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
   if (t.fp32r) return launch_force_mm32(g, t, fa, max_nm, cap_mm, w, s);
-  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 atoms per block
-    dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
-    const size_t lds = (size_t)64 * (g.NY + 1) * sizeof(double2);
-#define FE(N)                                                                                                    \
-  case N:                                                                                                        \
-    hipLaunchKernelGGL((k_force_mm_eyl<N>), grid, dim3(256), lds, s, g, fa, t.kc, cap_mm, w.mm_xy, w.mm_ztab, \
-                       w.wfrag, w.wk0, w.fpart);                                                                 \
+  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 (or 32) atoms per block
+    const int wv = eyl_waves(g);
+    dim3 grid((max_nm + 16 * wv - 1) / (16 * wv), t.kc, fa.n_frames);
+    const size_t lds = (size_t)16 * wv * (g.NY + 1) * sizeof(double2);
+#define FE(N)                                                                                                  \
+  case N:                                                                                                      \
+    if (wv == 4)                                                                                               \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 4>), grid, dim3(256), lds, s, g, fa, t.kc, cap_mm, w.mm_xy,       \
+                         w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 2>), grid, dim3(128), lds, s, g, fa, t.kc, cap_mm, w.mm_xy,       \
+                         w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
     break;
     switch (g.NK2) { FE(2) FE(4) FE(6) FE(8) FE(10) FE(12) FE(14) FE(16) default: return hipErrorInvalidValue; }
 #undef FE
