@@ -315,14 +315,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     arow[r] = fr.moff + min(a0 + 4 * lk + r, fr.nm - 1);
     erow[r] = (wave * 16 + 4 * lk + r) * ys;
   }
+  // this lane's column in group gbeg, then 16 columns further per group; the
+  // x phases of the next group are in flight while a group is contracted
+  int colp = gbeg * 16 + li;
+  float2 exn[4];
+  {
+    const int nxp = min(colp, g.NCOL - 1) / g.NY;
+#pragma unroll
+    for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
+  }
   for (int grp = gbeg; grp < gend; grp++) {
-    const int col = grp * 16 + li;
+    const int col = colp;
     const bool cok = col < g.NCOL;
     const int colc = cok ? col : g.NCOL - 1;
     const int nx = colc / g.NY, iy = colc - nx * g.NY;
     float2 ex[4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) ex[r] = tab[(size_t)arow[r] * g.NXY + nx];
+    for (int r = 0; r < 4; r++) ex[r] = exn[r];
+    colp += 16;
+    {
+      const int nxp = min(colp, g.NCOL - 1) / g.NY;
+#pragma unroll
+      for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
+    }
     const double2 w0d = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
     const float w0x = (float)w0d.x, w0y = (float)w0d.y;
     const float* __restrict__ wg = wfrag + ((size_t)f * g.NG + grp) * NK * 256 + lane;
