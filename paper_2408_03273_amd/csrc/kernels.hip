@@ -707,23 +707,39 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
   const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
   const double2* __restrict__ tb = tab + (size_t)fr.moff * g.NXY;
   const double* __restrict__ zb = ztab + (size_t)fr.moff * g.ZKP + li;
-  // K step: atoms a .. a+3, lane atom a + lk (row k of B and column k of A)
-  for (int a = a0 + 4 * wave; a < a1; a += 16) {
+  // K step: atoms a .. a+3, lane atom a + lk (row k of B and column k of A);
+  // the charge and x/y phases of the next K step are in flight during this one
+  double qn;
+  double2 exn[CT], eyn[CT];
+  auto fetch = [&](int a) {
     const int ai = a + lk;
     const bool ok = ai < a1;
     const int ar = ok ? ai : a0;
     // unconditional load of a valid row, then a select: no branch inside the loop
-    const double q = qv[ar] * (ok ? 1.0 : 0.0);
+    qn = qv[ar] * (ok ? 1.0 : 0.0);
     const double2* __restrict__ row = tb + (size_t)ar * g.NXY;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      exn[ct] = row[cx[ct]];
+      eyn[ct] = row[cy[ct]];
+    }
+  };
+  fetch(a0 + 4 * wave);
+  for (int a = a0 + 4 * wave; a < a1; a += 16) {
+    const int ai = a + lk;
+    const bool ok = ai < a1;
+    const int ar = ok ? ai : a0;
+    const double q = qn;
     double bz[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) bz[nt] = zb[(size_t)ar * g.ZKP + nt * 16];
     double2 ex[CT], ey[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
-      ex[ct] = row[cx[ct]];
-      ey[ct] = row[cy[ct]];
+      ex[ct] = exn[ct];
+      ey[ct] = eyn[ct];
     }
+    fetch(a + 16);
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
       const double cr = q * (ex[ct].x * ey[ct].x - ex[ct].y * ey[ct].y);
