@@ -465,18 +465,19 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
-      // second stream: QM phase tables and structure factors (A, B, C, adjoint
-      // weights), then real space, which needs no reciprocal data (prep has
+      // second stream: real space first (it needs no reciprocal data; prep has
       // zeroed rpart: over all pairs the MM-side adjoint terms accumulate there
-      // with atomics); the small kernels run before the big grids of the hot
-      // loops fill the GPU
-      LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm,
-                       pl->cap_mm, tables, 1, PREP_QM_TAB));
-      LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
+      // with atomics), then the QM phase tables and structure factors (A, B, C,
+      // adjoint weights), so that the adjoint hot loop can start as soon as the
+      // MM tables are ready; the small kernels run before the big grids of the
+      // hot loops fill the GPU
       if (q.cells)
         LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
       else
         LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+      LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm,
+                       pl->cap_mm, tables, 1, PREP_QM_TAB));
+      LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
       HIPCHK(hipEventRecord(pl->ev_qside, q.s));
     }
   }
