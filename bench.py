@@ -158,7 +158,8 @@ def main():
                                        executed_frac=round(executed[k] / (per[k]["avg_us"] * 1e-6) / 1e12
                                                            / FP64_PEAK_TFLOPS, 4)) for k in sorted(hot)},
                       flops_per_step=path_flops, kernel_us=round(hot_total_us, 2),
-                      note="the two hot loops run concurrently on two streams; their durations overlap",
+                      note="the two hot loops are launched on two streams; the adjoint's blocks take the GPU as the "
+                           "forward's drain, and each duration includes whatever overlap there was",
                       step_frac_of_fp64_peak=round(path_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
         kernel_source_hash=src_hash, plan=pplan.describe())
 
