@@ -230,9 +230,10 @@ void set_describe(ewald_plan* pl) {
     snprintf(fwd, sizeof(fwd), "mfma-fold ct=%d nt=%d xcd=%d", pl->t.fwd_ct, pl->g.NT, pl->t.fwd_xcd);
   else
     snprintf(fwd, sizeof(fwd), "valu zc=%d nzp=%d", pl->g.Zc, pl->g.NZP);
-  snprintf(buf, sizeof(buf), "fwd=%s blocks~%d bwd=%s kc=%s kgrid=%dx%dx%d precision=%s", fwd, pl->t.fwd_target,
-           bwd[pl->t.bwd_ilp], pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY,
-           pl->g.NZ, precision_name(pl->p.precision));
+  snprintf(buf, sizeof(buf), "fwd=%s blocks~%d bwd=%s%s kc=%s kgrid=%dx%dx%d precision=%s", fwd, pl->t.fwd_target,
+           bwd[pl->t.bwd_ilp], pl->t.bwd_ilp == 6 ? (pl->t.bwd_xcd ? " xcd=1" : " xcd=0") : "",
+           pl->t.kc > 0 ? std::to_string(pl->t.kc).c_str() : "auto", pl->g.NX, pl->g.NY, pl->g.NZ,
+           precision_name(pl->p.precision));
   pl->describe = buf;
 }
 
@@ -549,6 +550,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->t.fwd_mode = mfma_fwd_ok(pl->g) ? 1 : 0;
   pl->t.fwd_ct = mfma_fwd_ct_ok(pl->g, 2) ? 2 : 1;
   pl->t.fwd_xcd = 1;
+  pl->t.bwd_xcd = 1;
   pl->t.fwd_target = pl->t.fwd_mode == 1 ? 1024 : 8192;
   pl->t.bwd_ilp = mfma_bwd_eyl_ok(pl->g) ? 6 : mfma_bwd_ok(pl->g) ? 3 : 2;
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
@@ -570,6 +572,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   }
   if (const char* e = getenv("MPEWALD_SERIAL")) pl->serial = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_FWD_XCD")) pl->t.fwd_xcd = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_BWD_XCD")) pl->t.bwd_xcd = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_FWD_CT")) {
     const int v = atoi(e);
     if (mfma_fwd_ct_ok(pl->g, v)) pl->t.fwd_ct = v;
@@ -1289,8 +1292,10 @@ bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
     const char* p4 = strstr(line, "\"fwd\": ");
     const char* p5 = strstr(line, "\"ct\": ");
     const char* p6 = strstr(line, "\"xcd\": ");
-    int xcd = 0;
+    const char* p7 = strstr(line, "\"bxcd\": ");
+    int xcd = 0, bxcd = 1;
     if (!p6 || sscanf(p6, "\"xcd\": %d", &xcd) != 1) continue;
+    if (p7 && sscanf(p7, "\"bxcd\": %d", &bxcd) != 1) continue;
     if (p1 && p2 && p3 && p4 && p5 && sscanf(p1, "\"fwd_target\": %d", &ft) == 1 &&
         sscanf(p2, "\"bwd\": %d", &bw) == 1 && sscanf(p3, "\"kc\": %d", &kc) == 1 &&
         sscanf(p4, "\"fwd\": %d", &fm) == 1 && sscanf(p5, "\"ct\": %d", &ct) == 1 && ft >= 64 &&
@@ -1302,6 +1307,7 @@ bool tune_lookup(ewald_plan* pl, const std::string& key, const char* path) {
       pl->t.kc = kc;
       pl->t.fwd_mode = fm;
       pl->t.fwd_xcd = xcd ? 1 : 0;
+      pl->t.bwd_xcd = bxcd ? 1 : 0;
       if (fm == 1) pl->t.fwd_ct = ct;
       found = true;
     }
@@ -1444,25 +1450,32 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
       if (bw >= 3 && !mfma_bwd_ok(plan->g)) continue;
       if (bw == 6 && !mfma_bwd_eyl_ok(plan->g)) continue;
       if (saved.fp32r && bw != 6) continue;  // the FP32 variant has only the LDS-y adjoint
-      for (int kc : {0, 1, 2, 4, 8, 16}) {
-        if (kc > plan->cap_kc) continue;
-        plan->t = saved;
-        plan->t.bwd_ilp = bw;
-        plan->t.kc = kc;
-        plan->t.kc = choose_kc(plan, n_mm);
-        const double us = time_it([&]() { return launch_force_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s); });
-        if (us < 0) {
-          st = fail(EWALD_ERR_HIP, "autotune: adjoint launch failed");
-          goto done;
+      for (int kc : {0, 1, 2, 3, 4, 5, 6, 8, 16})
+        for (int bx : {0, 1}) {
+          if (kc > plan->cap_kc || (bx == 1 && bw != 6)) continue;
+          plan->t = saved;
+          plan->t.bwd_ilp = bw;
+          plan->t.bwd_xcd = bx;
+          plan->t.kc = kc;
+          plan->t.kc = choose_kc(plan, n_mm);
+          const double us =
+              time_it([&]() { return launch_force_mm(plan->g, plan->t, q.fa, n_mm, plan->cap_mm, plan->w, s); });
+          if (us < 0) {
+            st = fail(EWALD_ERR_HIP, "autotune: adjoint launch failed");
+            goto done;
+          }
+          if (bw == 6)
+            snprintf(item, sizeof(item), ", \"bwd%d_kc%d_x%d\": %.1f", bw, plan->t.kc, bx, us);
+          else
+            snprintf(item, sizeof(item), ", \"bwd%d_kc%d\": %.1f", bw, plan->t.kc, us);
+          report += item;
+          if (us < best_b) {
+            best_b = us;
+            best.bwd_ilp = bw;
+            best.bwd_xcd = bx;
+            best.kc = kc;
+          }
         }
-        snprintf(item, sizeof(item), ", \"bwd%d_kc%d\": %.1f", bw, plan->t.kc, us);
-        report += item;
-        if (us < best_b) {
-          best_b = us;
-          best.bwd_ilp = bw;
-          best.kc = kc;
-        }
-      }
     }
   }
 done:
@@ -1482,9 +1495,9 @@ done:
     if (fp) {
       fprintf(fp,
               "{\"key\": \"%s\", \"fwd\": %d, \"ct\": %d, \"xcd\": %d, \"fwd_target\": %d, \"bwd\": %d, "
-              "\"kc\": %d, \"times_us\": {%s}}\n",
+              "\"bxcd\": %d, \"kc\": %d, \"times_us\": {%s}}\n",
               key.c_str(), plan->t.fwd_mode, plan->t.fwd_ct, plan->t.fwd_xcd, plan->t.fwd_target, plan->t.bwd_ilp,
-              plan->t.kc, report.c_str());
+              plan->t.bwd_xcd, plan->t.kc, report.c_str());
       fclose(fp);
     }
   }

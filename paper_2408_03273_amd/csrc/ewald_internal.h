@@ -139,16 +139,18 @@ struct Tuning {
   int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
   int fwd_ct;     // matrix-core forward: 16-column tiles per wave
   int fwd_xcd;    // matrix-core forward: XCD-aware block order (single-frame calls)
+  int bwd_xcd;    // LDS-y adjoint: XCD-aware block order (single-frame calls)
   int fp32r;      // both hot loops on the FP32 matrix cores (mixed-precision variant)
 };
 
 // matrix-core kernels are instantiated for mz <= 32
 inline bool mfma_fwd_ok(const Grid& g) { return g.NT >= 1 && g.NT <= 4; }
 inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
-// the y-phase LDS tile must fit in 64 KB: 64 atoms per block, or 32 when 64
-// rows of the y grid do not fit
-inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && 32 * (g.NY + 1) * 16 <= 65536; }
-inline int eyl_waves(const Grid& g) { return 64 * (g.NY + 1) * 16 <= 65536 ? 4 : 2; }
+// the y-phase LDS tile (NY rows of 16 WV + 1 complex entries) must fit in
+// 64 KB: 64 atoms per block, or 32 when the 64-atom tile does not fit
+inline size_t eyl_lds_bytes(const Grid& g, int wv) { return (size_t)(16 * wv + 1) * g.NY * 16; }
+inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && eyl_lds_bytes(g, 2) <= 65536; }
+inline int eyl_waves(const Grid& g) { return eyl_lds_bytes(g, 4) <= 65536 ? 4 : 2; }
 // the forward tiles per wave are limited by the LDS of the block reduction
 inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
 inline int fwd_col_groups(const Grid& g, const Tuning& t) {

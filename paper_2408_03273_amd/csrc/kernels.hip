@@ -1406,34 +1406,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
   }
 }
 
-// Matrix-core adjoint with the y phases of the block's 64 atoms staged in
-// LDS once: the epilogue reads e^{i ky y} for every (atom, column) of every
+// Matrix-core adjoint with the y phases of the block's atoms staged in LDS
+// once: the epilogue reads e^{i ky y} for every (atom, column) of every
 // column group, and from LDS these re-reads no longer compete for L2 with the
 // other blocks (from L2 they spilled to HBM).  The B operand (the folded
 // weights of one frame, ~2 MB at |n| <= 24) is read from L2.  The LDS tile is
-// (16 WV) x (NY + 1) complex entries, dynamic: WV = 4 waves (64 atoms) per
-// block, or 2 (32 atoms) when 64 rows of a large y grid do not fit 64 KB.
+// NY rows of (16 WV + 1) complex entries, ny-major (one pad entry per row
+// spreads the 16 columns a wave reads at once over all banks), dynamic:
+// WV = 4 waves (64 atoms) per block, or 2 (32 atoms) when the 64-atom tile
+// of a large y grid does not fit 64 KB.
+// On gfx950 an FP64 matrix-core instruction and a VALU instruction of the
+// same SIMD do not execute together, so every VALU instruction of the column
+// loop lengthens it.  The loop therefore does no address arithmetic per load:
+// B, w0 and the x phases are buffer loads from a wave-uniform resource with
+// one per-lane offset and uniform (scalar) offsets per K step or atom row;
+// the column (nx, ny) of a lane advances without a division; two column
+// groups are unrolled so the prefetched x phases need no register copies;
+// the nz = 0 weight is added in the epilogue rather than copied into the
+// accumulators; the epilogue is fused multiply-adds.  Buffer loads past the
+// end of their resource return zero, so the atom rows of a partial tile need
+// no clamping (their results are not stored).
+// The grid is one-dimensional per frame, atom-tile major: the kc_n blocks of
+// one atom tile are consecutive logical blocks.  With xcd_remap (single
+// frame) consecutive logical blocks are placed on one XCD, so that the blocks
+// sharing an atom tile read its phase rows through one L2.
+DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+DEV double buf_load_f64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+DEV double2 buf_load_c64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <int NK, int WV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
-    Grid g, FrameArg fa, int kc_n, int cap_mm, const double2* __restrict__ tab, const double* __restrict__ ztab,
-    const double* __restrict__ wfrag, const double2* __restrict__ wk0, double* __restrict__ fpart) {
-  extern __shared__ double2 eysh[];  // [16 WV][NY + 1]
+    Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const double2* __restrict__ tab,
+    const double* __restrict__ ztab, const double* __restrict__ wfrag, const double2* __restrict__ wk0,
+    double* __restrict__ fpart) {
+  extern __shared__ double2 eysh[];  // [NY][16 WV + 1]
   constexpr int NA = 16 * WV;        // atoms per block
+  constexpr int ES = NA + 1;         // LDS row stride in entries
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
-  const int ablk = blockIdx.x * NA;
+  int bid = blockIdx.x;
+  if (xcd_remap) {
+    const int per = (int)gridDim.x / 8;
+    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  }
+  const int tile = bid / kc_n, kc = bid - tile * kc_n;
+  const int ablk = tile * NA;
   if (ablk >= fr.nm) return;  // uniform over the block
-  const int ys = g.NY + 1;
   for (int e = threadIdx.x; e < NA * g.NY; e += 64 * WV) {
     const int a = e / g.NY, c = e - a * g.NY;
-    eysh[a * ys + c] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
+    eysh[c * ES + a] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
   }
   __syncthreads();
   const int a0 = ablk + wave * 16;
   if (a0 >= fr.nm) return;  // no barrier after this point
-  const int kc = blockIdx.y;
   const int per = (g.NG + kc_n - 1) / kc_n;
   const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
   const int li = lane & 15, lk = lane >> 4;
@@ -1445,60 +1478,91 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int st = 0; st < NK; st++) za[st] = zr[4 * st];
   }
   double acc0[4], acc1[4], acc2[4], acc3[4];
-  int arow[4], erow[4];
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
-    acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
-    arow[r] = fr.moff + min(a0 + lk + 4 * r, fr.nm - 1);
-    erow[r] = (wave * 16 + lk + 4 * r) * ys;
-  }
-  // this lane's column in group gbeg, then 16 columns further per group; the
-  // x phases of the next group are in flight while a group is contracted
-  int colp = gbeg * 16 + li;
-  double2 exn[4];
+  for (int r = 0; r < 4; r++) acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.0;
+  // x phases of this frame's atoms (the launcher keeps one frame's table
+  // below 2 GB): row a0 + lk at byte xoff, rows 4 apart at a uniform stride
+  const __amdgpu_buffer_rsrc_t xr = buf_rsrc(tab + (size_t)fr.moff * g.NXY, (unsigned)fr.nm * g.NXY * 16u);
+  const int xoff = (a0 + lk) * g.NXY * 16;
+  const int xrow = 4 * g.NXY * 16;
+  const int erow = wave * 16 + lk;  // LDS entry of row r = 0; rows r are 4 entries apart
+  const int q16 = 16 / g.NY, r16 = 16 - q16 * g.NY;
+  auto load_ex = [&](int nx, double2 (&ex)[4]) {
+    const int vo = xoff + min(nx, g.NX - 1) * 16;
+#pragma unroll
+    for (int r = 0; r < 4; r++) ex[r] = buf_load_c64(xr, vo, r * xrow);
+  };
+  const double2* __restrict__ w0f = wk0 + (size_t)f * g.NG * 16;
+  const double* __restrict__ wff = wfrag + (size_t)f * g.NG * NK * 256;
+  // B operand ring: the fragments of K step st + BD are in flight while step
+  // st is contracted, across the end of a group into the next one (BD divides
+  // NK, so a K step has the same ring slot in every group)
+  constexpr int BD = NK % 3 == 0 ? 3 : (NK % 4 == 0 && NK <= 4) ? 4 : 2;
+  static_assert(NK % BD == 0, "ring depth must divide the K steps");
+  double bq[BD][4];
+  auto wrsrc = [&](int grp) { return buf_rsrc(wff + (size_t)grp * NK * 256, NK * 256 * 8); };
+  auto load_b = [&](__amdgpu_buffer_rsrc_t wr, int st, double (&b)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = buf_load_f64(wr, lane * 8, st * 2048 + k * 512);
+  };
+  int col = gbeg * 16 + li;
+  int nx = col / g.NY, iy = col - nx * g.NY;
   {
-    const int nxp = min(colp, g.NCOL - 1) / g.NY;
+    const __amdgpu_buffer_rsrc_t w = wrsrc(min(gbeg, g.NG - 1));  // an empty chunk loads and discards
 #pragma unroll
-    for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
+    for (int st = 0; st < BD; st++) load_b(w, st, bq[st]);
   }
   for (int grp = gbeg; grp < gend; grp++) {
-    const int col = colp;
-    const bool cok = col < g.NCOL;
-    const int colc = cok ? col : g.NCOL - 1;
-    const int nx = colc / g.NY, iy = colc - nx * g.NY;
+    // the x phases of this group arrive while it is contracted
     double2 ex[4];
-#pragma unroll
-    for (int r = 0; r < 4; r++) ex[r] = exn[r];
-    colp += 16;
-    {
-      const int nxp = min(colp, g.NCOL - 1) / g.NY;
-#pragma unroll
-      for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
-    }
-    const double2 w0 = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
-    const double* __restrict__ wg = wfrag + ((size_t)f * g.NG + grp) * NK * 256 + lane;
-    v4d Pr = v4d{w0.x, w0.x, w0.x, w0.x}, Pi = v4d{w0.y, w0.y, w0.y, w0.y};
-    v4d Zr = v4d{0.0, 0.0, 0.0, 0.0}, Zi = v4d{0.0, 0.0, 0.0, 0.0};
+    load_ex(nx, ex);
+    // the next group this wave contracts (the last one repeats itself)
+    const __amdgpu_buffer_rsrc_t wn = wrsrc(min(grp + 1, gend - 1));
+    const __amdgpu_buffer_rsrc_t wr = wrsrc(grp);
+    const double2 w0 = w0f[grp * 16 + li];
+    v4d Pr = v4d{0.0, 0.0, 0.0, 0.0}, Pi = Pr, Zr = Pr, Zi = Pr;
+    // the order is fixed as written (the compiler would otherwise trade the
+    // loads in flight for registers): per K step four independent
+    // matrix-core chains, then the loads of step st + BD into the freed slot
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int st = 0; st < NK; st++) {
-      const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
-      Pr = mfma4(za[st], b0, Pr);
-      Pi = mfma4(za[st], b1, Pi);
-      Zr = mfma4(za[st], b2, Zr);
-      Zi = mfma4(za[st], b3, Zi);
+      double (&b)[4] = bq[st % BD];
+      Pr = mfma4(za[st], b[0], Pr);
+      Pi = mfma4(za[st], b[1], Pi);
+      Zr = mfma4(za[st], b[2], Zr);
+      Zi = mfma4(za[st], b[3], Zi);
+      if (st + BD < NK)
+        load_b(wr, st + BD, b);
+      else
+        load_b(wn, st + BD - NK, b);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (cok) {
-      const double fnx = (double)nx, fny = (double)(iy - g.my);
+    // columns past NCOL (in the last group) have zero weights: their terms
+    // vanish without a branch
+    const double fnx = (double)nx, fny = (double)(iy - g.my);
+    const double2* __restrict__ ey = eysh + iy * ES + erow;
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
-        const double2 c = cconj(cmul(ex[r], eysh[erow[r] + iy]));
-        const double cpi = c.x * Pi[r] + c.y * Pr[r];
-        acc0[r] += c.x * Pr[r] - c.y * Pi[r];
-        acc1[r] += fnx * cpi;
-        acc2[r] += fny * cpi;
-        acc3[r] += c.x * Zi[r] + c.y * Zr[r];
-      }
+    for (int r = 0; r < 4; r++) {
+      // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y}) = cr - i s
+      const double2 e = ey[4 * r];
+      const double pr = Pr[r] + w0.x, pi = Pi[r] + w0.y;
+      const double cr = fma(ex[r].x, e.x, -ex[r].y * e.y);
+      const double s = fma(ex[r].x, e.y, ex[r].y * e.x);
+      const double cpi = fma(cr, pi, -s * pr);
+      acc0[r] = fma(cr, pr, acc0[r]);
+      acc0[r] = fma(s, pi, acc0[r]);
+      acc1[r] = fma(fnx, cpi, acc1[r]);
+      acc2[r] = fma(fny, cpi, acc2[r]);
+      acc3[r] = fma(cr, Zi[r], acc3[r]);
+      acc3[r] = fma(-s, Zr[r], acc3[r]);
+    }
+    // next column of this lane: 16 further, (nx, iy) without a division
+    iy += r16;
+    nx += q16;
+    if (iy >= g.NY) {
+      iy -= g.NY;
+      nx++;
     }
   }
   // sum over the 16 columns held by lanes with the same lk
@@ -1656,17 +1720,20 @@ hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, i
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
   if (t.fp32r) return launch_force_mm32(g, t, fa, max_nm, cap_mm, w, s);
-  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 (or 32) atoms per block
+  // y phases in LDS: 64 (or 32) atoms per block; its buffer loads address one
+  // frame's x/y table with 32-bit offsets
+  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g) && (size_t)max_nm * g.NXY * 16 < (size_t(1) << 31)) {
     const int wv = eyl_waves(g);
-    dim3 grid((max_nm + 16 * wv - 1) / (16 * wv), t.kc, fa.n_frames);
-    const size_t lds = (size_t)16 * wv * (g.NY + 1) * sizeof(double2);
+    dim3 grid(((max_nm + 16 * wv - 1) / (16 * wv)) * t.kc, 1, fa.n_frames);
+    const size_t lds = eyl_lds_bytes(g, wv);
+    const int xcd = (t.bwd_xcd && fa.n_frames == 1) ? 1 : 0;
 #define FE(N)                                                                                                  \
   case N:                                                                                                      \
     if (wv == 4)                                                                                               \
-      hipLaunchKernelGGL((k_force_mm_eyl<N, 4>), grid, dim3(256), lds, s, g, fa, t.kc, cap_mm, w.mm_xy,       \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 4>), grid, dim3(256), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy,  \
                          w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_force_mm_eyl<N, 2>), grid, dim3(128), lds, s, g, fa, t.kc, cap_mm, w.mm_xy,       \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 2>), grid, dim3(128), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy,  \
                          w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
     break;
     switch (g.NK2) { FE(2) FE(4) FE(6) FE(8) FE(10) FE(12) FE(14) FE(16) default: return hipErrorInvalidValue; }

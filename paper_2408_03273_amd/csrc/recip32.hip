@@ -276,17 +276,25 @@ hipError_t launch_sfac_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, 
 // wave (all K steps in registers), B = folded weights (Re P, Im P, Re Pz,
 // Im Pz) from L2, the block's 64 rows of y phases staged in LDS; the
 // epilogue multiplies by conj(e^{i kx x} e^{i ky y}) and sums over its
-// columns; per-atom results leave in FP64.
+// columns; per-atom results leave in FP64.  Block order as the FP64 kernel:
+// atom-tile major, optionally with the blocks of one tile on one XCD.
 template <int NK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl32(
-    Grid g, FrameArg fa, int kc_n, int cap_mm, const float2* __restrict__ tab, const float* __restrict__ ztab,
-    const float* __restrict__ wfrag, const double2* __restrict__ wk0, double* __restrict__ fpart) {
+    Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const float2* __restrict__ tab,
+    const float* __restrict__ ztab, const float* __restrict__ wfrag, const double2* __restrict__ wk0,
+    double* __restrict__ fpart) {
   extern __shared__ float2 eysh32[];  // [64][NY + 1]
   const int f = blockIdx.z;
   const FrameDev fr = frame32(fa, f);
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int32(threadIdx.x >> 6);
-  const int ablk = blockIdx.x * 64;
+  int bid = blockIdx.x;
+  if (xcd_remap) {
+    const int per = (int)gridDim.x / 8;
+    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  }
+  const int tile = bid / kc_n, kc = bid - tile * kc_n;
+  const int ablk = tile * 64;
   if (ablk >= fr.nm) return;  // uniform over the block
   const int ys = g.NY + 1;
   for (int e = threadIdx.x; e < 64 * g.NY; e += 256) {
@@ -296,7 +304,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __syncthreads();
   const int a0 = ablk + wave * 16;
   if (a0 >= fr.nm) return;  // no barrier after this point
-  const int kc = blockIdx.y;
   const int per = (g.NG + kc_n - 1) / kc_n;
   const int gbeg = kc * per, gend = min(g.NG, gbeg + per);
   const int li = lane & 15, lk = lane >> 4;
@@ -398,11 +405,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 hipError_t launch_force_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                              hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
-  dim3 grid((max_nm + 63) / 64, t.kc, fa.n_frames);
+  dim3 grid(((max_nm + 63) / 64) * t.kc, 1, fa.n_frames);
   const size_t lds = (size_t)64 * (g.NY + 1) * sizeof(float2);
+  const int xcd = (t.bwd_xcd && fa.n_frames == 1) ? 1 : 0;
 #define FE(N)                                                                                                      \
   case N:                                                                                                          \
-    hipLaunchKernelGGL((k_force_mm_eyl32<N>), grid, dim3(256), lds, s, g, fa, t.kc, cap_mm, w.mm_xy32,            \
+    hipLaunchKernelGGL((k_force_mm_eyl32<N>), grid, dim3(256), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy32,       \
                        w.mm_ztab32, w.wfrag32, w.wk0, w.fpart);                                                    \
     break;
   switch (g.NK2) { FE(2) FE(4) FE(6) FE(8) FE(10) FE(12) FE(14) FE(16) default: return hipErrorInvalidValue; }
