@@ -57,7 +57,9 @@ typedef enum {
   EWALD_OK = 0,
   EWALD_ERR_ARG = -1,      /* null pointer, bad size or bad parameter */
   EWALD_ERR_CUTOFF = -2,   /* rcut needs more than 3 lattice images per direction */
-  EWALD_ERR_CAPACITY = -3, /* more atoms/frames than the plan was set up for */
+  EWALD_ERR_CAPACITY = -3, /* more atoms/frames than the plan was set up for, or a frame of more MM
+                               charges than the matrix-core kernels address: 2^31 / (16 (kmax[0] + 2 kmax[1]
+                               + 2)), 1.8 million at kmax 24 */
   EWALD_ERR_HIP = -4,      /* a HIP runtime call failed */
   EWALD_ERR_OOM = -5       /* workspace allocation failed */
 } ewald_status_t;

@@ -316,6 +316,16 @@ int choose_kc(const ewald_plan* pl, long total_nm) {
   return (int)kc;
 }
 
+// The matrix-core hot loops address one frame's x/y phase table with 32-bit
+// buffer offsets: a frame may hold fewer than 2^31 / (16 (NX + NY)) MM charges
+// (1.8 million at |n| <= 24).
+ewald_status_t check_frame_mm(const ewald_plan* pl, long n_mm) {
+  if (!tab32_ok(pl->g, n_mm))
+    return fail(EWALD_ERR_CAPACITY, "a frame of %ld MM charges exceeds the %ld the kernels address at this k grid",
+                n_mm, (long)(((size_t(1) << 31) - 1) / ((size_t)pl->g.NXY * 16)));
+  return EWALD_OK;
+}
+
 // Caller-owned context of one forward call:
 //   S_MM(k) | MM potential data at the QM sites (10 per site) |
 //   gradients of E for unit upstream gradient: QM (3+1+3+6 per site), MM (3+1 per atom)
@@ -557,7 +567,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   // atoms per lane) or 3|4 (matrix cores, 16|32 atoms per wave); MPEWALD_FWD =
   // 0|1 (VALU | matrix cores); MPEWALD_FWD_CT = 1|2|4 (matrix-core column
   // tiles per wave); MPEWALD_FWD_PF = 0|1 (VALU prefetch); MPEWALD_FWD_TARGET =
-  // forward block count target
+  // forward block count target; MPEWALD_FWD_XCD, MPEWALD_BWD_XCD = 0|1
+  // (XCD-aware block order); MPEWALD_KC = adjoint column chunks (0: automatic)
   if (const char* e = getenv("MPEWALD_BWD")) {
     const int v = atoi(e);
     if ((v >= 1 && v <= 2) || (v >= 3 && v <= 5 && mfma_bwd_ok(pl->g)) || (v == 6 && mfma_bwd_eyl_ok(pl->g)))
@@ -573,6 +584,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   if (const char* e = getenv("MPEWALD_SERIAL")) pl->serial = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_FWD_XCD")) pl->t.fwd_xcd = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_BWD_XCD")) pl->t.bwd_xcd = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_KC")) pl->t.kc = std::max(0, atoi(e));
   if (const char* e = getenv("MPEWALD_FWD_CT")) {
     const int v = atoi(e);
     if (mfma_fwd_ct_ok(pl->g, v)) pl->t.fwd_ct = v;
@@ -709,6 +721,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   if (!energy) return fail(EWALD_ERR_ARG, "null energy output");
   if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
     return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  if (check_frame_mm(plan, n_mm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   Seq q;
   q.pl = plan;
@@ -777,6 +790,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   if (n_mm > 0 && !g_mm_xyz) return fail(EWALD_ERR_ARG, "null MM gradient output");
   if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
     return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  if (check_frame_mm(plan, n_mm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   Seq q;
   q.pl = plan;
@@ -918,6 +932,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   if (end_q > plan->cap_qm || end_m > plan->cap_mm)
     return fail(EWALD_ERR_CAPACITY, "packed rows (%ld QM, %ld MM) exceed capacity %d/%d", end_q, end_m, plan->cap_qm,
                 plan->cap_mm);
+  if (check_frame_mm(plan, max_nm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   ewald_status_t st = check_arrays((int)total_nq, (int)total_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q);
   if (st != EWALD_OK) return st;
   if (mode == EWALD_FWD_BWD && ((total_nq > 0 && (!g_qm_xyz || !g_Q || !g_mu || !g_theta)) || (total_nm > 0 && !g_mm_xyz)))
@@ -1061,6 +1076,7 @@ extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx
   if (st != EWALD_OK) return st;
   if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
     return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  if (check_frame_mm(plan, n_mm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   // QM-side kernels only: a frame without MM atoms makes S_MM and every QM-MM
   // sum vanish, leaving the QM-QM image terms of the new moments
@@ -1115,6 +1131,7 @@ static ewald_status_t region_args(ewald_plan* plan, int n_qm, const double* qm_x
   if (st != EWALD_OK) return st;
   if (n_qm > plan->cap_qm || n_mm > plan->cap_mm)
     return fail(EWALD_ERR_CAPACITY, "n_qm=%d n_mm=%d exceed capacity %d/%d", n_qm, n_mm, plan->cap_qm, plan->cap_mm);
+  if (check_frame_mm(plan, n_mm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   if (!std::isfinite(r_region) || !std::isfinite(r_gauss) || r_region < 0.0 || r_gauss < 0.0)
     return fail(EWALD_ERR_ARG, "r_region=%g r_gauss=%g must be finite and >= 0", r_region, r_gauss);
   const double lmin = std::min(plan->p.box[0], std::min(plan->p.box[1], plan->p.box[2]));
@@ -1322,13 +1339,16 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
   g_last_error.clear();
   if (!plan) return fail(EWALD_ERR_ARG, "null plan");
   if (n_mm < 1 || n_mm > plan->cap_mm) return fail(EWALD_ERR_CAPACITY, "n_mm=%d outside 1..%d", n_mm, plan->cap_mm);
+  if (check_frame_mm(plan, n_mm) != EWALD_OK) return EWALD_ERR_CAPACITY;
   const std::string key = tune_key(plan, n_mm);
   if (tune_lookup(plan, key, cache_path)) {
     set_describe(plan);
     return EWALD_OK;
   }
-  // synthetic frame: uniform MM charges (neutral) and a few QM multipoles near the centre
-  const int nq = std::min(8, plan->cap_qm);
+  // synthetic frame: uniform MM charges (neutral) and QM multipoles near the
+  // centre, as many as the plan holds (up to 64: the QM-side kernels share the
+  // GPU with the hot loops in the fused step)
+  const int nq = std::min(64, plan->cap_qm);
   std::vector<double> hm(3 * (size_t)n_mm), hq(n_mm), hqp(3 * (size_t)nq), hQ(nq), hmu(3 * (size_t)nq),
       hth(6 * (size_t)nq);
   unsigned long long st64 = 0x9E3779B97F4A7C15ull;
@@ -1350,6 +1370,9 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
     for (int a = 0; a < 6; a++) hth[6 * j + a] = 0.1 * (rnd() - 0.5);
   }
   double *dm = nullptr, *dq = nullptr, *dqp = nullptr, *dQ = nullptr, *dmu = nullptr, *dth = nullptr;
+  double *d_out = nullptr;  // energy, phi, efield, efgrad of the in-context steps
+  void* d_ctx = nullptr;
+  std::vector<std::pair<double, Tuning>> fres, bres;  // standalone times of the candidates
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ewald_status_t st = EWALD_OK;
@@ -1438,6 +1461,7 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
       else
         snprintf(item, sizeof(item), "%s\"fwd_valu_%d\": %.1f", report.empty() ? "" : ", ", c.ft, us);
       report += item;
+      fres.push_back({us, plan->t});
       if (us < best_f) {
         best_f = us;
         best.fwd_mode = c.mode;
@@ -1469,6 +1493,7 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
           else
             snprintf(item, sizeof(item), ", \"bwd%d_kc%d\": %.1f", bw, plan->t.kc, us);
           report += item;
+          bres.push_back({us, plan->t});
           if (us < best_b) {
             best_b = us;
             best.bwd_ilp = bw;
@@ -1477,14 +1502,81 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
           }
         }
     }
+    // In-context pick.  Inside the fused step the adjoint's blocks start while
+    // the forward's drain, beside the QM-side kernels, and the standalone times
+    // of close candidates do not rank their step times (a forward grid of one
+    // full round can finish sooner but leave the adjoint a worse start): the
+    // standalone finalists (within 3% of the best; the best block order of up
+    // to three forward tilings and four adjoint chunkings) are timed as whole
+    // forward+adjoint steps.
+    {
+      auto finalists = [](std::vector<std::pair<double, Tuning>> v, double b, size_t n, auto key) {
+        std::stable_sort(v.begin(), v.end(),
+                         [](const std::pair<double, Tuning>& x, const std::pair<double, Tuning>& y) {
+                           return x.first < y.first;
+                         });
+        std::vector<Tuning> out;
+        for (const auto& e : v) {
+          if (e.first > 1.03 * b || out.size() >= n) break;
+          bool seen = false;
+          for (const Tuning& o : out) seen = seen || key(o) == key(e.second);
+          if (!seen) out.push_back(e.second);
+        }
+        return out;
+      };
+      const std::vector<Tuning> ff = finalists(fres, best_f, 3, [](const Tuning& t) {
+        return (long)t.fwd_mode * 1000000L + (long)t.fwd_ct * 100000L + t.fwd_target;
+      });
+      const std::vector<Tuning> bf =
+          finalists(bres, best_b, 4, [](const Tuning& t) { return (long)t.bwd_ilp * 1000L + t.kc; });
+      if (ff.size() * bf.size() > 1) {
+        TCHK(hipMalloc(&d_out, sizeof(double) * (1 + 10 * (size_t)std::max(nq, 1))));
+        TCHK(hipMalloc(&d_ctx, std::max<size_t>(ctx_bytes(plan->g, nq, n_mm), 256)));
+        double best_s = 1e30;
+        Tuning pick = best;
+        for (const Tuning& a : ff)
+          for (const Tuning& b : bf) {
+            plan->t = best;
+            plan->t.fwd_mode = a.fwd_mode;
+            plan->t.fwd_ct = a.fwd_ct;
+            plan->t.fwd_target = a.fwd_target;
+            plan->t.fwd_xcd = a.fwd_xcd;
+            plan->t.a_chunk = 0;
+            plan->t.bwd_ilp = b.bwd_ilp;
+            plan->t.bwd_xcd = b.bwd_xcd;
+            plan->t.kc = b.kc;
+            const Tuning cand = plan->t;
+            const double us = time_it([&]() {
+              const ewald_status_t r =
+                  ewald_forward(plan, nq, dqp, dQ, dmu, dth, n_mm, dm, dq, d_out, d_out + 1, d_out + 1 + nq,
+                                d_out + 1 + 4 * (size_t)nq, d_ctx, (void*)s);
+              return r == EWALD_OK ? hipSuccess : hipErrorLaunchFailure;
+            });
+            plan->t = cand;
+            if (us < 0) {
+              st = fail(EWALD_ERR_HIP, "autotune: step failed: %s", g_last_error.c_str());
+              goto done;
+            }
+            snprintf(item, sizeof(item), ", \"step_ct%d_%d_x%d_bwd%d_kc%d_x%d\": %.1f", cand.fwd_ct, cand.fwd_target,
+                     cand.fwd_xcd, cand.bwd_ilp, cand.kc, cand.bwd_xcd, us);
+            report += item;
+            if (us < best_s) {
+              best_s = us;
+              pick = cand;
+            }
+          }
+        best = pick;
+      }
+    }
   }
 done:
 #undef TCHK
   plan->t = st == EWALD_OK ? best : saved;
   plan->t.a_chunk = 0;
   if (s) (void)hipStreamSynchronize(s);
-  for (double* p : {dm, dq, dqp, dQ, dmu, dth})
+  for (double* p : {dm, dq, dqp, dQ, dmu, dth, d_out})
     if (p) (void)hipFree(p);
+  if (d_ctx) (void)hipFree(d_ctx);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (s) (void)hipStreamDestroy(s);

@@ -151,6 +151,9 @@ inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
 inline size_t eyl_lds_bytes(const Grid& g, int wv) { return (size_t)(16 * wv + 1) * g.NY * 16; }
 inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && eyl_lds_bytes(g, 2) <= 65536; }
 inline int eyl_waves(const Grid& g) { return eyl_lds_bytes(g, 4) <= 65536 ? 4 : 2; }
+// the matrix-core hot loops address one frame's x/y phase table with 32-bit
+// buffer offsets
+inline bool tab32_ok(const Grid& g, long nm) { return (size_t)nm * g.NXY * 16 < (size_t(1) << 31); }
 // the forward tiles per wave are limited by the LDS of the block reduction
 inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
 inline int fwd_col_groups(const Grid& g, const Tuning& t) {

@@ -471,6 +471,19 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 DEV v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
+// Raw buffer loads: a resource holds a wave-uniform base and a byte count
+// (loads past it return zero without touching memory); the offset is a
+// per-lane byte offset plus a uniform (scalar) byte offset.
+DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+DEV double buf_load_f64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+DEV double2 buf_load_c64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 // ------------------------------------------------------------------ MM structure factor (forward hot loop)
 // S_MM(k) = sum_i q_i e^{i k.R_i}.  Each lane owns one column (nx,ny) and Z
 // consecutive nz values; for every atom it forms c = q e^{i(kx x + ky y)}
@@ -631,7 +644,10 @@ static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const Fram
 hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                           hipStream_t s) {
   if (t.fp32r) return launch_sfac_mm32(g, t, fa, max_nm, cap_mm, w, s);
-  if (t.fwd_mode == 1) return launch_sfac_mm_mfma(g, t, fa, max_nm, cap_mm, w, s);
+  if (t.fwd_mode == 1) {
+    if (!tab32_ok(g, max_nm)) return hipErrorInvalidValue;  // the API rejects such frames first
+    return launch_sfac_mm_mfma(g, t, fa, max_nm, cap_mm, w, s);
+  }
   switch (g.Zc) {
     case 7: return launch_sfac_mm_z<7>(g, t, fa, max_nm, cap_mm, w, s);
     case 8: return launch_sfac_mm_z<8>(g, t, fa, max_nm, cap_mm, w, s);
@@ -704,55 +720,72 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
       di[ct][nt] = v4d{0.0, 0.0, 0.0, 0.0};
     }
   }
-  const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
-  const double2* __restrict__ tb = tab + (size_t)fr.moff * g.NXY;
-  const double* __restrict__ zb = ztab + (size_t)fr.moff * g.ZKP + li;
-  // K step: atoms a .. a+3, lane atom a + lk (row k of B and column k of A);
-  // the charge and x/y phases of the next K step are in flight during this one
-  double qn;
-  double2 exn[CT], eyn[CT];
-  auto fetch = [&](int a) {
-    const int ai = a + lk;
-    const bool ok = ai < a1;
-    const int ar = ok ? ai : a0;
-    // unconditional load of a valid row, then a select: no branch inside the loop
-    qn = qv[ar] * (ok ? 1.0 : 0.0);
-    const double2* __restrict__ row = tb + (size_t)ar * g.NXY;
+  // Operands are buffer loads from resources that end at the chunk's last
+  // atom (rows past it read as zero, so a partial K step needs no clamp or
+  // select), with one offset per lane and a uniform offset per K step.  The
+  // loads of step i + 1 are issued before step i is contracted; two steps are
+  // unrolled so that the prefetched operands need no register copies, and the
+  // order is fixed with scheduling barriers (the compiler would otherwise
+  // move the loads next to their use).  Lane: column li of each tile, atom
+  // a + lk of the step (row k of B and column k of A).
+  const int arow = a0 + 4 * wave + lk;
+  const __amdgpu_buffer_rsrc_t qr = buf_rsrc(mm4 + (size_t)3 * cap_mm + fr.moff, (unsigned)a1 * 8u);
+  const __amdgpu_buffer_rsrc_t tr = buf_rsrc(tab + (size_t)fr.moff * g.NXY, (unsigned)a1 * g.NXY * 16u);
+  const __amdgpu_buffer_rsrc_t zr = buf_rsrc(ztab + (size_t)fr.moff * g.ZKP, (unsigned)a1 * g.ZKP * 8u);
+  const int qo = arow * 8, zo = (arow * g.ZKP + li) * 8;
+  int xo[CT], yo[CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ct++) {
-      exn[ct] = row[cx[ct]];
-      eyn[ct] = row[cy[ct]];
-    }
-  };
-  fetch(a0 + 4 * wave);
-  for (int a = a0 + 4 * wave; a < a1; a += 16) {
-    const int ai = a + lk;
-    const bool ok = ai < a1;
-    const int ar = ok ? ai : a0;
-    const double q = qn;
-    double bz[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; nt++) bz[nt] = zb[(size_t)ar * g.ZKP + nt * 16];
+  for (int ct = 0; ct < CT; ct++) {
+    xo[ct] = (arow * g.NXY + cx[ct]) * 16;
+    yo[ct] = (arow * g.NXY + cy[ct]) * 16;
+  }
+  const int ts = 16 * g.NXY * 16, zs = 16 * g.ZKP * 8;  // bytes per K step (16 atoms)
+  const int nst = a0 + 4 * wave < a1 ? (a1 - a0 - 4 * wave + 15) / 16 : 0;
+  struct Ops {
+    double q;
     double2 ex[CT], ey[CT];
+    double bz[NT];
+  };
+  auto fetch = [&](int i, Ops& o) {
+    o.q = buf_load_f64(qr, qo, i * 128);
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
-      ex[ct] = exn[ct];
-      ey[ct] = eyn[ct];
+      o.ex[ct] = buf_load_c64(tr, xo[ct], i * ts);
+      o.ey[ct] = buf_load_c64(tr, yo[ct], i * ts);
     }
-    fetch(a + 16);
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) o.bz[nt] = buf_load_f64(zr, zo + nt * 128, i * zs);
+  };
+  auto step = [&](const Ops& o) {
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
-      const double cr = q * (ex[ct].x * ey[ct].x - ex[ct].y * ey[ct].y);
-      const double ci = q * (ex[ct].x * ey[ct].y + ex[ct].y * ey[ct].x);
+      const double pr = fma(o.ex[ct].x, o.ey[ct].x, -o.ex[ct].y * o.ey[ct].y);
+      const double pi = fma(o.ex[ct].x, o.ey[ct].y, o.ex[ct].y * o.ey[ct].x);
+      const double cr = o.q * pr, ci = o.q * pi;
       s0r[ct] += cr;
       s0i[ct] += ci;
 #pragma unroll
       for (int nt = 0; nt < NT; nt++) {
-        dr[ct][nt] = mfma4(cr, bz[nt], dr[ct][nt]);
-        di[ct][nt] = mfma4(ci, bz[nt], di[ct][nt]);
+        dr[ct][nt] = mfma4(cr, o.bz[nt], dr[ct][nt]);
+        di[ct][nt] = mfma4(ci, o.bz[nt], di[ct][nt]);
       }
     }
+  };
+  // (a fetch past the last step reads rows past the chunk: zeros)
+  Ops A, B;
+  fetch(0, A);
+  int i = 0;
+  for (; i + 1 < nst; i += 2) {
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(i + 1, B);
+    __builtin_amdgcn_sched_barrier(0);
+    step(A);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(i + 2, A);
+    __builtin_amdgcn_sched_barrier(0);
+    step(B);
   }
+  if (i < nst) step(A);
   // nz = 0: sum over the four atom rows of the wave, then over the waves
 #pragma unroll
   for (int ct = 0; ct < CT; ct++) {
@@ -1430,15 +1463,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
 // one atom tile are consecutive logical blocks.  With xcd_remap (single
 // frame) consecutive logical blocks are placed on one XCD, so that the blocks
 // sharing an atom tile read its phase rows through one L2.
-DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-DEV double buf_load_f64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-DEV double2 buf_load_c64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-}
 
 template <int NK, int WV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
@@ -1720,9 +1744,8 @@ hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, i
                            hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
   if (t.fp32r) return launch_force_mm32(g, t, fa, max_nm, cap_mm, w, s);
-  // y phases in LDS: 64 (or 32) atoms per block; its buffer loads address one
-  // frame's x/y table with 32-bit offsets
-  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g) && (size_t)max_nm * g.NXY * 16 < (size_t(1) << 31)) {
+  if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 (or 32) atoms per block
+    if (!tab32_ok(g, max_nm)) return hipErrorInvalidValue;  // the API rejects such frames first
     const int wv = eyl_waves(g);
     dim3 grid(((max_nm + 16 * wv - 1) / (16 * wv)) * t.kc, 1, fa.n_frames);
     const size_t lds = eyl_lds_bytes(g, wv);
