@@ -49,6 +49,24 @@ DEV FrameDev frame32(const FrameArg& fa, int f) {
   return r;
 }
 
+// Raw buffer loads: a resource holds a wave-uniform base and a byte count
+// (loads past it return zero without touching memory); offsets are a per-lane
+// byte offset plus a uniform (scalar) byte offset.
+DEV __amdgpu_buffer_rsrc_t buf_rsrc32(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+DEV float2 buf_load_f2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+DEV float4 buf_load_f4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+DEV float buf_load_f1(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+DEV double buf_load_d1(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
 // ------------------------------------------------------------------ FP32 copies of the operands
 // MM rows of the compact x/y table and of the real z table (padding included).
 __global__ __launch_bounds__(256) void k_tab32(Grid g, FrameArg fa, int cap_mm, const double2* __restrict__ xy,
@@ -78,9 +96,17 @@ hipError_t launch_tab32(const Grid& g, const FrameArg& fa, int max_nm, int cap_m
   return hipGetLastError();
 }
 
-// folded adjoint weights of every frame (padding entries are zero in both)
+// folded adjoint weights of every frame (padding entries are zero in both).
+// A 256-entry K step holds the four B fragments (Re P, Im P, Re Pz, Im Pz) of
+// 64 lanes; the FP64 layout is fragment-major (entry 64 k + lane), the FP32
+// copy lane-major (entry 4 lane + k), so that a lane reads its four values of
+// a K step as one 16-byte load.
 __global__ __launch_bounds__(256) void k_wfrag32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = (float)src[i];
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const size_t blk = i >> 8;
+    const int rem = (int)(i & 255), k = rem >> 6, lane = rem & 63;
+    dst[(blk << 8) + 4 * lane + k] = (float)src[i];
+  }
 }
 
 hipError_t launch_wfrag32(const Grid& g, const FrameArg& fa, Work& w, hipStream_t s) {
@@ -140,37 +166,69 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma32(Grid g, FrameArg fa, int
       di[ct][nt] = v4f{0.f, 0.f, 0.f, 0.f};
     }
   }
-  const double* __restrict__ qv = mm4 + (size_t)3 * cap_mm + fr.moff;
-  const float2* __restrict__ tb = tab + (size_t)fr.moff * g.NXY;
-  const float* __restrict__ zb = ztab + (size_t)fr.moff * g.ZKP + li;
-  for (int a = a0 + 4 * wave; a < a1; a += 16) {
-    const int ai = a + lk;
-    const bool ok = ai < a1;
-    const int ar = ok ? ai : a0;
-    const float q = (float)qv[ar] * (ok ? 1.f : 0.f);
-    const float2* __restrict__ row = tb + (size_t)ar * g.NXY;
-    float bz[NT];
+  // operands as in the FP64 kernel: buffer loads from resources that end at
+  // the chunk's last atom, one offset per lane and a scalar offset per K step,
+  // the next step's loads issued before the current one is contracted (two
+  // steps unrolled, order pinned with scheduling barriers)
+  const int arow = a0 + 4 * wave + lk;
+  const __amdgpu_buffer_rsrc_t qr = buf_rsrc32(mm4 + (size_t)3 * cap_mm + fr.moff, (unsigned)a1 * 8u);
+  const __amdgpu_buffer_rsrc_t tr = buf_rsrc32(tab + (size_t)fr.moff * g.NXY, (unsigned)a1 * g.NXY * 8u);
+  const __amdgpu_buffer_rsrc_t zr = buf_rsrc32(ztab + (size_t)fr.moff * g.ZKP, (unsigned)a1 * g.ZKP * 4u);
+  const int qo = arow * 8, zo = (arow * g.ZKP + li) * 4;
+  int xo[CT], yo[CT];
 #pragma unroll
-    for (int nt = 0; nt < NT; nt++) bz[nt] = zb[(size_t)ar * g.ZKP + nt * 16];
+  for (int ct = 0; ct < CT; ct++) {
+    xo[ct] = (arow * g.NXY + cx[ct]) * 8;
+    yo[ct] = (arow * g.NXY + cy[ct]) * 8;
+  }
+  const int ts = 16 * g.NXY * 8, zs = 16 * g.ZKP * 4;  // bytes per K step (16 atoms)
+  const int nst = a0 + 4 * wave < a1 ? (a1 - a0 - 4 * wave + 15) / 16 : 0;
+  struct Ops {
+    double q;
     float2 ex[CT], ey[CT];
+    float bz[NT];
+  };
+  auto fetch = [&](int i, Ops& o) {
+    o.q = buf_load_d1(qr, qo, i * 128);
 #pragma unroll
     for (int ct = 0; ct < CT; ct++) {
-      ex[ct] = row[cx[ct]];
-      ey[ct] = row[cy[ct]];
+      o.ex[ct] = buf_load_f2(tr, xo[ct], i * ts);
+      o.ey[ct] = buf_load_f2(tr, yo[ct], i * ts);
     }
 #pragma unroll
+    for (int nt = 0; nt < NT; nt++) o.bz[nt] = buf_load_f1(zr, zo + nt * 64, i * zs);
+  };
+  auto step = [&](const Ops& o) {
+    const float q = (float)o.q;
+#pragma unroll
     for (int ct = 0; ct < CT; ct++) {
-      const float cr = q * (ex[ct].x * ey[ct].x - ex[ct].y * ey[ct].y);
-      const float ci = q * (ex[ct].x * ey[ct].y + ex[ct].y * ey[ct].x);
+      const float pr = fmaf(o.ex[ct].x, o.ey[ct].x, -o.ex[ct].y * o.ey[ct].y);
+      const float pi = fmaf(o.ex[ct].x, o.ey[ct].y, o.ex[ct].y * o.ey[ct].x);
+      const float cr = q * pr, ci = q * pi;
       s0r[ct] += cr;
       s0i[ct] += ci;
 #pragma unroll
       for (int nt = 0; nt < NT; nt++) {
-        dr[ct][nt] = mfma4f(cr, bz[nt], dr[ct][nt]);
-        di[ct][nt] = mfma4f(ci, bz[nt], di[ct][nt]);
+        dr[ct][nt] = mfma4f(cr, o.bz[nt], dr[ct][nt]);
+        di[ct][nt] = mfma4f(ci, o.bz[nt], di[ct][nt]);
       }
     }
+  };
+  // (a fetch past the last step reads rows past the chunk: zeros)
+  Ops A, B;
+  fetch(0, A);
+  int i = 0;
+  for (; i + 1 < nst; i += 2) {
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(i + 1, B);
+    __builtin_amdgcn_sched_barrier(0);
+    step(A);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(i + 2, A);
+    __builtin_amdgcn_sched_barrier(0);
+    step(B);
   }
+  if (i < nst) step(A);
 #pragma unroll
   for (int ct = 0; ct < CT; ct++) {
     s0r[ct] += __shfl_xor(s0r[ct], 16, 64);
@@ -253,6 +311,7 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma32(Grid g, FrameArg fa, int
 
 hipError_t launch_sfac_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                             hipStream_t s) {
+  if (!tab32_ok(g, max_nm)) return hipErrorInvalidValue;  // the API rejects such frames first
   Tuning tm = t;
   tm.fwd_mode = 1;
   const int ngc = fwd_col_groups(g, tm);
@@ -274,16 +333,23 @@ hipError_t launch_sfac_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, 
 // ------------------------------------------------------------------ adjoint: MM gradients on FP32 matrix cores
 // As the FP64 adjoint with the y phases in LDS: A = z table of 16 atoms per
 // wave (all K steps in registers), B = folded weights (Re P, Im P, Re Pz,
-// Im Pz) from L2, the block's 64 rows of y phases staged in LDS; the
-// epilogue multiplies by conj(e^{i kx x} e^{i ky y}) and sums over its
-// columns; per-atom results leave in FP64.  Block order as the FP64 kernel:
+// Im Pz) from L2, the block's 64 rows of y phases staged in LDS (ny-major,
+// rows of 66 entries); the epilogue multiplies by conj(e^{i kx x} e^{i ky y})
+// and sums over its columns; per-atom results leave in FP64.  The loop is
+// organised as the FP64 kernel's: B through a ring of K steps in flight
+// across column groups (one 16-byte load per lane and step from the
+// lane-major FP32 weights), buffer loads with scalar offsets, no division or
+// branch per group, order pinned with scheduling barriers.  Block order:
 // atom-tile major, optionally with the blocks of one tile on one XCD.
+constexpr int kEyStride32 = 66;  // LDS row of the FP32 adjoint: 64 atoms + 2 (16-byte aligned rows)
+
 template <int NK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl32(
     Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const float2* __restrict__ tab,
     const float* __restrict__ ztab, const float* __restrict__ wfrag, const double2* __restrict__ wk0,
     double* __restrict__ fpart) {
-  extern __shared__ float2 eysh32[];  // [64][NY + 1]
+  extern __shared__ float2 eysh32[];  // [NY][66]
+  constexpr int ES = kEyStride32;
   const int f = blockIdx.z;
   const FrameDev fr = frame32(fa, f);
   const int lane = threadIdx.x & 63;
@@ -296,10 +362,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int tile = bid / kc_n, kc = bid - tile * kc_n;
   const int ablk = tile * 64;
   if (ablk >= fr.nm) return;  // uniform over the block
-  const int ys = g.NY + 1;
   for (int e = threadIdx.x; e < 64 * g.NY; e += 256) {
     const int a = e / g.NY, c = e - a * g.NY;
-    eysh32[a * ys + c] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
+    eysh32[c * ES + a] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
   }
   __syncthreads();
   const int a0 = ablk + wave * 16;
@@ -315,63 +380,78 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int st = 0; st < NK; st++) za[st] = zr[4 * st];
   }
   float acc0[4], acc1[4], acc2[4], acc3[4];
-  int arow[4], erow[4];
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
-    acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.f;
-    arow[r] = fr.moff + min(a0 + 4 * lk + r, fr.nm - 1);
-    erow[r] = (wave * 16 + 4 * lk + r) * ys;
-  }
-  // this lane's column in group gbeg, then 16 columns further per group; the
-  // x phases of the next group are in flight while a group is contracted
-  int colp = gbeg * 16 + li;
-  float2 exn[4];
+  for (int r = 0; r < 4; r++) acc0[r] = acc1[r] = acc2[r] = acc3[r] = 0.f;
+  // x phases: this lane's rows a0 + 4 lk + r (r = 0..3: one row apart)
+  const __amdgpu_buffer_rsrc_t xr = buf_rsrc32(tab + (size_t)fr.moff * g.NXY, (unsigned)fr.nm * g.NXY * 8u);
+  const int xoff = (a0 + 4 * lk) * g.NXY * 8;
+  const int xrow = g.NXY * 8;
+  const int erow = wave * 16 + 4 * lk;  // LDS entry of row r = 0 (rows r follow)
+  const int q16 = 16 / g.NY, r16 = 16 - q16 * g.NY;
+  const double2* __restrict__ w0f = wk0 + (size_t)f * g.NG * 16;
+  const float* __restrict__ wff = wfrag + (size_t)f * g.NG * NK * 256;
+  constexpr int BD = NK % 3 == 0 ? 3 : (NK % 4 == 0 && NK <= 4) ? 4 : 2;
+  static_assert(NK % BD == 0, "ring depth must divide the K steps");
+  float4 bq[BD];
+  auto wrsrc = [&](int grp) { return buf_rsrc32(wff + (size_t)grp * NK * 256, NK * 256 * 4); };
+  int col = gbeg * 16 + li;
+  int nx = col / g.NY, iy = col - nx * g.NY;
   {
-    const int nxp = min(colp, g.NCOL - 1) / g.NY;
+    const __amdgpu_buffer_rsrc_t w = wrsrc(min(gbeg, g.NG - 1));  // an empty chunk loads and discards
 #pragma unroll
-    for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
+    for (int st = 0; st < BD; st++) bq[st] = buf_load_f4(w, lane * 16, st * 1024);
   }
   for (int grp = gbeg; grp < gend; grp++) {
-    const int col = colp;
-    const bool cok = col < g.NCOL;
-    const int colc = cok ? col : g.NCOL - 1;
-    const int nx = colc / g.NY, iy = colc - nx * g.NY;
     float2 ex[4];
-#pragma unroll
-    for (int r = 0; r < 4; r++) ex[r] = exn[r];
-    colp += 16;
     {
-      const int nxp = min(colp, g.NCOL - 1) / g.NY;
+      const int vo = xoff + min(nx, g.NX - 1) * 8;
 #pragma unroll
-      for (int r = 0; r < 4; r++) exn[r] = tab[(size_t)arow[r] * g.NXY + nxp];
+      for (int r = 0; r < 4; r++) ex[r] = buf_load_f2(xr, vo, r * xrow);
     }
-    const double2 w0d = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
-    const float w0x = (float)w0d.x, w0y = (float)w0d.y;
-    const float* __restrict__ wg = wfrag + ((size_t)f * g.NG + grp) * NK * 256 + lane;
-    v4f Pr = v4f{w0x, w0x, w0x, w0x}, Pi = v4f{w0y, w0y, w0y, w0y};
-    v4f Zr = v4f{0.f, 0.f, 0.f, 0.f}, Zi = v4f{0.f, 0.f, 0.f, 0.f};
+    const __amdgpu_buffer_rsrc_t wn = wrsrc(min(grp + 1, gend - 1));
+    const __amdgpu_buffer_rsrc_t wr = wrsrc(grp);
+    const double2 w0d = w0f[grp * 16 + li];
+    v4f Pr = v4f{0.f, 0.f, 0.f, 0.f}, Pi = Pr, Zr = Pr, Zi = Pr;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int st = 0; st < NK; st++) {
-      const float b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
-      Pr = mfma4f(za[st], b0, Pr);
-      Pi = mfma4f(za[st], b1, Pi);
-      Zr = mfma4f(za[st], b2, Zr);
-      Zi = mfma4f(za[st], b3, Zi);
+      float4& b = bq[st % BD];
+      Pr = mfma4f(za[st], b.x, Pr);
+      Pi = mfma4f(za[st], b.y, Pi);
+      Zr = mfma4f(za[st], b.z, Zr);
+      Zi = mfma4f(za[st], b.w, Zi);
+      if (st + BD < NK)
+        b = buf_load_f4(wr, lane * 16, (st + BD) * 1024);
+      else
+        b = buf_load_f4(wn, lane * 16, (st + BD - NK) * 1024);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (cok) {
-      const float fnx = (float)nx, fny = (float)(iy - g.my);
+    // columns past NCOL have zero weights: their terms vanish without a branch
+    const float w0x = (float)w0d.x, w0y = (float)w0d.y;
+    const float fnx = (float)nx, fny = (float)(iy - g.my);
+    const float4* __restrict__ ey = reinterpret_cast<const float4*>(eysh32 + iy * ES + erow);
+    const float4 e01 = ey[0], e23 = ey[1];
+    const float2 e[4] = {make_float2(e01.x, e01.y), make_float2(e01.z, e01.w), make_float2(e23.x, e23.y),
+                         make_float2(e23.z, e23.w)};
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y})
-        const float2 e = eysh32[erow[r] + iy];
-        const float cx = ex[r].x * e.x - ex[r].y * e.y;
-        const float cy = -(ex[r].x * e.y + ex[r].y * e.x);
-        const float cpi = cx * Pi[r] + cy * Pr[r];
-        acc0[r] += cx * Pr[r] - cy * Pi[r];
-        acc1[r] += fnx * cpi;
-        acc2[r] += fny * cpi;
-        acc3[r] += cx * Zi[r] + cy * Zr[r];
-      }
+    for (int r = 0; r < 4; r++) {
+      // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y}) = cr - i s
+      const float pr = Pr[r] + w0x, pi = Pi[r] + w0y;
+      const float cr = fmaf(ex[r].x, e[r].x, -ex[r].y * e[r].y);
+      const float s = fmaf(ex[r].x, e[r].y, ex[r].y * e[r].x);
+      const float cpi = fmaf(cr, pi, -s * pr);
+      acc0[r] = fmaf(cr, pr, acc0[r]);
+      acc0[r] = fmaf(s, pi, acc0[r]);
+      acc1[r] = fmaf(fnx, cpi, acc1[r]);
+      acc2[r] = fmaf(fny, cpi, acc2[r]);
+      acc3[r] = fmaf(cr, Zi[r], acc3[r]);
+      acc3[r] = fmaf(-s, Zr[r], acc3[r]);
+    }
+    iy += r16;
+    nx += q16;
+    if (iy >= g.NY) {
+      iy -= g.NY;
+      nx++;
     }
   }
 #pragma unroll
@@ -406,7 +486,8 @@ hipError_t launch_force_mm32(const Grid& g, const Tuning& t, const FrameArg& fa,
                              hipStream_t s) {
   if (max_nm == 0) return hipSuccess;
   dim3 grid(((max_nm + 63) / 64) * t.kc, 1, fa.n_frames);
-  const size_t lds = (size_t)64 * (g.NY + 1) * sizeof(float2);
+  if (!tab32_ok(g, max_nm)) return hipErrorInvalidValue;  // the API rejects such frames first
+  const size_t lds = (size_t)kEyStride32 * g.NY * sizeof(float2);
   const int xcd = (t.bwd_xcd && fa.n_frames == 1) ? 1 : 0;
 #define FE(N)                                                                                                      \
   case N:                                                                                                          \
