@@ -1532,39 +1532,56 @@ extern "C" ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char*
       if (ff.size() * bf.size() > 1) {
         TCHK(hipMalloc(&d_out, sizeof(double) * (1 + 10 * (size_t)std::max(nq, 1))));
         TCHK(hipMalloc(&d_ctx, std::max<size_t>(ctx_bytes(plan->g, nq, n_mm), 256)));
-        double best_s = 1e30;
-        Tuning pick = best;
+        // the combinations are timed in interleaved rounds (drift of clocks and
+        // of the other streams' timing affects all alike) and each keeps the
+        // median of its rounds
+        std::vector<Tuning> cands;
         for (const Tuning& a : ff)
           for (const Tuning& b : bf) {
-            plan->t = best;
-            plan->t.fwd_mode = a.fwd_mode;
-            plan->t.fwd_ct = a.fwd_ct;
-            plan->t.fwd_target = a.fwd_target;
-            plan->t.fwd_xcd = a.fwd_xcd;
-            plan->t.a_chunk = 0;
-            plan->t.bwd_ilp = b.bwd_ilp;
-            plan->t.bwd_xcd = b.bwd_xcd;
-            plan->t.kc = b.kc;
-            const Tuning cand = plan->t;
+            Tuning c = best;
+            c.fwd_mode = a.fwd_mode;
+            c.fwd_ct = a.fwd_ct;
+            c.fwd_target = a.fwd_target;
+            c.fwd_xcd = a.fwd_xcd;
+            c.a_chunk = 0;
+            c.bwd_ilp = b.bwd_ilp;
+            c.bwd_xcd = b.bwd_xcd;
+            c.kc = b.kc;
+            cands.push_back(c);
+          }
+        constexpr int kRounds = 5;
+        std::vector<std::vector<double>> times(cands.size());
+        for (int rd = 0; rd < kRounds; rd++)
+          for (size_t ci = 0; ci < cands.size(); ci++) {
+            plan->t = cands[ci];
             const double us = time_it([&]() {
               const ewald_status_t r =
                   ewald_forward(plan, nq, dqp, dQ, dmu, dth, n_mm, dm, dq, d_out, d_out + 1, d_out + 1 + nq,
                                 d_out + 1 + 4 * (size_t)nq, d_ctx, (void*)s);
               return r == EWALD_OK ? hipSuccess : hipErrorLaunchFailure;
             });
-            plan->t = cand;
+            plan->t = cands[ci];
             if (us < 0) {
               st = fail(EWALD_ERR_HIP, "autotune: step failed: %s", g_last_error.c_str());
               goto done;
             }
-            snprintf(item, sizeof(item), ", \"step_ct%d_%d_x%d_bwd%d_kc%d_x%d\": %.1f", cand.fwd_ct, cand.fwd_target,
-                     cand.fwd_xcd, cand.bwd_ilp, cand.kc, cand.bwd_xcd, us);
-            report += item;
-            if (us < best_s) {
-              best_s = us;
-              pick = cand;
-            }
+            times[ci].push_back(us);
           }
+        double best_s = 1e30;
+        Tuning pick = best;
+        for (size_t ci = 0; ci < cands.size(); ci++) {
+          std::vector<double> v = times[ci];
+          std::sort(v.begin(), v.end());
+          const double med = v[v.size() / 2];
+          const Tuning& c = cands[ci];
+          snprintf(item, sizeof(item), ", \"step_ct%d_%d_x%d_bwd%d_kc%d_x%d\": %.1f", c.fwd_ct, c.fwd_target,
+                   c.fwd_xcd, c.bwd_ilp, c.kc, c.bwd_xcd, med);
+          report += item;
+          if (med < best_s) {
+            best_s = med;
+            pick = c;
+          }
+        }
         best = pick;
       }
     }
