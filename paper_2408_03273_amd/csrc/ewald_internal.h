@@ -155,7 +155,8 @@ inline int eyl_waves(const Grid& g) { return eyl_lds_bytes(g, 4) <= 65536 ? 4 : 
 // buffer offsets
 inline bool tab32_ok(const Grid& g, long nm) { return (size_t)nm * g.NXY * 16 < (size_t(1) << 31); }
 // the forward tiles per wave are limited by the LDS of the block reduction
-inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 6; }
+// (64 KB of FP64 partial tiles at CT NT = 8; gfx950 gives a block up to 160 KB)
+inline bool mfma_fwd_ct_ok(const Grid& g, int ct) { return (ct == 1 || ct == 2 || ct == 4) && ct * g.NT <= 8; }
 inline int fwd_col_groups(const Grid& g, const Tuning& t) {
   return t.fwd_mode == 1 ? (g.NG + t.fwd_ct - 1) / t.fwd_ct : ((g.NCOL + 63) / 64) * (g.NZP / g.Zc);
 }

@@ -679,7 +679,7 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
                                                       const double2* __restrict__ tab,
                                                       const double* __restrict__ ztab,
                                                       double2* __restrict__ spart) {
-  static_assert(CT * NT <= 6, "LDS budget of the block reduction");
+  static_assert(CT * NT <= 8, "LDS budget of the block reduction (66 KB at 8)");
   constexpr int NACC = CT * NT * 8;  // accumulator doubles per lane
   __shared__ double red[2][NACC * 64];
   __shared__ double s0red[4][CT][2][16];
@@ -885,7 +885,7 @@ static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const Fram
     launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, xcd, cap_mm, w); \
     return hipGetLastError();                                                         \
   }
-  SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(1, 3) SF(2, 3) SF(1, 4)
+  SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(4, 2) SF(1, 3) SF(2, 3) SF(1, 4) SF(2, 4)
 #undef SF
   return hipErrorInvalidValue;
 }
