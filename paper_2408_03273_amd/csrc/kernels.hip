@@ -980,7 +980,7 @@ hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa,
 // site from S_MM.  Backward: the QM-MM long-range gradient with the
 // effective moments, and the QM-QM long-range gradient and moment
 // derivatives of the order-2 truncated image energy.
-template <int BWD>
+template <int BWD, int S>
 __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_pc, const double2* __restrict__ smm,
                                                     size_t smm_stride, const double* __restrict__ Q,
                                                     const double* __restrict__ mu, const double* __restrict__ theta,
@@ -991,25 +991,38 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
                                                     double* __restrict__ qacc) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
-  const int j = blockIdx.x;
-  if (j >= fr.nq) return;
-  const int r = fr.qoff + j;
+  // S sites per block: the per-k data (weight, S_MM, A/B/C) is loaded once per
+  // k and applied to each site; the sites' moments are block-uniform
+  const int j0 = blockIdx.x * S;
+  if (j0 >= fr.nq) return;
+  const int ns = min(S, fr.nq - j0);  // uniform
   // BWD: 0 forward (10 sums), 1 adjoint (16), 2 both (26, adjoint after the forward ones)
   constexpr int NV = BWD == 0 ? 10 : BWD == 1 ? 16 : 26;
   constexpr int OB = BWD == 2 ? 10 : 0;
-  double acc[NV];
+  double acc[S][NV];
 #pragma unroll
-  for (int t = 0; t < NV; t++) acc[t] = 0.0;
-  const double2* row = qtab + (size_t)r * g.R;
-  double Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
-  double Qo = 0, o0 = 0, o1 = 0, o2 = 0, u0 = 0, u1 = 0, u2 = 0, u3 = 0, u4 = 0, u5 = 0;
-  if (BWD) {
-    const double* qe = qeff + 10 * (size_t)r;
-    Qe = qe[0]; m0 = qe[1]; m1 = qe[2]; m2 = qe[3];
-    t0 = qe[4]; t1 = qe[5]; t2 = qe[6]; t3 = qe[7]; t4 = qe[8]; t5 = qe[9];
-    Qo = Q[r]; o0 = mu[3 * (size_t)r]; o1 = mu[3 * (size_t)r + 1]; o2 = mu[3 * (size_t)r + 2];
-    const double* th = theta + 6 * (size_t)r;
-    u0 = th[0]; u1 = th[1]; u2 = th[2]; u3 = th[3]; u4 = th[4]; u5 = th[5];
+  for (int u = 0; u < S; u++)
+#pragma unroll
+    for (int t = 0; t < NV; t++) acc[u][t] = 0.0;
+  struct Mom {
+    double Qe, m0, m1, m2, t0, t1, t2, t3, t4, t5, Qo, o0, o1, o2, u0, u1, u2, u3, u4, u5;
+  };
+  Mom mo[S];
+  const double2* row[S];
+#pragma unroll
+  for (int u = 0; u < S; u++) {
+    const int r = fr.qoff + min(j0 + u, fr.nq - 1);
+    row[u] = qtab + (size_t)r * g.R;
+    Mom& m = mo[u];
+    m = Mom{};
+    if (BWD) {
+      const double* qe = qeff + 10 * (size_t)r;
+      m.Qe = qe[0]; m.m0 = qe[1]; m.m1 = qe[2]; m.m2 = qe[3];
+      m.t0 = qe[4]; m.t1 = qe[5]; m.t2 = qe[6]; m.t3 = qe[7]; m.t4 = qe[8]; m.t5 = qe[9];
+      m.Qo = Q[r]; m.o0 = mu[3 * (size_t)r]; m.o1 = mu[3 * (size_t)r + 1]; m.o2 = mu[3 * (size_t)r + 2];
+      const double* th = theta + 6 * (size_t)r;
+      m.u0 = th[0]; m.u1 = th[1]; m.u2 = th[2]; m.u3 = th[3]; m.u4 = th[4]; m.u5 = th[5];
+    }
   }
   // thread item = (column, p = |nz|): k = (nx, ny, +p) and (nx, ny, -p) share e^{i(kx x + ky y)}
   const int NP = g.mz + 1;
@@ -1018,8 +1031,12 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
     const int col = t / NP, p = t - col * NP;
     const int nx = col / g.NY, iy = col - nx * g.NY;
     const int ny = iy - g.my;
-    const double2 exy = cmul(row[nx], row[g.NX + iy]);
-    const double2 ez = row[g.NX + g.NY + g.mz + p];
+    double2 exy[S], ez[S];
+#pragma unroll
+    for (int u = 0; u < S; u++) {
+      exy[u] = cmul(row[u][nx], row[u][g.NX + iy]);
+      ez[u] = row[u][g.NX + g.NY + g.mz + p];
+    }
     for (int sg = 0; sg < 2; sg++) {
       if (sg == 1 && p == 0) break;
       const int nz = sg ? -p : p;
@@ -1028,79 +1045,96 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
       if (w == 0.0) continue;
       const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
                    kz = 2.0 * kPi * nz * fr.inv_box[2];
-      const double2 e = cmul(exy, sg ? cconj(ez) : ez);
-      const double2 S = smm[(size_t)f * smm_stride + k];
-      // Y = e conj(S)
-      const double yr = e.x * S.x + e.y * S.y, yi = e.y * S.x - e.x * S.y;
-      if (BWD != 1) {
-        acc[0] += w * yr;
-        acc[1] -= w * kx * yi;
-        acc[2] -= w * ky * yi;
-        acc[3] -= w * kz * yi;
-        const double h = -0.5 * w * yr;
-        acc[4] += h * kx * kx;
-        acc[5] += h * kx * ky;
-        acc[6] += h * kx * kz;
-        acc[7] += h * ky * ky;
-        acc[8] += h * ky * kz;
-        acc[9] += h * kz * kz;
+      const double2 Sk = smm[(size_t)f * smm_stride + k];
+      double2 A = make_double2(0.0, 0.0), B = A, C = A;
+      if (BWD != 0 && qmqm) {
+        const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
+        A = abc[0];
+        B = abc[1];
+        C = abc[2];
       }
-      if (BWD != 0) {
-        // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
-        const double kthk = kx * kx * t0 + ky * ky * t3 + kz * kz * t5 + 2.0 * (kx * ky * t1 + kx * kz * t2 + ky * kz * t4);
-        const double wr = Qe - 0.5 * kthk, wi = kx * m0 + ky * m1 + kz * m2;
-        const double gr = -(wr * yi + wi * yr);
-        acc[OB + 0] += w * kx * gr;
-        acc[OB + 1] += w * ky * gr;
-        acc[OB + 2] += w * kz * gr;
-        if (qmqm) {
-          const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
-          const double2 A = abc[0], B = abc[1], C = abc[2];
-          const double kmu = kx * o0 + ky * o1 + kz * o2;
-          const double kthko = kx * kx * u0 + ky * ky * u3 + kz * kz * u5 + 2.0 * (kx * ky * u1 + kx * kz * u2 + ky * kz * u4);
-          // a_j = Q e, b_j = i kmu e, c_j = -1/2 kthk e
-          const double ajr = Qo * e.x, aji = Qo * e.y;
-          const double bjr = -kmu * e.y, bji = kmu * e.x;
-          const double cjr = -0.5 * kthko * e.x, cji = -0.5 * kthko * e.y;
-          const double T1r = A.x + B.x + C.x, T1i = A.y + B.y + C.y;
-          const double T2r = A.x + B.x, T2i = A.y + B.y;
-          // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
-          const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
-          acc[OB + 3] -= w * kx * zi;
-          acc[OB + 4] -= w * ky * zi;
-          acc[OB + 5] -= w * kz * zi;
-          acc[OB + 6] += w * (e.x * T1r + e.y * T1i);
-          const double ime = e.y * T2r - e.x * T2i;
-          acc[OB + 7] -= w * kx * ime;
-          acc[OB + 8] -= w * ky * ime;
-          acc[OB + 9] -= w * kz * ime;
-          const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
-          acc[OB + 10] += h * kx * kx;
-          acc[OB + 11] += h * kx * ky;
-          acc[OB + 12] += h * kx * kz;
-          acc[OB + 13] += h * ky * ky;
-          acc[OB + 14] += h * ky * kz;
-          acc[OB + 15] += h * kz * kz;
+#pragma unroll
+      for (int u = 0; u < S; u++) {
+        if (u >= ns) break;  // uniform
+        const Mom& m = mo[u];
+        double* ac = acc[u];
+        const double2 e = cmul(exy[u], sg ? cconj(ez[u]) : ez[u]);
+        // Y = e conj(S)
+        const double yr = e.x * Sk.x + e.y * Sk.y, yi = e.y * Sk.x - e.x * Sk.y;
+        if (BWD != 1) {
+          ac[0] += w * yr;
+          ac[1] -= w * kx * yi;
+          ac[2] -= w * ky * yi;
+          ac[3] -= w * kz * yi;
+          const double h = -0.5 * w * yr;
+          ac[4] += h * kx * kx;
+          ac[5] += h * kx * ky;
+          ac[6] += h * kx * kz;
+          ac[7] += h * ky * ky;
+          ac[8] += h * ky * kz;
+          ac[9] += h * kz * kz;
+        }
+        if (BWD != 0) {
+          // QM-MM: d/dR of Re[(Q' + i k.mu' - 1/2 k.th'.k) Y] = k Re[i (..) Y]
+          const double kthk = kx * kx * m.t0 + ky * ky * m.t3 + kz * kz * m.t5 +
+                              2.0 * (kx * ky * m.t1 + kx * kz * m.t2 + ky * kz * m.t4);
+          const double wr = m.Qe - 0.5 * kthk, wi = kx * m.m0 + ky * m.m1 + kz * m.m2;
+          const double gr = -(wr * yi + wi * yr);
+          ac[OB + 0] += w * kx * gr;
+          ac[OB + 1] += w * ky * gr;
+          ac[OB + 2] += w * kz * gr;
+          if (qmqm) {
+            const double kmu = kx * m.o0 + ky * m.o1 + kz * m.o2;
+            const double kthko = kx * kx * m.u0 + ky * ky * m.u3 + kz * kz * m.u5 +
+                                 2.0 * (kx * ky * m.u1 + kx * kz * m.u2 + ky * kz * m.u4);
+            // a_j = Q e, b_j = i kmu e, c_j = -1/2 kthk e
+            const double ajr = m.Qo * e.x, aji = m.Qo * e.y;
+            const double bjr = -kmu * e.y, bji = kmu * e.x;
+            const double cjr = -0.5 * kthko * e.x, cji = -0.5 * kthko * e.y;
+            const double T1r = A.x + B.x + C.x, T1i = A.y + B.y + C.y;
+            const double T2r = A.x + B.x, T2i = A.y + B.y;
+            // Im[a_j conj(T1) + b_j conj(T2) + c_j conj(A)]
+            const double zi = (aji * T1r - ajr * T1i) + (bji * T2r - bjr * T2i) + (cji * A.x - cjr * A.y);
+            ac[OB + 3] -= w * kx * zi;
+            ac[OB + 4] -= w * ky * zi;
+            ac[OB + 5] -= w * kz * zi;
+            ac[OB + 6] += w * (e.x * T1r + e.y * T1i);
+            const double ime = e.y * T2r - e.x * T2i;
+            ac[OB + 7] -= w * kx * ime;
+            ac[OB + 8] -= w * ky * ime;
+            ac[OB + 9] -= w * kz * ime;
+            const double h = -0.5 * w * (e.x * A.x + e.y * A.y);
+            ac[OB + 10] += h * kx * kx;
+            ac[OB + 11] += h * kx * ky;
+            ac[OB + 12] += h * kx * kz;
+            ac[OB + 13] += h * ky * ky;
+            ac[OB + 14] += h * ky * kz;
+            ac[OB + 15] += h * kz * kz;
+          }
         }
       }
     }
   }
-  double tot[NV];
-  block_sum256<NV>(acc, tot);
-  if (threadIdx.x == 0) {
-    double* qa = qacc + (size_t)r * QA_STRIDE;
-    if (BWD != 1) {
-      atomicAdd(&qa[QA_PHI_LR], tot[0]);
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_LR + t], tot[1 + t]);
-      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_LR + t], tot[4 + t]);
-    }
-    if (BWD != 0) {
-      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_LR + t], tot[OB + t]);
-      if (qmqm) {
-        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QQ_LR + t], tot[OB + 3 + t]);
-        atomicAdd(&qa[QA_DQ_QQ_LR], tot[OB + 6]);
-        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DMU_QQ_LR + t], tot[OB + 7 + t]);
-        for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_DTH_QQ_LR + t], tot[OB + 10 + t]);
+#pragma unroll
+  for (int u = 0; u < S; u++) {
+    if (u >= ns) break;  // uniform
+    double tot[NV];
+    block_sum256<NV>(acc[u], tot);
+    if (threadIdx.x == 0) {
+      double* qa = qacc + (size_t)(fr.qoff + j0 + u) * QA_STRIDE;
+      if (BWD != 1) {
+        atomicAdd(&qa[QA_PHI_LR], tot[0]);
+        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_LR + t], tot[1 + t]);
+        for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_LR + t], tot[4 + t]);
+      }
+      if (BWD != 0) {
+        for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_LR + t], tot[OB + t]);
+        if (qmqm) {
+          for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QQ_LR + t], tot[OB + 3 + t]);
+          atomicAdd(&qa[QA_DQ_QQ_LR], tot[OB + 6]);
+          for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DMU_QQ_LR + t], tot[OB + 7 + t]);
+          for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_DTH_QQ_LR + t], tot[OB + 10 + t]);
+        }
       }
     }
   }
@@ -1110,15 +1144,18 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
                              size_t smm_frame_stride, const double* Q, const double* mu, const double* theta,
                              int backward, int qmqm, Work& w, hipStream_t s) {
   if (max_nq == 0) return hipSuccess;
-  // about 640 blocks in all: enough k items per thread to amortise the block reduction
-  int n_pc = (640 + total_nq - 1) / (total_nq > 0 ? total_nq : 1);
+  // two sites per block (the per-k loads serve both); about 640 blocks in all:
+  // enough k items per thread to amortise the block reduction
+  constexpr int S = 2;
+  const int site_blocks = (total_nq + S - 1) / S;
+  int n_pc = (640 + site_blocks - 1) / (site_blocks > 0 ? site_blocks : 1);
   const int kblocks = (g.NCOL * (g.mz + 1) + 255) / 256;
   if (n_pc > kblocks) n_pc = kblocks;
   if (n_pc < 1) n_pc = 1;
-  dim3 grid(max_nq, n_pc, fa.n_frames);
-#define PQ(B)                                                                                               \
-  hipLaunchKernelGGL(k_project_qm<B>, grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, theta, \
-                     w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc)
+  dim3 grid((max_nq + S - 1) / S, n_pc, fa.n_frames);
+#define PQ(B)                                                                                                  \
+  hipLaunchKernelGGL((k_project_qm<B, S>), grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, \
+                     theta, w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc)
   if (backward == 2)
     PQ(2);
   else if (backward)
