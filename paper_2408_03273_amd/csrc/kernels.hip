@@ -939,9 +939,24 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
     const int col = k / g.NZ, iz = k - col * g.NZ;
     const int nslots = plain ? 1 : (fr.nm + a_chunk - 1) / a_chunk;
     const size_t idx = kmajor ? (size_t)k : (size_t)iz * g.NCOL + col;
+    // eight partials in flight per round trip (a load-add chain per slot left
+    // the kernel latency bound); the slots are still summed in order
+    const size_t sstride = (size_t)g.NZP * g.NCOL;
+    const double2* __restrict__ pp = spart + (size_t)fr.slot_base * sstride + idx;
     double sr = 0.0, si = 0.0;
-    for (int sl = 0; sl < nslots; sl++) {
-      const double2 p = spart[(size_t)(fr.slot_base + sl) * g.NZP * g.NCOL + idx];
+    int sl = 0;
+    for (; sl + 8 <= nslots; sl += 8) {
+      double2 p[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) p[u] = pp[(size_t)(sl + u) * sstride];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        sr += p[u].x;
+        si += p[u].y;
+      }
+    }
+    for (; sl < nslots; sl++) {
+      const double2 p = pp[(size_t)sl * sstride];
       sr += p.x;
       si += p.y;
     }
