@@ -1052,22 +1052,32 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
       exy[u] = cmul(row[u][nx], row[u][g.NX + iy]);
       ez[u] = row[u][g.NX + g.NY + g.mz + p];
     }
+    // both signs of nz at once, without data-dependent branches, so that all
+    // the item's loads are issued together (one round trip per item); the
+    // second sign of p = 0 and k outside the half space carry zero weight
+    const int k0 = col * g.NZ + g.mz;
+    double wv[2];
+    double2 Sv[2], Av[2], Bv[2], Cv[2];
+#pragma unroll
     for (int sg = 0; sg < 2; sg++) {
-      if (sg == 1 && p == 0) break;
-      const int nz = sg ? -p : p;
-      const int k = col * g.NZ + g.mz + nz;
-      const double w = kw[(size_t)f * g.KF + k];
-      if (w == 0.0) continue;
-      const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
-                   kz = 2.0 * kPi * nz * fr.inv_box[2];
-      const double2 Sk = smm[(size_t)f * smm_stride + k];
-      double2 A = make_double2(0.0, 0.0), B = A, C = A;
+      const int k = k0 + (sg ? -p : p);
+      wv[sg] = (sg && p == 0) ? 0.0 : kw[(size_t)f * g.KF + k];
+      Sv[sg] = smm[(size_t)f * smm_stride + k];
+      Av[sg] = Bv[sg] = Cv[sg] = make_double2(0.0, 0.0);
       if (BWD != 0 && qmqm) {
         const double2* abc = sabc + ((size_t)f * g.KF + k) * 3;
-        A = abc[0];
-        B = abc[1];
-        C = abc[2];
+        Av[sg] = abc[0];
+        Bv[sg] = abc[1];
+        Cv[sg] = abc[2];
       }
+    }
+#pragma unroll
+    for (int sg = 0; sg < 2; sg++) {
+      const int nz = sg ? -p : p;
+      const double w = wv[sg];
+      const double kx = 2.0 * kPi * nx * fr.inv_box[0], ky = 2.0 * kPi * ny * fr.inv_box[1],
+                   kz = 2.0 * kPi * nz * fr.inv_box[2];
+      const double2 Sk = Sv[sg], A = Av[sg], B = Bv[sg], C = Cv[sg];
 #pragma unroll
       for (int u = 0; u < S; u++) {
         if (u >= ns) break;  // uniform
