@@ -149,6 +149,14 @@ def main():
                 kernel=dom, flops_per_launch=flops[dom], avg_launch_us=round(per[dom]["avg_us"], 2),
                 executed_flops_per_launch=executed[dom],
                 executed_frac=round(executed[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    # the same kernel launched alone: the autotuner's standalone timing of the
+    # chosen candidate (HIP events around repeated launches on a synthetic frame
+    # of the same size, before the timed region); inside the step the two hot
+    # loops and the QM-side kernels share the GPU, so the in-step duration above
+    # also holds the time the kernel's blocks wait for room
+    iso = _isolated_us(cache, pplan.describe(), dom)
+    roof["isolated_avg_us"] = iso
+    roof["isolated_frac"] = None if iso is None else round(flops[dom] / (iso * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4)
     hot_total_us = sum(per[k]["avg_us"] for k in hot)
     path_flops = 14.0 * nh * s.nm
     extra = dict(
@@ -219,6 +227,31 @@ def _scf_update(plan, inputs, s, step_ms, calls=20):
     us = (time.perf_counter() - t0) * 1e6 / calls
     plan.close()
     return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
+
+
+def _isolated_us(cache, describe, kernel):
+    """Standalone launch time (us) of the plan's hot-loop candidate from the autotune cache, or None."""
+    import re
+    try:
+        lines = open(cache).read().strip().splitlines()
+    except OSError:
+        return None
+    if not lines:
+        return None
+    times = json.loads(lines[-1]).get("times_us", {})
+    if kernel == "force_mm":
+        m = re.search(r"bwd=mfma-fold-eyl xcd=(\d)(?: kc=(\d+))?", describe)
+        if not m:
+            return None
+        keys = [k for k in times if k.startswith("bwd6_") and k.endswith(f"_x{m.group(1)}")
+                and (m.group(2) is None or k.startswith(f"bwd6_kc{m.group(2)}_"))]
+    else:
+        m = re.search(r"fwd=mfma-fold ct=(\d) nt=\d xcd=(\d) blocks~(\d+)", describe)
+        if not m:
+            return None
+        keys = [f"fwd_mfma_ct{m.group(1)}_{m.group(3)}_x{m.group(2)}"]
+    vals = [times[k] for k in keys if k in times]
+    return round(min(vals), 2) if vals else None
 
 
 def _per_config(dev, no_autotune, steps=5):

@@ -476,16 +476,10 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
-      // second stream: real space first (it needs no reciprocal data; prep has
-      // zeroed rpart: over all pairs the MM-side adjoint terms accumulate there
-      // with atomics), then the QM phase tables and structure factors (A, B, C,
-      // adjoint weights), so that the adjoint hot loop can start as soon as the
-      // MM tables are ready; the small kernels run before the big grids of the
-      // hot loops fill the GPU
-      if (q.cells)
-        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
-      else
-        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+      // second stream: the QM phase tables and structure factors (A, B, C,
+      // adjoint weights) first, while the forward hot loop has not yet filled
+      // the GPU (behind it they were starved and held the adjoint back); the
+      // adjoint hot loop follows as soon as the MM tables are ready
       LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm,
                        pl->cap_mm, tables, 1, PREP_QM_TAB));
       LCHK(launch_sfac_qm(g, q.fa, q.max_nq, Q, mu, theta, w.qeff, nullptr, 1, w, q.s));
@@ -505,10 +499,18 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
-      // second stream: the adjoint hot loop (and the MM side of real space with the cell list)
+      // second stream: the adjoint hot loop, then real space (forward, QM- and
+      // MM-side adjoint in one pass; prep has zeroed rpart, where the MM-side
+      // terms accumulate with atomics), which runs beside the projection on
+      // the caller stream and is needed only by the final epilogue
       HIPCHK(hipStreamWaitEvent(q.s, pl->ev_mtab, 0));
       LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
-      if (q.cells) LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
+      if (q.cells) {
+        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
+        LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
+      } else {
+        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+      }
     }
   }
   HIPCHK(hipStreamWaitEvent(q.s, pl->ev_qside, 0));
