@@ -254,8 +254,13 @@ ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewald_frame_t* 
                            double* g_mm_q, void* stream);
 
 /* Time the candidate tilings of the two reciprocal-space kernels for a
- * system of n_mm MM charges on the plan's device and keep the fastest in the
- * plan (and in cache_path as JSON lines if not null).  Synchronises. */
+ * system of n_mm MM charges (synthetic, with the plan's QM capacity up to 64
+ * sites) on the plan's device: each kernel alone, then the finalists within
+ * 3% of the best as whole forward+adjoint steps in interleaved rounds; keep
+ * the fastest step in the plan (and in cache_path as JSON lines if not null;
+ * a later call with the same key reads it instead).  Allocates its own
+ * scratch inputs and streams and synchronises.  n_mm outside 1..max_mm, or a
+ * frame too large for the kernels' 32-bit offsets: EWALD_ERR_CAPACITY. */
 ewald_status_t ewald_autotune(ewald_plan* plan, int n_mm, const char* cache_path);
 
 /* Per-kernel launch counts and summed durations (ms) since the last report,

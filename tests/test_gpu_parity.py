@@ -87,6 +87,20 @@ def test_backward_kernel_variants(variant, monkeypatch):
     _check(wl.random_system(42, 3, 700, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=5))
 
 
+@pytest.mark.parametrize("kc,xcd", [("1", "1"), ("2", "0"), ("5", "1"), ("16", "1"), ("16", "0")])
+def test_adjoint_column_chunks_and_block_order(kc, xcd, monkeypatch):
+    """The LDS-y matrix-core adjoint with 1 to 16 column chunks per atom tile
+    (16 leaves some chunks without a column group on these grids) in natural
+    and XCD-grouped block order; K steps 6 and 4 take load rings of depth 3
+    and 4, and the ragged atom counts end in partial tiles whose rows past the
+    frame are read through the buffer bounds."""
+    monkeypatch.setenv("MPEWALD_BWD", "6")
+    monkeypatch.setenv("MPEWALD_KC", kc)
+    monkeypatch.setenv("MPEWALD_BWD_XCD", xcd)
+    _check(wl.random_system(47, 9, 2333, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11)))
+    _check(wl.random_system(48, 3, 701, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=5))
+
+
 @pytest.mark.parametrize("cell_list", [True, False])
 def test_real_space_cell_list_and_all_pairs(cell_list, monkeypatch):
     """Real space over the cell list (>= 3 cells of edge >= rcut per axis) and
@@ -102,15 +116,18 @@ def test_real_space_cell_list_and_all_pairs(cell_list, monkeypatch):
                                          ("1", "4", "1")])
 def test_forward_kernel_variants(mode, ct, xcd, monkeypatch):
     """VALU forward and the folded matrix-core forward with 1, 2 or 4 column
-    tiles per wave (where the z tiles allow it), in natural and XCD-grouped
-    block order, meet the parity bar, on a ragged atom count and a column
-    count that is not a multiple of 16."""
+    tiles per wave (where the z tiles allow it: up to 8 tiles per wave), in
+    natural and XCD-grouped block order, meet the parity bar, on a ragged atom
+    count and a column count that is not a multiple of 16."""
     monkeypatch.setenv("MPEWALD_FWD", mode)
     monkeypatch.setenv("MPEWALD_FWD_CT", ct)
     monkeypatch.setenv("MPEWALD_FWD_XCD", xcd)
     _check(wl.random_system(44, 7, 2901, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11)),
            keys=H.FWD_KEYS)
     _check(wl.random_system(45, 5, 1203, box=(17.0, 17.0, 17.0), alpha=0.4, rcut=8.0, kmax=(5, 5, 3)),
+           keys=H.FWD_KEYS)
+    # four 16-wide z tiles (|nz| <= 27): one or two column tiles per wave
+    _check(wl.random_system(49, 4, 811, box=(15.0, 16.0, 30.0), alpha=0.45, rcut=7.0, kmax=(4, 5, 27)),
            keys=H.FWD_KEYS)
 
 
