@@ -566,7 +566,9 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   pl->t.fwd_target = pl->t.fwd_mode == 1 ? 1024 : 8192;
   pl->t.bwd_ilp = mfma_bwd_eyl_ok(pl->g) ? 6 : mfma_bwd_ok(pl->g) ? 3 : 2;
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
-  // atoms per lane) or 3|4 (matrix cores, 16|32 atoms per wave); MPEWALD_FWD =
+  // atoms per lane), 3|4 (matrix cores, 16|32 atoms per wave), 5 (matrix cores
+  // with separate epilogue waves) or 6 (matrix cores, y phases in LDS);
+  // MPEWALD_SERIAL = 1 runs the adjoint chain on the caller's stream; MPEWALD_FWD =
   // 0|1 (VALU | matrix cores); MPEWALD_FWD_CT = 1|2|4 (matrix-core column
   // tiles per wave); MPEWALD_FWD_PF = 0|1 (VALU prefetch); MPEWALD_FWD_TARGET =
   // forward block count target; MPEWALD_FWD_XCD, MPEWALD_BWD_XCD = 0|1

@@ -1513,14 +1513,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
 // On gfx950 an FP64 matrix-core instruction and a VALU instruction of the
 // same SIMD do not execute together, so every VALU instruction of the column
 // loop lengthens it.  The loop therefore does no address arithmetic per load:
-// B, w0 and the x phases are buffer loads from a wave-uniform resource with
-// one per-lane offset and uniform (scalar) offsets per K step or atom row;
-// the column (nx, ny) of a lane advances without a division; two column
-// groups are unrolled so the prefetched x phases need no register copies;
+// B and the x phases are buffer loads from a wave-uniform resource with one
+// per-lane offset and uniform (scalar) offsets per K step or atom row; the
+// column (nx, ny) of a lane advances without a division; a group's x phases
+// are loaded at its start and used in its epilogue, after the contraction;
 // the nz = 0 weight is added in the epilogue rather than copied into the
-// accumulators; the epilogue is fused multiply-adds.  Buffer loads past the
-// end of their resource return zero, so the atom rows of a partial tile need
-// no clamping (their results are not stored).
+// accumulators; the epilogue is fused multiply-adds with no branch (padded
+// columns have zero weights).  The B fragments of the next BD K steps are in
+// flight through a register ring that runs across groups, its order pinned
+// with scheduling barriers (left alone, the compiler drained each step's
+// loads before the next).  Buffer loads past the end of their resource
+// return zero, so the atom rows of a partial tile need no clamping (their
+// results are not stored).
 // The grid is one-dimensional per frame, atom-tile major: the kc_n blocks of
 // one atom tile are consecutive logical blocks.  With xcd_remap (single
 // frame) consecutive logical blocks are placed on one XCD, so that the blocks
