@@ -157,6 +157,13 @@ def main():
     iso = _isolated_us(cache, pplan.describe(), dom)
     roof["isolated_avg_us"] = iso
     roof["isolated_frac"] = None if iso is None else round(flops[dom] / (iso * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4)
+    # the same against the FP64 throughput this GPU reaches with the library's
+    # probe kernels (back-to-back matrix-core / VALU chains)
+    peaks = _fp64_peaks(dev)
+    roof["measured_peak_tflops"] = peaks
+    unit_peak = peaks.get("mfma_f64" if mfma else "valu_f64")
+    roof["isolated_executed_frac_vs_measured"] = (None if iso is None or not unit_peak else
+                                                  round(executed[dom] / (iso * 1e-6) / 1e12 / unit_peak, 4))
     hot_total_us = sum(per[k]["avg_us"] for k in hot)
     path_flops = 14.0 * nh * s.nm
     extra = dict(
@@ -227,6 +234,39 @@ def _scf_update(plan, inputs, s, step_ms, calls=20):
     us = (time.perf_counter() - t0) * 1e6 / calls
     plan.close()
     return dict(us_per_call=round(us, 1), vs_full_step=round(step_ms * 1e3 / us, 1))
+
+
+def _fp64_peaks(dev, blocks=2048):
+    """FP64 TFLOP/s reached by the library's probe kernels on this GPU: v_mfma_f64
+    16x16x4 in four independent chains per wave, and VALU FMAs in eight chains
+    per lane (mean of five launches of ~1-2 ms, HIP events on the stream)."""
+    import ctypes
+
+    import torch
+
+    from paper_2408_03273_amd import _lib
+    lib = _lib.load()
+    out = torch.empty(4 * blocks, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for kind, name, iters in ((0, "mfma_f64", 2000), (1, "valu_f64", 16000)):
+        fl = ctypes.c_double(0.0)
+
+        def run():
+            _lib.check(lib.ewald_fp64_probe(kind, blocks, iters, ctypes.c_void_p(out.data_ptr()), ctypes.byref(fl),
+                                            ctypes.c_void_p(stream.cuda_stream)))
+
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[name] = round(fl.value / (ms * 1e-3) / 1e12, 2)
+    return res
 
 
 def _isolated_us(cache, describe, kernel):

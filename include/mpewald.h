@@ -279,6 +279,17 @@ const char* ewald_last_error(void);
 /* Library version string. */
 const char* ewald_version(void);
 
+/* FP64 throughput probe (a diagnostic beside the published peaks, for
+ * roofline reports): kind 0 issues back-to-back v_mfma_f64_16x16x4
+ * instructions in four independent accumulator chains per wave, kind 1 FP64
+ * VALU fused multiply-adds in eight independent chains per lane; blocks of
+ * 256 threads, iters iterations each.  out: device buffer of at least
+ * 4 * blocks doubles (one value per wave, written so no chain is optimised
+ * away; caller-owned); *flops (host) receives the flops of the launch.
+ * Asynchronous on stream; the caller times it.  Bad kind, blocks outside
+ * 1..65536, iters outside 1..1e7 or a null pointer: EWALD_ERR_ARG. */
+ewald_status_t ewald_fp64_probe(int kind, int blocks, int iters, double* out, double* flops, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

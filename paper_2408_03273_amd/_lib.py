@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "EWALD_OK", -1: "EWALD_ERR_ARG", -2: "EWALD_ERR_CUTOFF", -3: 
 EXPORTED = ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_ctx_bytes", "ewald_forward", "ewald_backward",
             "ewald_moments_update", "ewald_suggest_params", "ewald_region_forward", "ewald_region_backward",
             "ewald_octupole_error", "ewald_batch", "ewald_autotune", "ewald_profile_report", "ewald_plan_describe", "ewald_last_error",
-            "ewald_version")
+            "ewald_version", "ewald_fp64_probe")
 
 
 class EwaldParams(ctypes.Structure):
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_last_error.restype = ctypes.c_char_p
     lib.ewald_version.argtypes = []
     lib.ewald_version.restype = ctypes.c_char_p
+    lib.ewald_fp64_probe.argtypes = [ip, ip, ip, vp, dp, vp]
+    lib.ewald_fp64_probe.restype = ip
     for name in ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_forward", "ewald_backward",
                  "ewald_moments_update", "ewald_suggest_params", "ewald_region_forward", "ewald_region_backward",
                  "ewald_octupole_error", "ewald_batch", "ewald_autotune", "ewald_profile_report"):

@@ -16,6 +16,10 @@
 #include "../../include/mpewald.h"
 #include "ewald_internal.h"
 
+namespace mpe {
+hipError_t launch_peak_probe(int kind, int blocks, int iters, double* out, hipStream_t s, double* flops);
+}
+
 using namespace mpe;
 
 namespace {
@@ -531,6 +535,19 @@ extern "C" {
 const char* ewald_last_error(void) { return g_last_error.c_str(); }
 
 const char* ewald_version(void) { return "mpewald 0.1 (gfx950)"; }
+
+ewald_status_t ewald_fp64_probe(int kind, int blocks, int iters, double* out, double* flops, void* stream) {
+  g_last_error.clear();
+  if (kind != 0 && kind != 1) return fail(EWALD_ERR_ARG, "probe kind must be 0 or 1");
+  if (blocks < 1 || blocks > 65536 || iters < 1 || iters > 10000000)
+    return fail(EWALD_ERR_ARG, "probe blocks must be in 1..65536 and iters in 1..1e7");
+  if (!out || !flops) return fail(EWALD_ERR_ARG, "null probe buffer");
+  double f = 0.0;
+  const hipError_t e = mpe::launch_peak_probe(kind, blocks, iters, out, (hipStream_t)stream, &f);
+  if (e != hipSuccess) return fail(EWALD_ERR_HIP, "probe launch: %s", hipGetErrorString(e));
+  *flops = f;
+  return EWALD_OK;
+}
 
 ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   g_last_error.clear();
