@@ -141,7 +141,11 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
  * ctx as filled by the matching forward call.
  * Outputs (overwritten): g_qm_xyz (Nq,3), g_Q (Nq), g_mu (Nq,3), g_theta (Nq,6),
  * g_mm_xyz (Nm,3), g_mm_q (Nm, may be null).  Each output is the gradient of
- * L = gE*E + g_phi.phi + g_efield.efield + g_efgrad.efgrad. */
+ * L = gE*E + g_phi.phi + g_efield.efield + g_efgrad.efgrad.
+ * With upstream gradients on E only, the gradients that the forward call
+ * stored in ctx are scaled by gE (one short kernel); after an
+ * ewald_moments_update call on the same ctx (new moments at the same
+ * geometry) the full adjoint runs instead, for the moments passed here. */
 ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz, const double* Q,
                               const double* mu, const double* theta, int n_mm, const double* mm_xyz,
                               const double* mm_q, const double* gE, const double* g_phi, const double* g_efield,
@@ -168,7 +172,9 @@ ewald_status_t ewald_suggest_params(const double box[3], double rcut, double tol
  * recomputed.  Outputs: energy (1, device), and, each may be null, g_Q (Nq),
  * g_mu (Nq,3), g_theta (Nq,6) = dE/d(moments) as in ewald_backward with gE = 1.
  * n_mm is the MM count of the forward call (it fixes the ctx layout).
- * Forces are not produced (positions are fixed). */
+ * Forces are not produced (positions are fixed); a later ewald_backward on
+ * this ctx computes them, and every other gradient, for the moments it is
+ * given (the plan remembers that the stored gradients no longer apply). */
 ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx, int n_qm, const double* qm_xyz,
                                     const double* Q, const double* mu, const double* theta, int n_mm,
                                     double* energy, double* g_Q, double* g_mu, double* g_theta, void* stream);

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/mpewald.h"
@@ -75,6 +76,10 @@ struct ewald_plan {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<std::string, std::pair<long, double>>> prof_acc;
   bool capturing = false;
+  // contexts whose stored gradients belong to other moments than the caller's
+  // latest ones (an ewald_moments_update call since their forward call):
+  // ewald_backward on them runs the full adjoint for the moments it is given
+  std::unordered_set<const void*> stale_ctx;
 };
 
 namespace {
@@ -758,6 +763,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
+  if (ctx) plan->stale_ctx.erase(ctx);
   if (ctx && !q.plain) {
     plan->t.kc = choose_kc(plan, n_mm);
     CtxView cv = ctx_view(plan->g, ctx, n_qm, n_mm);
@@ -829,7 +835,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
   CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
   Work& w = plan->w;
-  if (!g_phi && !g_efield && !g_efgrad && !(plan->p.flags & EWALD_PLAIN)) {
+  if (!g_phi && !g_efield && !g_efgrad && !(plan->p.flags & EWALD_PLAIN) && !plan->stale_ctx.count(ctx)) {
     // the forward call stored the gradients of E; L = gE E scales them
     hipError_t e;
     {
@@ -1117,6 +1123,8 @@ extern "C" ewald_status_t ewald_moments_update(ewald_plan* plan, const void* ctx
   Work& w = plan->w;
   const Grid& g = plan->g;
   ewald_plan* pl = plan;
+  // the gradients stored in ctx by the forward call are those of its moments
+  plan->stale_ctx.insert(ctx);
   st = seq_begin(q, qm_xyz, Q, mu, theta, nullptr, nullptr, 0, 1);
   if (st != EWALD_OK) return st;
   LCHK(launch_sfac_qm(g, q.fa, n_qm, Q, mu, theta, w.qeff, nullptr, 0, w, s));

@@ -2093,10 +2093,18 @@ hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap
 // MM atoms are binned into nc[0] x nc[1] x nc[2] cells of edge >= rcut (at
 // least 3 per axis), so all minimum-image partners within rcut of a point lie
 // in its cell and the 26 around it.  Counting sort: count, scan, fill.
+// Cell index along one axis of a wrapped coordinate, clamped to [0, n - 1]
+// at both ends before the conversion; a NaN coordinate (NaN input) lands in
+// cell 0, so no index ever leaves the cell arrays.
+DEV int cell_axis(double x, double inv_box, int n) {
+  const double c = x * inv_box * (double)n;
+  return c >= 0.0 ? (c < (double)(n - 1) ? (int)c : n - 1) : 0;
+}
+
 DEV int cell_of(double x, double y, double z, const FrameDev& fr) {
-  const int cx = min(fr.nc[0] - 1, (int)(x * fr.inv_box[0] * fr.nc[0]));
-  const int cy = min(fr.nc[1] - 1, (int)(y * fr.inv_box[1] * fr.nc[1]));
-  const int cz = min(fr.nc[2] - 1, (int)(z * fr.inv_box[2] * fr.nc[2]));
+  const int cx = cell_axis(x, fr.inv_box[0], fr.nc[0]);
+  const int cy = cell_axis(y, fr.inv_box[1], fr.nc[1]);
+  const int cz = cell_axis(z, fr.inv_box[2], fr.nc[2]);
   return (cx * fr.nc[1] + cy) * fr.nc[2] + cz;
 }
 
@@ -2212,9 +2220,9 @@ __global__ __launch_bounds__(256) void k_real_cells(Grid g, FrameArg fa, const d
   // neighbour cell of this block
   const int nb = blockIdx.y;
   const int dx = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dz = nb % 3 - 1;
-  const int cx = min(fr.nc[0] - 1, (int)(X * fr.inv_box[0] * fr.nc[0]));
-  const int cy = min(fr.nc[1] - 1, (int)(Y * fr.inv_box[1] * fr.nc[1]));
-  const int cz = min(fr.nc[2] - 1, (int)(Zc * fr.inv_box[2] * fr.nc[2]));
+  const int cx = cell_axis(X, fr.inv_box[0], fr.nc[0]);
+  const int cy = cell_axis(Y, fr.inv_box[1], fr.nc[1]);
+  const int cz = cell_axis(Zc, fr.inv_box[2], fr.nc[2]);
   const int c = (((cx + dx + fr.nc[0]) % fr.nc[0]) * fr.nc[1] + (cy + dy + fr.nc[1]) % fr.nc[1]) * fr.nc[2] +
                 (cz + dz + fr.nc[2]) % fr.nc[2];
   const int s0 = cell_start[fr.cell_base + c], s1 = cell_start[fr.cell_base + c + 1];

@@ -144,11 +144,23 @@ DEV bool in_region(const RegionArgs& ra, const double d[3], int nx, int ny, int 
   return x * x + y * y + z * z < ra.r_region * ra.r_region;
 }
 
-// Range of n with |c + n L| < R possible along one axis.
+// Range of n with |c + n L| < R possible along one axis (at most 2 R / L + 1
+// values: the radii are validated against the box on the host).  The bounds
+// are checked before the conversion to int: a NaN offset (NaN input) or one
+// beyond 2^30 box lengths gives an empty range, so no loop runs away.
 DEV void n_range(double c, double R, double L, int& lo, int& hi) {
-  lo = (int)ceil((-R - c) / L);
-  hi = (int)floor((R - c) / L);
+  const double a = ceil((-R - c) / L), b = floor((R - c) / L);
+  if (!(a >= -1073741824.0 && b <= 1073741824.0)) {
+    lo = 1;
+    hi = 0;
+    return;
+  }
+  lo = (int)a;
+  hi = (int)b;
 }
+
+// nearest lattice index of x (in box lengths), 0 for NaN or beyond 2^30
+DEV int nearest_n(double x) { return fabs(x) <= 1073741824.0 ? (int)rint(x) : 0; }
 
 // ------------------------------------------------------------------ preparation
 // Work arrays of one region call (RegionWork):
@@ -251,7 +263,7 @@ DEV void for_each_pair(const RegionArgs& ra, const double d[3], int f, double ka
   // r = s - (d + n L): |s_a - d_a - n L_a| < RG
   if (RG <= ra.half_min) {
     int n[3];
-    for (int a = 0; a < 3; a++) n[a] = (int)rint((s[a] - d[a]) * ra.inv_box[a]);
+    for (int a = 0; a < 3; a++) n[a] = nearest_n((s[a] - d[a]) * ra.inv_box[a]);
     const double x = s[0] - tr_coord(d[0], n[0], ra.box[0]);
     const double y = s[1] - tr_coord(d[1], n[1], ra.box[1]);
     const double z = s[2] - tr_coord(d[2], n[2], ra.box[2]);

@@ -39,3 +39,30 @@ def test_moments_update_matches_oracle(qmqm):
                    g_theta=gth.cpu().numpy())
         errs = H.compare(got, ref, ("energy", "g_Q", "g_mu", "g_theta"))
         assert max(errs.values()) <= 1e-10, (it, errs)
+
+
+def test_backward_after_moments_update():
+    """Forward, then a moments-only update with new moments, then the backward
+    pass with an upstream gradient on E only: every gradient is that of the
+    new moments (the gradients the forward call stored belong to the old ones)."""
+    s = wl.random_system(62, 9, 1800, box=(19.0, 21.0, 23.0), alpha=0.33, rcut=9.0, kmax=(7, 9, 11))
+    plan = H.make_plan(s)
+    dev = plan.device
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)  # noqa: E731
+    x = [t(a) for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+    _, _, _, _, ctx = plan.forward(*x, want_ctx=True)
+    Q, mu, th = _moments(np.random.default_rng(8), s.nq)
+    plan.update_moments(ctx, x[0], t(Q), t(mu), t(th), s.nm)
+    g = plan.backward(ctx, x[0], t(Q), t(mu), t(th), x[4], x[5])
+    torch.cuda.synchronize()
+    got = dict(zip(H.BWD_KEYS, (v.cpu().numpy() for v in g)))
+    s2 = wl.System(box=s.box, alpha=s.alpha, rcut=s.rcut, kmax=s.kmax, qm_pos=s.qm_pos, Q=Q, mu=mu, theta=th,
+                   mm_pos=s.mm_pos, q=s.q, name=f"{s.name}/scf")
+    errs = H.compare(got, H.oracle_outputs(s2), H.BWD_KEYS)
+    assert max(errs.values()) <= 1e-10, errs
+    # a new forward call on the same ctx makes the stored gradients current again
+    plan.forward(x[0], t(Q), t(mu), t(th), x[4], x[5], want_ctx=False)
+    _, _, _, _, ctx2 = plan.forward(x[0], t(Q), t(mu), t(th), x[4], x[5], want_ctx=True)
+    g2 = plan.backward(ctx2, x[0], t(Q), t(mu), t(th), x[4], x[5])
+    errs = H.compare(dict(zip(H.BWD_KEYS, (v.cpu().numpy() for v in g2))), H.oracle_outputs(s2), H.BWD_KEYS)
+    assert max(errs.values()) <= 1e-10, errs
