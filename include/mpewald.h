@@ -244,6 +244,23 @@ ewald_status_t ewald_octupole_error(ewald_plan* plan, int n_qm, const double* qm
                                     double r_step, double r_outer, double eps, double* err, double* r_cut,
                                     void* stream);
 
+/* Allocation-free variant of ewald_octupole_error, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): no plan; the box (3 orthorhombic edges,
+ * host array) is passed directly and every other argument is as in
+ * ewald_octupole_error.  The block partial sums of the estimate live in a
+ * fixed array of the library in device memory (8 MiB, one copy per GPU, kept
+ * until the process ends; its address is looked up on the first call on each
+ * device), so the call allocates nothing.  Limit: n_r * ceil(n_mm / 256) <=
+ * 1048576 (EWALD_ERR_CAPACITY beyond).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams, or host threads)
+ * race and must be ordered by the caller.  Each call writes every partial sum
+ * it reads, so nothing carries over from the previous call. */
+ewald_status_t ewald_octupole_error_noalloc(const double box[3], int n_qm, const double* qm_xyz, const double* omega,
+                                            int n_mm, const double* mm_xyz, const double* mm_q, int n_r,
+                                            double r_first, double r_step, double r_outer, double eps, double* err,
+                                            double* r_cut, void* stream);
+
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
  * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or

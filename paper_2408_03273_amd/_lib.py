@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "EWALD_OK", -1: "EWALD_ERR_ARG", -2: "EWALD_ERR_CUTOFF", -3: 
 EXPORTED = ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_ctx_bytes", "ewald_forward", "ewald_backward",
             "ewald_moments_update", "ewald_suggest_params", "ewald_region_forward", "ewald_region_backward",
             "ewald_octupole_error", "ewald_batch", "ewald_autotune", "ewald_profile_report", "ewald_plan_describe", "ewald_last_error",
-            "ewald_version", "ewald_fp64_probe")
+            "ewald_version", "ewald_fp64_probe", "ewald_octupole_error_noalloc")
 
 
 class EwaldParams(ctypes.Structure):
@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_region_backward.argtypes = [vp, ip, vp, vp, vp, vp, ip, vp, vp, vp, dd, dd, vp, vp, vp, vp, vp, vp, vp,
                                           vp, vp, vp, vp]
     lib.ewald_octupole_error.argtypes = [vp, ip, vp, vp, ip, vp, vp, ip, dd, dd, dd, dd, vp, vp, vp]
+    lib.ewald_octupole_error_noalloc.argtypes = [dp, ip, vp, vp, ip, vp, vp, ip, dd, dd, dd, dd,
+                                                 vp, vp, vp]
     lib.ewald_autotune.argtypes = [vp, ip, ctypes.c_char_p]
     lib.ewald_profile_report.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.ewald_plan_describe.argtypes = [vp]
@@ -94,7 +96,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ewald_fp64_probe.restype = ip
     for name in ("ewald_setup", "ewald_destroy", "ewald_set_box", "ewald_forward", "ewald_backward",
                  "ewald_moments_update", "ewald_suggest_params", "ewald_region_forward", "ewald_region_backward",
-                 "ewald_octupole_error", "ewald_batch", "ewald_autotune", "ewald_profile_report"):
+                 "ewald_octupole_error", "ewald_octupole_error_noalloc", "ewald_batch", "ewald_autotune",
+                 "ewald_profile_report"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpewald.so")
-SOURCES = ["kernels.hip", "region.hip", "recip32.hip", "peak.hip", "api.hip"]
+SOURCES = ["kernels.hip", "region.hip", "recip32.hip", "peak.hip", "api.hip", "noalloc.hip"]
 ARCH = os.environ.get("MPEWALD_ARCH", "gfx950")
 
 

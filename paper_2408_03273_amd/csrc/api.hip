@@ -1226,18 +1226,23 @@ extern "C" ewald_status_t ewald_region_backward(ewald_plan* plan, int n_qm, cons
   return EWALD_OK;
 }
 
-extern "C" ewald_status_t ewald_octupole_error(ewald_plan* plan, int n_qm, const double* qm_xyz,
-                                               const double* omega, int n_mm, const double* mm_xyz,
-                                               const double* mm_q, int n_r, double r_first, double r_step,
-                                               double r_outer, double eps, double* err, double* r_cut,
-                                               void* stream) {
-  g_last_error.clear();
-  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+namespace mpe {
+
+ewald_status_t set_error(ewald_status_t st, const char* msg) { return fail(st, "%s", msg); }
+
+void clear_error() { g_last_error.clear(); }
+
+// Host-side checks of the octupole estimate's arguments (shared by the plan
+// entry point and its allocation-free variant) and the kernel arguments.
+ewald_status_t octupole_args(const double box[3], int n_qm, const double* qm_xyz, const double* omega, int n_mm,
+                             const double* mm_xyz, const double* mm_q, int n_r, double r_first, double r_step,
+                             double r_outer, double eps, const double* err, OctArgs& oa) {
   if (n_qm < 0 || n_mm < 0) return fail(EWALD_ERR_ARG, "negative atom count");
   if (n_qm > 0 && (!qm_xyz || !omega)) return fail(EWALD_ERR_ARG, "null QM input array");
   if (n_mm > 0 && (!mm_xyz || !mm_q)) return fail(EWALD_ERR_ARG, "null MM input array");
   if (!err) return fail(EWALD_ERR_ARG, "null err output");
-  if (n_mm > plan->cap_mm) return fail(EWALD_ERR_CAPACITY, "n_mm=%d exceeds capacity %d", n_mm, plan->cap_mm);
+  for (int a = 0; a < 3; a++)
+    if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(EWALD_ERR_ARG, "box[%d] must be positive", a);
   if (n_r < 1 || n_r > kMaxOctCandidates)
     return fail(EWALD_ERR_ARG, "n_r=%d outside [1, %d]", n_r, kMaxOctCandidates);
   const double r_last = r_first + (double)(n_r - 1) * r_step;
@@ -1245,22 +1250,38 @@ extern "C" ewald_status_t ewald_octupole_error(ewald_plan* plan, int n_qm, const
       r_first < 0.0 || r_step < 0.0 || (n_r > 1 && r_step == 0.0) || r_outer < 0.0 || !(eps > 0.0) ||
       !std::isfinite(eps))
     return fail(EWALD_ERR_ARG, "bad candidates r_first=%g r_step=%g r_outer=%g eps=%g", r_first, r_step, r_outer, eps);
-  const double lmin = std::min(plan->p.box[0], std::min(plan->p.box[1], plan->p.box[2]));
+  const double lmin = std::min(box[0], std::min(box[1], box[2]));
   if (r_outer > kMaxRegionBoxes * lmin)
     return fail(EWALD_ERR_CUTOFF, "r_outer=%g above %g box lengths (%g)", r_outer, kMaxRegionBoxes,
                 kMaxRegionBoxes * lmin);
-  OctArgs oa;
   oa.nq = n_qm;
   oa.nm = n_mm;
   oa.qm_xyz = qm_xyz;
   oa.omega = omega;
   oa.mm_xyz = mm_xyz;
   oa.mm_q = mm_q;
-  for (int a = 0; a < 3; a++) oa.box[a] = plan->p.box[a];
+  for (int a = 0; a < 3; a++) oa.box[a] = box[a];
   oa.r_first = r_first;
   oa.r_step = r_step;
   oa.r_outer = r_outer;
   oa.n_r = n_r;
+  return EWALD_OK;
+}
+
+}  // namespace mpe
+
+extern "C" ewald_status_t ewald_octupole_error(ewald_plan* plan, int n_qm, const double* qm_xyz,
+                                               const double* omega, int n_mm, const double* mm_xyz,
+                                               const double* mm_q, int n_r, double r_first, double r_step,
+                                               double r_outer, double eps, double* err, double* r_cut,
+                                               void* stream) {
+  g_last_error.clear();
+  if (!plan) return fail(EWALD_ERR_ARG, "null plan");
+  if (n_mm > plan->cap_mm) return fail(EWALD_ERR_CAPACITY, "n_mm=%d exceeds capacity %d", n_mm, plan->cap_mm);
+  OctArgs oa;
+  const ewald_status_t st = octupole_args(plan->p.box, n_qm, qm_xyz, omega, n_mm, mm_xyz, mm_q, n_r, r_first, r_step,
+                                          r_outer, eps, err, oa);
+  if (st != EWALD_OK) return st;
   ewald_plan* pl = plan;
   hipStream_t s = (hipStream_t)stream;
   LCHK_P(pl, s, "launch_octupole", launch_octupole(oa, plan->w.oct_part, eps, err, r_cut, s));

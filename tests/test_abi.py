@@ -92,3 +92,20 @@ def test_no_cpu_fallback_in_product_path():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         Plan(EwaldConfig(box=(20, 20, 20), alpha=0.3, rcut=9, kmax=8, max_qm=1, max_mm=1))
+
+
+def test_noalloc_octupole_host_checks():
+    """The allocation-free octupole estimate validates on the host before any
+    device call: a null box, bad candidates and more partial sums than its
+    fixed device array holds are refused (the pointers are never read)."""
+    lib = _lib.load()
+    box = (ctypes.c_double * 3)(20.0, 20.0, 20.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.ewald_octupole_error_noalloc(None, 2, fake, fake, 10, fake, fake, 4, 1.0, 1.0, 9.0, 1e-3, fake, None,
+                                            None) == _lib.EWALD_ERR_ARG
+    assert lib.ewald_octupole_error_noalloc(box, 2, fake, fake, 10, fake, fake, 0, 1.0, 1.0, 9.0, 1e-3, fake, None,
+                                            None) == _lib.EWALD_ERR_ARG
+    assert lib.ewald_octupole_error_noalloc(box, 2, fake, fake, 10, fake, fake, 4, 1.0, 1.0, 90.0, 1e-3, fake, None,
+                                            None) == _lib.EWALD_ERR_CUTOFF
+    assert lib.ewald_octupole_error_noalloc(box, 2, fake, fake, 1100000, fake, fake, 256, 1.0, 0.1, 30.0, 1e-3, fake,
+                                            None, None) == _lib.EWALD_ERR_CAPACITY
