@@ -36,8 +36,13 @@ def ref(sys_, mm_sel):
 
 
 def main():
+    # c3 and the first c4 frames with larger MM samples; every other c4 frame
+    # (each has its own size, box and packed offset in the batch) and the
+    # middle and last c5 replicas with smaller ones
     jobs = [("c3_f0", 3, 0, 1500), ("c4_f0", 4, 0, 600), ("c4_f1", 4, 1, 600), ("c4_f2", 4, 2, 600),
             ("c5_f0", 5, 0, 400)]
+    jobs += [(f"c4_f{f}", 4, f, 200) for f in range(3, 64)]
+    jobs += [("c5_f7", 5, 7, 200), ("c5_f15", 5, 15, 200)]
     only = sys.argv[1:]
     for name, cfg, frame, nsel in jobs:
         if only and name not in only:

@@ -1,8 +1,9 @@
 """Full-size workloads against stored oracle values (tests/golden/oracle_*.json,
 written by tests/golden/make_golden.py from the CPU oracle only): c3 as one
-frame through autograd, c4 and c5 through the batched path exactly as the
-benchmark runs them; QM outputs compared in full, MM gradients on the stored
-sample of rows."""
+frame through autograd, c4 (all 64 frames) and c5 (replicas 0, 7, 15) through
+the batched path exactly as the benchmark runs them; QM outputs compared in
+full, MM gradients on the stored sample of rows; every batch frame also in
+full against a single-frame call."""
 import json
 import os
 
@@ -61,7 +62,15 @@ def test_c3_autograd_full_size(tuned, tmp_path):
     _check(got, g, "c3")
 
 
-def _batch_config(cfg, nframes, check, tune=False):
+def _single_frame_outputs(f):
+    """One frame through ewald_forward / ewald_backward on a plan of its own size."""
+    plan = Plan(EwaldConfig(box=tuple(f.box), alpha=f.alpha, rcut=f.rcut, kmax=f.kmax, max_qm=f.nq, max_mm=f.nm))
+    out = H.gpu_outputs(f, plan=plan)
+    plan.close()
+    return out
+
+
+def _batch_config(cfg, nframes, check, tune=False, single=()):
     frames = [wl.make_config(cfg, f) for f in range(nframes)]
     qoff = np.cumsum([0] + [f.nq for f in frames])
     moff = np.cumsum([0] + [f.nm for f in frames])
@@ -81,20 +90,40 @@ def _batch_config(cfg, nframes, check, tune=False):
     out = plan.batch(desc, *x, out=out)   # second call replays the graph
     torch.cuda.synchronize()
     o = {k: v.cpu().numpy() for k, v in out.items()}
+
+    def frame_out(i):
+        sq, sm = slice(qoff[i], qoff[i + 1]), slice(moff[i], moff[i + 1])
+        return dict(energy=o["energy"][i], phi=o["phi"][sq], efield=o["efield"][sq], efgrad=o["efgrad"][sq],
+                    g_qm_pos=o["g_qm_pos"][sq], g_Q=o["g_Q"][sq], g_mu=o["g_mu"][sq], g_theta=o["g_theta"][sq],
+                    g_mm_pos=o["g_mm_pos"][sm], g_mm_q=o["g_mm_q"][sm])
+
     for i in check:
         g = _golden(f"c{cfg}_f{i}")
         assert frames[i].sha256() == g["input_sha256"], "generator output changed"
-        sq, sm = slice(qoff[i], qoff[i + 1]), slice(moff[i], moff[i + 1])
-        got = dict(energy=o["energy"][i], phi=o["phi"][sq], efield=o["efield"][sq], efgrad=o["efgrad"][sq],
-                   g_qm_pos=o["g_qm_pos"][sq], g_Q=o["g_Q"][sq], g_mu=o["g_mu"][sq], g_theta=o["g_theta"][sq],
-                   g_mm_pos=o["g_mm_pos"][sm], g_mm_q=o["g_mm_q"][sm])
-        _check(got, g, f"c{cfg}_f{i}")
+        _check(frame_out(i), g, f"c{cfg}_f{i}")
+    # every output row of the frames in `single` against a single-frame call
+    # of the same frame (each frame of a batch has its own size, box, packed
+    # offsets and partial-sum slots; the single-frame path meets the oracle
+    # bar on its own tests)
+    worst = 0.0
+    for i in single:
+        errs = H.compare(frame_out(i), _single_frame_outputs(frames[i]), H.FWD_KEYS + H.BWD_KEYS)
+        worst = max(worst, max(errs.values()))
+        assert max(errs.values()) <= 1e-12, (i, errs)
+    if single:
+        print(f"[large] c{cfg}: {len(single)} frames in full against single-frame calls, worst {worst:.2e}",
+              flush=True)
 
 
 def test_c4_batch_64_frames():
-    _batch_config(4, 64, check=(0, 1, 2))
+    """All 64 uneven frames against the oracle (every QM output, a sample of
+    MM rows per frame) and in full against single-frame calls."""
+    _batch_config(4, 64, check=range(64), single=range(64))
 
 
 @pytest.mark.parametrize("tune", [False, True])
 def test_c5_batch_16_replicas(tune):
-    _batch_config(5, 16, check=(0,), tune=tune)
+    """Replicas 0, 7 and 15 (first, middle, last packed offsets) against the
+    oracle; with the tuned plan every replica in full against a single-frame
+    call."""
+    _batch_config(5, 16, check=(0, 7, 15), tune=tune, single=range(16) if tune else ())
