@@ -40,7 +40,8 @@
  *    P = Qa Qb psi0 + (Qb mu_a - Qa mu_b).psi1 + (Qb th_a + Qa th_b):psi2
  *        - 2 mu_a.psi2.mu_b.
  *  - A uniform neutralising background is included for charged subsystems:
- *    -(pi/(2 a^2 V)) Qtot^2 (QM-QM) and -(pi/(a^2 V)) Qtot qtot (QM-MM).
+ *    -(pi/(2 a^2 V)) Qtot^2 (QM-QM) and -(pi/(a^2 V)) Qtot qtot (QM-MM)
+ *    (the paper is silent; params.background = 0 leaves both out).
  *  - k-set: every n with |n_x|<=mx, |n_y|<=my, |n_z|<=mz, n != 0, taken as
  *    the half-space nx>0 | (nx=0 & ny>0) | (nx=ny=0 & nz>0) with weight 2.
  *  - Real space: every lattice image with |r| < rcut (strict), all images.
@@ -68,7 +69,8 @@ typedef struct {
   double alpha;
   double rcut;
   int kmax[3];
-  int qmqm; /* include the QM-QM image terms */
+  int qmqm;       /* include the QM-QM image terms */
+  int background; /* include the uniform neutralising background terms */
 } oracle_params_t;
 
 enum {
@@ -569,7 +571,7 @@ int oracle_ewald(const oracle_params_t* P, int nq, const double* qm_pos, const d
   }
 
   /* ---------- 4. Self terms and neutralising background ---------- */
-  const double bgc = -PI / (al * al * V);
+  const double bgc = P->background ? -PI / (al * al * V) : 0.0;
   if (P->qmqm) {
     long double es = 0;
     for (int j = 0; j < nq; j++) {
@@ -640,6 +642,16 @@ int oracle_ewald(const oracle_params_t* P, int nq, const double* qm_pos, const d
   free(gk);
   free(kv);
   return 0;
+}
+
+/* OpenMP threads of later calls (timing only; no effect on the arithmetic's
+ * definition, though the order of the per-thread partial sums follows it) */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 int oracle_num_threads(void) {

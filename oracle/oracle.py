@@ -37,6 +37,7 @@ class _Params(ctypes.Structure):
         ("rcut", ctypes.c_double),
         ("kmax", ctypes.c_int * 3),
         ("qmqm", ctypes.c_int),
+        ("background", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,8 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     lib.oracle_ewald.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp,
                                  dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp, dp]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     lib.oracle_region.restype = ctypes.c_int
     lib.oracle_octupole_error.restype = ctypes.c_int
     lib.oracle_octupole_error.argtypes = [dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp,
@@ -80,6 +83,11 @@ def load(path: str = _LIB) -> ctypes.CDLL:
 
 def num_threads() -> int:
     return int(load().oracle_num_threads())
+
+
+def set_num_threads(n: int, lib_path: str | None = None) -> None:
+    """OpenMP threads of later oracle calls (for timing)."""
+    (load(lib_path) if lib_path else load()).oracle_set_num_threads(int(n))
 
 
 @dataclass
@@ -122,12 +130,14 @@ def _ptr(a):
 
 
 def oracle_ewald(box, alpha, rcut, kmax, qm_pos, Q, mu, theta, mm_pos, q, qmqm=True, mm_sel=None,
-                 lib_path: str | None = None) -> OracleResult:
+                 lib_path: str | None = None, background=True) -> OracleResult:
     """Evaluate the truncated Ewald sums for the given parameters.
 
     box: (3,) orthorhombic edges; kmax: int or (3,) per-axis |n| limit;
     qm_pos (nq,3), Q (nq,), mu (nq,3), theta (nq,6); mm_pos (nm,3), q (nm,).
     mm_sel: optional indices of MM atoms whose gradients are wanted.
+    background: include the uniform neutralising background of charged
+    subsystems (the paper is silent on it; on by default).
     """
     lib = load(lib_path) if lib_path else load()
     qm_pos = _c(qm_pos).reshape(-1, 3)
@@ -146,6 +156,7 @@ def oracle_ewald(box, alpha, rcut, kmax, qm_pos, Q, mu, theta, mm_pos, q, qmqm=T
     p.rcut = float(rcut)
     p.kmax[:] = [int(k) for k in kmax]
     p.qmqm = 1 if qmqm else 0
+    p.background = 1 if background else 0
     if mm_sel is None:
         nsel = nm
         sel_arg = None

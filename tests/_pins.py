@@ -236,6 +236,30 @@ def invariants(lib=None):
     return max(e1, e2, e3, e4)
 
 
+def background_switch(lib=None):
+    """Charged QM and MM subsystems with and without the uniform neutralising
+    background: the energy differs by -(pi/(2 a^2 V)) Qtot^2 - (pi/(a^2 V))
+    Qtot qtot, every QM potential by -(pi/(a^2 V)) qtot, dE/dQ_j by
+    -(pi/(a^2 V)) (Qtot + qtot), dE/dq_i by -(pi/(a^2 V)) Qtot, and no force
+    changes (a uniform background exerts none)."""
+    L, qm, Q, mu, th, mm, q = fd_system()
+    Q = Q + 0.37   # net charges of both subsystems
+    q = q - 0.21
+    a = 0.4
+    args = ([L] * 3, a, 7.0, 10)
+    on = oracle_ewald(*args, qm, Q, mu, th, mm, q, lib_path=lib)
+    off = oracle_ewald(*args, qm, Q, mu, th, mm, q, lib_path=lib, background=False)
+    c = -np.pi / (a * a * L ** 3)
+    Qt, qt = float(Q.sum()), float(q.sum())
+    e1 = abs((on.E - off.E) - (0.5 * c * Qt * Qt + c * Qt * qt)) / abs(on.E)
+    e2 = relerr(on.phi - off.phi, np.full(len(Q), c * qt))
+    e3 = relerr(on.g_Q - off.g_Q, np.full(len(Q), c * (Qt + qt)))
+    e4 = relerr(on.g_mm_q - off.g_mm_q, np.full(len(q), c * Qt))
+    e5 = max(float(np.max(np.abs(on.g_qm_pos - off.g_qm_pos))), float(np.max(np.abs(on.g_mm_pos - off.g_mm_pos)))) \
+        / float(np.max(np.abs(on.g_mm_pos)))
+    return max(e1, e2, e3, e4, e5)
+
+
 ALL_PINS = {
     "nacl_potential": (nacl_potential, 1e-9),
     "cscl_energy": (cscl_energy, 1e-9),
@@ -246,4 +270,5 @@ ALL_PINS = {
     "fd_positions": (fd_positions, 1e-8),
     "fd_moments": (fd_moments, 1e-8),
     "invariants": (invariants, 1e-11),
+    "background_switch": (background_switch, 1e-11),
 }

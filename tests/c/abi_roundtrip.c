@@ -22,6 +22,7 @@ typedef struct {
   double rcut;
   int kmax[3];
   int qmqm;
+  int background;
 } oracle_params_t;
 typedef struct {
   double box[3];
@@ -156,6 +157,7 @@ int main(void) {
   op.rcut = p.rcut;
   for (int a = 0; a < 3; a++) op.kmax[a] = p.kmax[a];
   op.qmqm = 1;
+  op.background = 1;
   static double oE[8], ophi[NQ], odphi[3 * NQ], ohphi[6 * NQ], ogq[3 * NQ], ogQ[NQ], ogmu[3 * NQ], ogth[6 * NQ],
       ogm[3 * NM], ogmq[NM], oef[3 * NQ], oeg[6 * NQ];
   if (oracle_ewald(&op, NQ, qm, Q, mu, th, NM, mm, q, oE, ophi, odphi, ohphi, ogq, ogQ, ogmu, ogth, -1, NULL, ogm,

@@ -23,7 +23,7 @@ MUTANTS = [
     ("dipole-dipole pair sign", "Pv -= 2.0 * ma[c] * p2[c][d] * mb[d];", "Pv += 2.0 * ma[c] * p2[c][d] * mb[d];", 0),
     ("charge-dipole operands swapped", "Pv += (Qb * ma[c] - Qa * mb[c]) * p1[c];", "Pv += (Qa * ma[c] - Qb * mb[c]) * p1[c];", 0),
     ("charge-quadrupole pair half", "Pv += (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", "Pv += 0.5 * (Qb * tha[c][d] + Qa * thb[c][d]) * p2[c][d];", 0),
-    ("background factor", "const double bgc = -PI / (al * al * V);", "const double bgc = -PI / (2.0 * al * al * V);"),
+    ("background factor", "P->background ? -PI / (al * al * V) : 0.0;", "P->background ? -PI / (2.0 * al * al * V) : 0.0;"),
     ("f5 coefficient", "f[2] = (f[1] + 4.0 / 3.0 * kappa", "f[2] = (f[1] + 2.0 / 3.0 * kappa"),
     ("f7 coefficient", "f[3] = (f[2] + 8.0 / 15.0 * pow(kappa, 5)", "f[3] = (f[2] + 4.0 / 15.0 * pow(kappa, 5)"),
     ("half in order-2 real tensor", "p2[a][b] = 0.5 * (3.0 * r[a] * r[b] * f[2]", "p2[a][b] = (3.0 * r[a] * r[b] * f[2]"),
