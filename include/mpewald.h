@@ -85,8 +85,19 @@ enum {
   EWALD_CELL_LIST = 4,     /* real space visits only neighbouring cells */
   EWALD_PROFILE = 8,       /* time every kernel launch with events on its stream
                               (single-frame calls only; read with ewald_profile_report) */
-  EWALD_PROFILE_HOT = 16   /* as EWALD_PROFILE, but only the two reciprocal-space
+  EWALD_PROFILE_HOT = 16,  /* as EWALD_PROFILE, but only the two reciprocal-space
                               hot loops (sfac_mm, force_mm): two events per launch */
+  EWALD_NO_BACKGROUND = 32, /* leave out the uniform neutralising background of charged
+                              subsystems, -(pi/(2 a^2 V)) Qtot^2 and -(pi/(a^2 V)) Qtot qtot,
+                              which is included by default (the paper is silent on it;
+                              neutral systems are unaffected) */
+  EWALD_DETERMINISTIC = 64  /* bitwise reproducible results: every cross-block sum is
+                              taken in a fixed order (per-block partial sums and a
+                              fixed-order reduction) instead of with floating-point
+                              atomics, and real space runs over all pairs (the cell
+                              fill orders atoms with atomics).  Repeated calls with
+                              the same plan, tiles and inputs return identical bytes;
+                              the default mode differs from it by rounding only */
 };
 
 typedef struct {
@@ -95,7 +106,8 @@ typedef struct {
   double rcut;     /* real-space cutoff: pairs and lattice images with |r| < rcut */
   int kmax[3];     /* reciprocal cube |n_a| <= kmax[a], each >= 1 */
   int precision;   /* EWALD_FP64, or EWALD_FP32_REAL and/or EWALD_FP32_RECIP */
-  int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT */
+  int flags;       /* EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT |
+                      EWALD_NO_BACKGROUND | EWALD_DETERMINISTIC */
   int max_qm;      /* capacity: QM sites per call (sum over frames in a batch) */
   int max_mm;      /* capacity: MM charges per call (sum over frames in a batch) */
   int max_frames;  /* capacity: frames per ewald_batch call (>= 1) */

@@ -23,6 +23,8 @@ EWALD_PLAIN = 2
 EWALD_CELL_LIST = 4
 EWALD_PROFILE = 8
 EWALD_PROFILE_HOT = 16
+EWALD_NO_BACKGROUND = 32
+EWALD_DETERMINISTIC = 64
 
 EWALD_FWD = 0
 EWALD_FWD_BWD = 1

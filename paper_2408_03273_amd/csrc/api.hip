@@ -165,6 +165,7 @@ Grid make_grid(const ewald_params_t& p) {
   g.NK2 = 2 * ((g.mz + 3) / 4);
   g.alpha = p.alpha;
   g.rcut = p.rcut;
+  g.bgw = (p.flags & EWALD_NO_BACKGROUND) ? 0.0 : 1.0;
   return g;
 }
 
@@ -266,7 +267,8 @@ FrameDev make_frame(const double box[3], int nq, int nm, int qoff, int moff, int
 // every frame has at least 3 cells per axis, else real space runs over all
 // pairs.  Returns whether the cell list is used and fills nc/cell_base.
 bool assign_cells(const ewald_plan* pl, FrameDev* frames, int n) {
-  bool ok = (pl->p.flags & EWALD_CELL_LIST) != 0;
+  // (the cell fill orders atoms with atomics: deterministic plans sum over all pairs)
+  bool ok = (pl->p.flags & EWALD_CELL_LIST) != 0 && !(pl->p.flags & EWALD_DETERMINISTIC);
   // Building the list costs a few kernel launches; over all pairs, real space
   // costs one distance test per (QM site, MM atom).  Use cells only when that
   // product is large, unless MPEWALD_CELLS forces the choice.
@@ -566,7 +568,8 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   if (st != EWALD_OK) return st;
   if (p.precision < 0 || p.precision > (EWALD_FP32_REAL | EWALD_FP32_RECIP))
     return fail(EWALD_ERR_ARG, "unknown precision %d", p.precision);
-  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT))
+  if (p.flags & ~(EWALD_QMQM | EWALD_PLAIN | EWALD_CELL_LIST | EWALD_PROFILE | EWALD_PROFILE_HOT |
+                  EWALD_NO_BACKGROUND | EWALD_DETERMINISTIC))
     return fail(EWALD_ERR_ARG, "unknown flags");
   if (p.max_qm < 0 || p.max_mm < 0 || p.max_frames < 1) return fail(EWALD_ERR_ARG, "bad capacities");
   ewald_plan* pl = new ewald_plan();
@@ -682,6 +685,15 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   A(w.region_rf, cm);
   A(w.region_part, cq * kRegionMaxChunks * kRegionNV);
   A(w.oct_part, (size_t)kMaxOctCandidates * ((cm + 255) / 256));
+  if (p.flags & EWALD_DETERMINISTIC) {
+    const size_t nb_pos = (std::max(cm, cq) + 255) / 256;
+    A(w.det_frame, cf * nb_pos * 3);
+    A(w.det_eff, cf * ((cq + 255) / 256));
+    A(w.det_smm, cf * (((size_t)g.KF + 255) / 256) * 2);
+    A(w.det_proj, cq * kDetPc * 26);
+    A(w.det_real, cq * kDetChunks * 13);
+    A(w.det_qq, cq);
+  }
   if (pl->t.fp32r) {
     A(w.mm_xy32, cm * g.NXY);
     A(w.mm_ztab32, cm * g.ZKP);

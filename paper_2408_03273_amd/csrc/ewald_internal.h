@@ -48,6 +48,7 @@ struct Grid {
   int NT;           // ZKP/16: 16-wide z tiles of the matrix-core forward kernel
   int NK2;          // K steps of 4 of the matrix-core adjoint kernel: 2*ceil(mz/4) (even, zero padded)
   double alpha, rcut;
+  double bgw;       // 1: uniform neutralising background terms included, 0: left out
 };
 
 // QM accumulator slots (doubles per QM row, zeroed at the start of each call).
@@ -122,7 +123,20 @@ struct Work {
   float2* mm_xy32;    // [cap_mm][NXY]
   float* mm_ztab32;   // [cap_mm][ZKP]
   float* wfrag32;     // [cap_frames][NG][NK2][4][64]
+  // deterministic mode only (null otherwise): per-block partial sums, added
+  // in a fixed order by k_det_reduce instead of floating-point atomics
+  double* det_frame;  // [cap_frames][ceil(max(cap_mm, cap_qm) / 256)][3] charge sums of k_prep_pos
+  double* det_eff;    // [cap_frames][ceil(cap_qm / 256)]              effective charge sums
+  double* det_smm;    // [cap_frames][ceil(KF / 256)][2]                long-range energies
+  double* det_proj;   // [cap_qm][kDetPc][26]                          QM-site projection sums
+  double* det_real;   // [cap_qm][kDetChunks][13]                      real-space QM-side sums
+  double* det_qq;     // [cap_qm]                                       QM-QM site energies
 };
+
+// deterministic mode: at most this many projection blocks per QM site and
+// real-space MM chunks per QM site
+static constexpr int kDetPc = 32;
+static constexpr int kDetChunks = 64;
 
 static constexpr int kMaxCellsPerAxis = 16;
 
@@ -164,6 +178,13 @@ inline int fwd_col_groups(const Grid& g, const Tuning& t) {
 // ---------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error; all are asynchronous.
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+// destination slots of a fixed-order sum (deterministic mode)
+struct DetMap {
+  int n;
+  int off[32];
+};
+hipError_t launch_det_reduce(const FrameArg& fa, int mode, int rows, const double* src, int nb, int stride,
+                             const DetMap& map, double* dst, int dst_stride, hipStream_t s);
 // wrap positions, clear the QM accumulators, sum the charges, build the phase
 // tables (mm_tables: 0 none, 1 x/y complex and real z tables, 2 also complex z);
 // unit_eff also sets the effective moments for an upstream gradient of 1 and

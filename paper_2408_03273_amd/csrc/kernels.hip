@@ -10,6 +10,8 @@
 // Flat index k = col*NZ + (nz+mz), col = nx*NY + (ny+my).
 #include <math.h>
 
+#include <initializer_list>
+
 #include "ewald_internal.h"
 
 namespace mpe {
@@ -100,6 +102,59 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ fixed-order sums (deterministic mode)
+// dst[row * dst_stride + map.off[t]] += sum over b of src[...] in the order of b:
+//   mode 0: row = frame f, src[(f * nb + b) * stride + t], b < nb;
+//   mode 1: row = packed QM row r = qoff + j of each site j of each frame,
+//           src[(r * nb + b) * stride + t], b < nb;
+//   mode 2: row = frame f, src[(qoff + b) * stride + t], b < nq (the frame's QM rows).
+__global__ __launch_bounds__(64) void k_det_reduce(FrameArg fa, int mode, const double* __restrict__ src, int nb,
+                                                   int stride, DetMap map, double* __restrict__ dst,
+                                                   int dst_stride) {
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  const int t = threadIdx.x;
+  if (t >= map.n) return;
+  size_t row, base;
+  int count = nb, step = stride;
+  if (mode == 1) {
+    const int j = blockIdx.x;
+    if (j >= fr.nq) return;
+    row = (size_t)(fr.qoff + j);
+    base = row * nb * stride;
+  } else if (mode == 2) {
+    row = (size_t)f;
+    base = (size_t)fr.qoff * stride;
+    count = fr.nq;
+  } else {
+    row = (size_t)f;
+    base = (size_t)f * nb * stride;
+  }
+  double sum = 0.0;
+  for (int b = 0; b < count; b++) sum += src[base + (size_t)b * step + t];
+  dst[row * dst_stride + map.off[t]] += sum;
+}
+
+hipError_t launch_det_reduce(const FrameArg& fa, int mode, int rows, const double* src, int nb, int stride,
+                             const DetMap& map, double* dst, int dst_stride, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_det_reduce, dim3(mode == 1 ? rows : 1, fa.n_frames), dim3(64), 0, s, fa, mode, src, nb,
+                     stride, map, dst, dst_stride);
+  return hipGetLastError();
+}
+
+static DetMap det_map(std::initializer_list<int> offs) {
+  DetMap m{};
+  m.n = 0;
+  for (int o : offs) m.off[m.n++] = o;
+  return m;
+}
+
+static DetMap det_range(DetMap m, int first, int count) {
+  for (int t = 0; t < count; t++) m.off[m.n++] = first + t;
+  return m;
+}
+
 // ------------------------------------------------------------------ preparation
 // Wrap positions into the cell, store them SoA with the charges, and sum the
 // charges of each subsystem of the frame.
@@ -109,7 +164,8 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
                                                   const double* __restrict__ theta, double* __restrict__ qm4,
                                                   int cap_qm, double* __restrict__ mm4, int cap_mm,
                                                   double* __restrict__ qacc, double* __restrict__ qeff, int unit_eff,
-                                                  double* __restrict__ facc, double* __restrict__ rpart) {
+                                                  double* __restrict__ facc, double* __restrict__ rpart,
+                                                  double* __restrict__ det) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -140,10 +196,18 @@ __global__ __launch_bounds__(256) void k_prep_pos(FrameArg fa, const double* __r
   }
   double tot[2];
   block_sum256<2>(v, tot);
-  if (threadIdx.x == 0 && blockIdx.x * 256 < max(fr.nm, fr.nq)) {
-    atomicAdd(&facc[f * FA_COUNT + FA_QTOT_MM], tot[0]);
-    atomicAdd(&facc[f * FA_COUNT + FA_QTOT_QM], tot[1]);
-    if (unit_eff) atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[1]);
+  if (threadIdx.x == 0) {
+    if (det) {
+      // every block writes its partial sums (zero past the frame's atoms)
+      double* o = det + ((size_t)f * gridDim.x + blockIdx.x) * 3;
+      o[0] = tot[0];
+      o[1] = tot[1];
+      o[2] = unit_eff ? tot[1] : 0.0;
+    } else if (blockIdx.x * 256 < max(fr.nm, fr.nq)) {
+      atomicAdd(&facc[f * FA_COUNT + FA_QTOT_MM], tot[0]);
+      atomicAdd(&facc[f * FA_COUNT + FA_QTOT_QM], tot[1]);
+      if (unit_eff) atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[1]);
+    }
   }
 }
 
@@ -930,7 +994,8 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
                                                     const double2* __restrict__ spart,
                                                     const double2* __restrict__ sabc,
                                                     const double* __restrict__ kw, double2* __restrict__ smm,
-                                                    size_t smm_stride, double* __restrict__ facc) {
+                                                    size_t smm_stride, double* __restrict__ facc,
+                                                    double* __restrict__ det) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int k = blockIdx.x * 256 + threadIdx.x;
@@ -976,8 +1041,14 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
   double tot[2];
   block_sum256<2>(v, tot);
   if (threadIdx.x == 0) {
-    atomicAdd(&facc[f * FA_COUNT + FA_E_QMMM_LR], tot[0]);
-    atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_LR], tot[1]);
+    if (det) {
+      double* o = det + ((size_t)f * gridDim.x + blockIdx.x) * 2;
+      o[0] = tot[0];
+      o[1] = tot[1];
+    } else {
+      atomicAdd(&facc[f * FA_COUNT + FA_E_QMMM_LR], tot[0]);
+      atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_LR], tot[1]);
+    }
   }
 }
 
@@ -986,8 +1057,11 @@ hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa,
   dim3 grid((g.KF + 255) / 256, fa.n_frames);
   const int kmajor = !plain && t.fwd_mode == 1;
   hipLaunchKernelGGL(k_reduce_smm, grid, dim3(256), 0, s, g, fa, t.a_chunk, plain, kmajor, w.spart, w.sabc, w.kw,
-                     smm_out, smm_frame_stride, w.facc);
-  return hipGetLastError();
+                     smm_out, smm_frame_stride, w.facc, w.det_smm);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !w.det_smm) return e;
+  return launch_det_reduce(fa, 0, 1, w.det_smm, (int)grid.x, 2, det_map({FA_E_QMMM_LR, FA_E_QQ_LR}), w.facc,
+                           FA_COUNT, s);
 }
 
 // ------------------------------------------------------------------ QM-site projection
@@ -1003,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
                                                     const double2* __restrict__ qtab,
                                                     const double2* __restrict__ sabc,
                                                     const double* __restrict__ kw, int qmqm,
-                                                    double* __restrict__ qacc) {
+                                                    double* __restrict__ qacc, double* __restrict__ det) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   // S sites per block: the per-k data (weight, S_MM, A/B/C) is loaded once per
@@ -1145,7 +1219,11 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
     if (u >= ns) break;  // uniform
     double tot[NV];
     block_sum256<NV>(acc[u], tot);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && det) {
+      // partial sums of this block, summed over the blocks in order afterwards
+      double* o = det + ((size_t)(fr.qoff + j0 + u) * n_pc + blockIdx.y) * 26;
+      for (int t = 0; t < NV; t++) o[t] = tot[t];
+    } else if (threadIdx.x == 0) {
       double* qa = qacc + (size_t)(fr.qoff + j0 + u) * QA_STRIDE;
       if (BWD != 1) {
         atomicAdd(&qa[QA_PHI_LR], tot[0]);
@@ -1176,11 +1254,12 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
   int n_pc = (640 + site_blocks - 1) / (site_blocks > 0 ? site_blocks : 1);
   const int kblocks = (g.NCOL * (g.mz + 1) + 255) / 256;
   if (n_pc > kblocks) n_pc = kblocks;
+  if (w.det_proj && n_pc > kDetPc) n_pc = kDetPc;
   if (n_pc < 1) n_pc = 1;
   dim3 grid((max_nq + S - 1) / S, n_pc, fa.n_frames);
 #define PQ(B)                                                                                                  \
   hipLaunchKernelGGL((k_project_qm<B, S>), grid, dim3(256), 0, s, g, fa, n_pc, smm, smm_frame_stride, Q, mu, \
-                     theta, w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc)
+                     theta, w.qeff, w.qm_tab, w.sabc, w.kw, qmqm, w.qacc, w.det_proj)
   if (backward == 2)
     PQ(2);
   else if (backward)
@@ -1188,7 +1267,13 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
   else
     PQ(0);
 #undef PQ
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !w.det_proj) return e;
+  // partial t of the forward sums goes to slot QA_PHI_LR + t, of the adjoint sums to QA_G_QMMM_LR + t
+  DetMap m{};
+  if (backward != 1) m = det_range(m, QA_PHI_LR, 10);
+  if (backward) m = det_range(m, QA_G_QMMM_LR, 16);
+  return launch_det_reduce(fa, 1, max_nq, w.det_proj, n_pc, 26, m, w.qacc, QA_STRIDE, s);
 }
 
 // ------------------------------------------------------------------ MM gradients (backward hot loop)
@@ -1912,13 +1997,13 @@ template <typename T, int BWD>
 __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk, const double* __restrict__ qm4,
                                                  int cap_qm, const double* __restrict__ mm4, int cap_mm,
                                                  const double* __restrict__ qeff, double* __restrict__ qacc,
-                                                 double* __restrict__ rpart) {
+                                                 double* __restrict__ rpart, double* __restrict__ det) {
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int j = blockIdx.x;
   if (j >= fr.nq) return;
   const int i0 = blockIdx.y * chunk;
-  if (i0 >= fr.nm) return;
+  if (i0 >= fr.nm && !det) return;  // (with det every chunk writes its, possibly zero, partial sums)
   const int i1 = min(fr.nm, i0 + chunk);
   const int r = fr.qoff + j;
   const double X = qm4[r], Y = qm4[(size_t)cap_qm + r], Zc = qm4[(size_t)2 * cap_qm + r];
@@ -1994,7 +2079,10 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
   }
   double tot[NV];
   block_sum256<NV>(acc, tot);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && det) {
+    double* o = det + ((size_t)r * gridDim.y + blockIdx.y) * 13;
+    for (int t = 0; t < NV; t++) o[t] = tot[t];
+  } else if (threadIdx.x == 0) {
     double* qa = qacc + (size_t)r * QA_STRIDE;
     if (BWD != 1) {
       atomicAdd(&qa[QA_PHI_SR], tot[0]);
@@ -2008,20 +2096,38 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
 
 static constexpr int kRealChunk = 2048;
 
+hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
+                          hipStream_t s);
+
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
                           int backward, int fp32, Work& w, hipStream_t s, double* rpart) {
   if (max_nq == 0 || max_nm == 0) return hipSuccess;
-  dim3 grid(max_nq, (max_nm + kRealChunk - 1) / kRealChunk, fa.n_frames);
-#define RQ(T, B)                                                                                                   \
-  hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, kRealChunk, w.qm4, cap_qm, w.mm4, cap_mm, \
-                     w.qeff, w.qacc, rpart)
+  int chunk = kRealChunk;
+  double* det = w.det_real;
+  if (det) {
+    // at most kDetChunks partial rows per site; the MM-side terms come from
+    // the per-atom kernel (fixed order over the sites) instead of atomics
+    chunk = max(chunk, ((max_nm + kDetChunks - 1) / kDetChunks + 255) / 256 * 256);
+  }
+  double* rp = det ? (double*)nullptr : rpart;
+  dim3 grid(max_nq, (max_nm + chunk - 1) / chunk, fa.n_frames);
+#define RQ(T, B)                                                                                              \
+  hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, chunk, w.qm4, cap_qm, w.mm4, cap_mm, \
+                     w.qeff, w.qacc, rp, det)
   if (fp32) {
     if (backward == 2) RQ(float, 2); else if (backward) RQ(float, 1); else RQ(float, 0);
   } else {
     if (backward == 2) RQ(double, 2); else if (backward) RQ(double, 1); else RQ(double, 0);
   }
 #undef RQ
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !det) return e;
+  DetMap m{};
+  if (backward != 1) m = det_range(m, QA_PHI_SR, 10);
+  if (backward) m = det_range(m, QA_G_QMMM_SR, 3);
+  e = launch_det_reduce(fa, 1, max_nq, det, (int)grid.y, 13, m, w.qacc, QA_STRIDE, s);
+  if (e != hipSuccess || !rpart || !backward) return e;
+  return launch_real_mm(g, fa, max_nm, cap_qm, cap_mm, fp32, w, s);
 }
 
 // MM side of the QM-MM real-space sum (backward): dL/dR_i and dL/dq_i with
@@ -2318,7 +2424,7 @@ hipError_t launch_real_cells(const Grid& g, const FrameArg& fa, int max_nq, int 
 __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
                                               const double* __restrict__ Q, const double* __restrict__ mu,
                                               const double* __restrict__ theta, double* __restrict__ qacc,
-                                              double* __restrict__ facc) {
+                                              double* __restrict__ facc, double* __restrict__ det) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int a = blockIdx.x;
@@ -2326,7 +2432,7 @@ __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double*
   const double al = g.alpha, rc2 = g.rcut * g.rcut;
   const double sp = 1.7724538509055160273;  // sqrt(pi)
   const double V = fr.box[0] * fr.box[1] * fr.box[2];
-  const double bgc = -kPi / (al * al * V);
+  const double bgc = -g.bgw * kPi / (al * al * V);
   const double Qtot = facc[f * FA_COUNT + FA_QTOT_QM];
   const int ra = fr.qoff + a;
   const double Xa = qm4[ra], Ya = qm4[(size_t)cap_qm + ra], Za = qm4[(size_t)2 * cap_qm + ra];
@@ -2402,7 +2508,10 @@ __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double*
     qa[QA_DQ_QQ_SR] = tot[4] - 2.0 * al / sp * Qa + a3 * tra + bgc * Qtot;
     for (int t = 0; t < 3; t++) qa[QA_DMU_QQ_SR + t] = tot[5 + t] - 2.0 * a3 * (t == 0 ? ma0 : t == 1 ? ma1 : ma2);
     for (int t = 0; t < 6; t++) qa[QA_DTH_QQ_SR + t] = tot[8 + t] + ((t == 0 || t == 3 || t == 5) ? a3 * Qa : 0.0);
-    atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_SR], e);
+    if (det)
+      det[ra] = e;
+    else
+      atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_SR], e);
   }
 }
 
@@ -2410,8 +2519,10 @@ hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm
                        const double* theta, Work& w, hipStream_t s) {
   if (max_nq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_qmqm, dim3(max_nq, fa.n_frames), dim3(256), 0, s, g, fa, w.qm4, cap_qm, Q, mu, theta, w.qacc,
-                     w.facc);
-  return hipGetLastError();
+                     w.facc, w.det_qq);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !w.det_qq) return e;
+  return launch_det_reduce(fa, 2, 1, w.det_qq, 0, 1, det_map({FA_E_QQ_SR}), w.facc, FA_COUNT, s);
 }
 
 // ------------------------------------------------------------------ forward outputs
@@ -2427,7 +2538,7 @@ __global__ __launch_bounds__(256) void k_finalize_fwd(Grid g, FrameArg fa, const
   const int f = blockIdx.x;
   const FrameDev fr = get_frame(fa, f);
   const double V = fr.box[0] * fr.box[1] * fr.box[2];
-  const double bg = -kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
+  const double bg = -g.bgw * kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
   double esum = 0.0;
   for (int j = threadIdx.x; j < fr.nq; j += 256) {
     const int r = fr.qoff + j;
@@ -2478,7 +2589,7 @@ __global__ __launch_bounds__(256) void k_eff_moments(FrameArg fa, const double* 
                                                      const double* __restrict__ gE, const double* __restrict__ g_phi,
                                                      const double* __restrict__ g_efield,
                                                      const double* __restrict__ g_efgrad, double* __restrict__ qeff,
-                                                     double* __restrict__ facc) {
+                                                     double* __restrict__ facc, double* __restrict__ det) {
   const int f = blockIdx.y;
   const FrameDev fr = get_frame(fa, f);
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -2496,7 +2607,12 @@ __global__ __launch_bounds__(256) void k_eff_moments(FrameArg fa, const double* 
   }
   double tot[1];
   block_sum256<1>(v, tot);
-  if (threadIdx.x == 0 && blockIdx.x * 256 < fr.nq) atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[0]);
+  if (threadIdx.x == 0) {
+    if (det)
+      det[(size_t)f * gridDim.x + blockIdx.x] = tot[0];
+    else if (blockIdx.x * 256 < fr.nq)
+      atomicAdd(&facc[f * FA_COUNT + FA_QTOT_EFF], tot[0]);
+  }
 }
 
 hipError_t launch_eff_moments(const FrameArg& fa, int max_nq, const double* Q, const double* mu, const double* theta,
@@ -2505,8 +2621,10 @@ hipError_t launch_eff_moments(const FrameArg& fa, int max_nq, const double* Q, c
   if (max_nq == 0) return hipSuccess;
   dim3 grid((max_nq + 255) / 256, fa.n_frames);
   hipLaunchKernelGGL(k_eff_moments, grid, dim3(256), 0, s, fa, Q, mu, theta, gE, g_phi, g_efield, g_efgrad, w.qeff,
-                     w.facc);
-  return hipGetLastError();
+                     w.facc, w.det_eff);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !w.det_eff) return e;
+  return launch_det_reduce(fa, 0, 1, w.det_eff, (int)grid.x, 1, det_map({FA_QTOT_EFF}), w.facc, FA_COUNT, s);
 }
 
 // MM outputs: sum the reciprocal partials over column chunks, add the real-space part
@@ -2535,7 +2653,7 @@ __global__ __launch_bounds__(256) void k_reduce_mm(Grid g, FrameArg fa, int kc_n
   g_mm_xyz[3 * (size_t)row + 0] = q * s1 + rp[1];
   g_mm_xyz[3 * (size_t)row + 1] = q * s2 + rp[2];
   g_mm_xyz[3 * (size_t)row + 2] = q * s3 + rp[3];
-  if (g_mm_q) g_mm_q[row] = s0 + rp[0] - kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
+  if (g_mm_q) g_mm_q[row] = s0 + rp[0] - g.bgw * kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
 }
 
 hipError_t launch_reduce_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
@@ -2611,10 +2729,10 @@ __global__ __launch_bounds__(256) void k_finish_fused(Grid g, FrameArg fa, int n
     g_mm_xyz[3 * (size_t)row + 0] = q * s1 + rp[1];
     g_mm_xyz[3 * (size_t)row + 1] = q * s2 + rp[2];
     g_mm_xyz[3 * (size_t)row + 2] = q * s3 + rp[3];
-    if (g_mm_q) g_mm_q[row] = s0 + rp[0] - kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
+    if (g_mm_q) g_mm_q[row] = s0 + rp[0] - g.bgw * kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_EFF];
     return;
   }
-  const double bg = -kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
+  const double bg = -g.bgw * kPi / (g.alpha * g.alpha * V) * facc[f * FA_COUNT + FA_QTOT_MM];
   const double w = qmqm ? 1.0 : 0.0;
   const double mult[6] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0};
   double esum = 0.0;
@@ -2767,9 +2885,15 @@ hipError_t launch_prep(const Grid& g, const FrameArg& fa, int max_nq, int max_nm
   if (nmax > 0 && (parts & PREP_POS)) {
     dim3 grid((nmax + 255) / 256, fa.n_frames);
     hipLaunchKernelGGL(k_prep_pos, grid, dim3(256), 0, s, fa, qm_xyz, Q, mm_xyz, mm_q, mu, theta, w.qm4, cap_qm,
-                       w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc, unit_eff ? w.rpart : (double*)nullptr);
+                       w.mm4, cap_mm, w.qacc, w.qeff, unit_eff, w.facc, unit_eff ? w.rpart : (double*)nullptr,
+                       w.det_frame);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (w.det_frame) {
+      e = launch_det_reduce(fa, 0, 1, w.det_frame, (int)grid.x, 3, det_map({FA_QTOT_MM, FA_QTOT_QM, FA_QTOT_EFF}),
+                            w.facc, FA_COUNT, s);
+      if (e != hipSuccess) return e;
+    }
   }
   if (max_nm > 0 && mm_tables && (parts & PREP_MM_TAB)) {
     launch_tab(g, fa, 0, mm_tables >= 2 ? 1 : 0, max_nm, w.mm4, cap_mm, w.mm_tab, w.mm_ztab, w.mm_xy, s);

@@ -60,6 +60,8 @@ class EwaldConfig:
     plain: bool = False       # unoptimised reference GPU path for the forward pass
     profile: object = False   # True: bracket every launch with HIP events; "hot": only the two hot loops
     cell_list: bool = True    # real space over cells of edge >= rcut when the box has >= 3 per axis
+    background: bool = True   # uniform neutralising background of charged subsystems
+    deterministic: bool = False  # fixed-order cross-block sums: bitwise reproducible outputs
 
 
 @dataclass
@@ -105,7 +107,9 @@ class Plan:
                        "fp32_all": _lib.EWALD_FP32_REAL | _lib.EWALD_FP32_RECIP}[cfg.precision]
         p.flags = ((_lib.EWALD_QMQM if cfg.qmqm else 0) | (_lib.EWALD_PLAIN if cfg.plain else 0)
                    | (_lib.EWALD_PROFILE_HOT if cfg.profile == "hot" else _lib.EWALD_PROFILE if cfg.profile else 0)
-                   | (_lib.EWALD_CELL_LIST if cfg.cell_list else 0))
+                   | (_lib.EWALD_CELL_LIST if cfg.cell_list else 0)
+                   | (0 if cfg.background else _lib.EWALD_NO_BACKGROUND)
+                   | (_lib.EWALD_DETERMINISTIC if cfg.deterministic else 0))
         p.max_qm, p.max_mm, p.max_frames = int(cfg.max_qm), int(cfg.max_mm), int(cfg.max_frames)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
