@@ -497,11 +497,15 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
       HIPCHK(hipEventRecord(pl->ev_qside, q.s));
     }
   }
-  // caller stream: MM phase tables and the (small) QM-QM image sums
+  // caller stream: MM phase tables and, for a single frame, the (small)
+  // QM-QM image sums; with many frames the QM-QM sums are a larger grid that
+  // would hold the forward back (the adjoint takes the GPU meanwhile), so
+  // they go to the second stream, after real space
+  const bool qq_first = q.fa.n_frames == 1;
   LCHK(launch_prep(g, q.fa, q.max_nq, q.max_nm, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w, q.s, pl->cap_qm, pl->cap_mm,
                    tables, 1, PREP_MM_TAB));
   HIPCHK(hipEventRecord(pl->ev_mtab, q.s));
-  if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
+  if (qq_first && q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
   // caller stream: the forward hot loop
   LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
   {
@@ -510,18 +514,23 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
-      // second stream: the adjoint hot loop, then real space (forward, QM- and
-      // MM-side adjoint in one pass; prep has zeroed rpart, where the MM-side
-      // terms accumulate with atomics), which runs beside the projection on
-      // the caller stream and is needed only by the final epilogue
+      // second stream: the adjoint hot loop, then real space (QM side:
+      // forward and adjoint in one pass; MM side: the per-atom kernel), which
+      // runs beside the projection on the caller stream and is needed only by
+      // the final epilogue
       HIPCHK(hipStreamWaitEvent(q.s, pl->ev_mtab, 0));
       LCHK(launch_force_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
       if (q.cells) {
         LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
         LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
       } else {
-        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+        // QM side (forward and adjoint) per (site, MM chunk) block; MM side
+        // one thread per MM atom over the sites (no per-pair atomics)
+        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, nullptr));
+        LCHK(launch_real_mm(g, q.fa, q.max_nm, pl->cap_qm, pl->cap_mm, q.fp32, w, q.s));
       }
+      if (!qq_first && q.qmqm && q.max_nq > 0)
+        LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
     }
   }
   HIPCHK(hipStreamWaitEvent(q.s, pl->ev_qside, 0));

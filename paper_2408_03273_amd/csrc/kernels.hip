@@ -69,22 +69,28 @@ DEV double wave_sum(double v) {
   return v;
 }
 
-// Sum N values over a 256-thread block; thread 0 gets the totals in out[].
+// Sum N values over a 256-thread block through red (4 N doubles of LDS);
+// thread 0 gets the totals in out[].
 template <int N>
-DEV void block_sum256(double (&v)[N], double (&out)[N]) {
-  __shared__ double red[4][N];
+DEV void block_sum256_lds(double (&v)[N], double (&out)[N], double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int t = 0; t < N; t++) {
     double s = wave_sum(v[t]);
-    if (lane == 0) red[wave][t] = s;
+    if (lane == 0) red[wave * N + t] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int t = 0; t < N; t++) out[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    for (int t = 0; t < N; t++) out[t] = red[t] + red[N + t] + red[2 * N + t] + red[3 * N + t];
   }
   __syncthreads();
+}
+
+template <int N>
+DEV void block_sum256(double (&v)[N], double (&out)[N]) {
+  __shared__ double red[4 * N];
+  block_sum256_lds<N>(v, out, red);
 }
 
 // ------------------------------------------------------------------ zero fill
@@ -737,28 +743,24 @@ hipError_t launch_sfac_mm(const Grid& g, const Tuning& t, const FrameArg& fa, in
 // with 4 atoms per K step.  A block of four waves covers CT 16-column tiles
 // and one atom chunk (the waves interleave its K steps); the waves are summed
 // through LDS and the block writes one partial S per k in k order.
+// LDS doubles of one forward item: two wave-pair accumulator sets, and the
+// nz = 0 sums of the four waves
 template <int CT, int NT>
-__global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
-                                                      int xcd_remap, const double* __restrict__ mm4, int cap_mm,
-                                                      const double2* __restrict__ tab,
-                                                      const double* __restrict__ ztab,
-                                                      double2* __restrict__ spart) {
+constexpr int sfac_lds_doubles() {
+  return 2 * CT * NT * 8 * 64 + 4 * CT * 2 * 16;
+}
+
+// One forward work item: column group gc (CT 16-column tiles) of atom chunk ac
+// of frame fr, all 256 threads of the block; lds holds sfac_lds_doubles().
+// Returns (uniformly) for a chunk past the frame's atoms.
+template <int CT, int NT>
+DEV void sfac_mm_mfma_item(const Grid& g, const FrameDev& fr, int gc, int ac, int a_chunk,
+                           const double* __restrict__ mm4, int cap_mm, const double2* __restrict__ tab,
+                           const double* __restrict__ ztab, double2* __restrict__ spart, double* lds) {
   static_assert(CT * NT <= 8, "LDS budget of the block reduction (66 KB at 8)");
   constexpr int NACC = CT * NT * 8;  // accumulator doubles per lane
-  __shared__ double red[2][NACC * 64];
-  __shared__ double s0red[4][CT][2][16];
-  const int f = blockIdx.z;
-  const FrameDev fr = get_frame(fa, f);
-  // Consecutive workgroups go to the 8 XCDs in turn.  With xcd_remap (single
-  // frame) the blocks that share an atom chunk (consecutive logical ids) are
-  // placed on one XCD, so that its L2 serves their common atom rows.
-  int bid = blockIdx.x;
-  if (xcd_remap) {
-    const int per = (int)gridDim.x / 8;
-    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
-  }
-  const int gc = bid % ngc, ac = bid / ngc;
-  if (ac >= nac) return;
+  double* red[2] = {lds, lds + NACC * 64};
+  double(*s0red)[CT][2][16] = reinterpret_cast<double(*)[CT][2][16]>(lds + 2 * NACC * 64);
   const int a0 = ac * a_chunk;
   if (a0 >= fr.nm) return;  // uniform over the block
   const int a1 = min(fr.nm, a0 + a_chunk);
@@ -931,6 +933,28 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
 }
 
 template <int CT, int NT>
+__global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
+                                                      int xcd_remap, const double* __restrict__ mm4, int cap_mm,
+                                                      const double2* __restrict__ tab,
+                                                      const double* __restrict__ ztab,
+                                                      double2* __restrict__ spart) {
+  __shared__ double lds[sfac_lds_doubles<CT, NT>()];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  // Consecutive workgroups go to the 8 XCDs in turn.  With xcd_remap (single
+  // frame) the blocks that share an atom chunk (consecutive logical ids) are
+  // placed on one XCD, so that its L2 serves their common atom rows.
+  int bid = blockIdx.x;
+  if (xcd_remap) {
+    const int per = (int)gridDim.x / 8;
+    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  }
+  const int gc = bid % ngc, ac = bid / ngc;
+  if (ac >= nac) return;
+  sfac_mm_mfma_item<CT, NT>(g, fr, gc, ac, a_chunk, mm4, cap_mm, tab, ztab, spart, lds);
+}
+
+template <int CT, int NT>
 static void launch_sfac_mm_mfma_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int a_chunk, int ngc,
                                   int nac, int xcd, int cap_mm, Work& w) {
   hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, xcd, w.mm4, cap_mm,
@@ -990,15 +1014,13 @@ hipError_t launch_sfac_mm_plain(const Grid& g, const FrameArg& fa, int cap_mm, W
 // truncated QM-QM term (4 pi/V) g (|A|^2 + 2Re A*B + 2Re A*C + |B|^2).
 // Partial sums are in k order (kmajor, matrix-core forward) or nz-major
 // (VALU and plain forward).
-__global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain, int kmajor,
-                                                    const double2* __restrict__ spart,
-                                                    const double2* __restrict__ sabc,
-                                                    const double* __restrict__ kw, double2* __restrict__ smm,
-                                                    size_t smm_stride, double* __restrict__ facc,
-                                                    double* __restrict__ det) {
-  const int f = blockIdx.y;
-  const FrameDev fr = get_frame(fa, f);
-  const int k = blockIdx.x * 256 + threadIdx.x;
+// One item: the 256 reciprocal vectors of block kb (of nkb) of frame f; red
+// holds 8 doubles of LDS.
+DEV void reduce_smm_item(const Grid& g, const FrameDev& fr, int f, int kb, int nkb, int a_chunk, int plain,
+                         int kmajor, const double2* __restrict__ spart, const double2* __restrict__ sabc,
+                         const double* __restrict__ kw, double2* __restrict__ smm, size_t smm_stride,
+                         double* __restrict__ facc, double* __restrict__ det, double* red) {
+  const int k = kb * 256 + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (k < g.KF) {
     const int col = k / g.NZ, iz = k - col * g.NZ;
@@ -1039,10 +1061,10 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
     }
   }
   double tot[2];
-  block_sum256<2>(v, tot);
+  block_sum256_lds<2>(v, tot, red);
   if (threadIdx.x == 0) {
     if (det) {
-      double* o = det + ((size_t)f * gridDim.x + blockIdx.x) * 2;
+      double* o = det + ((size_t)f * nkb + kb) * 2;
       o[0] = tot[0];
       o[1] = tot[1];
     } else {
@@ -1050,6 +1072,19 @@ __global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_c
       atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_LR], tot[1]);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_smm(Grid g, FrameArg fa, int a_chunk, int plain, int kmajor,
+                                                    const double2* __restrict__ spart,
+                                                    const double2* __restrict__ sabc,
+                                                    const double* __restrict__ kw, double2* __restrict__ smm,
+                                                    size_t smm_stride, double* __restrict__ facc,
+                                                    double* __restrict__ det) {
+  __shared__ double red[8];
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  reduce_smm_item(g, fr, f, blockIdx.x, gridDim.x, a_chunk, plain, kmajor, spart, sabc, kw, smm, smm_stride, facc,
+                  det, red);
 }
 
 hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa, int plain, double2* smm_out,
@@ -1069,20 +1104,24 @@ hipError_t launch_reduce_smm(const Grid& g, const Tuning& t, const FrameArg& fa,
 // site from S_MM.  Backward: the QM-MM long-range gradient with the
 // effective moments, and the QM-QM long-range gradient and moment
 // derivatives of the order-2 truncated image energy.
+// LDS doubles of the projection's block sums
+template <int BWD>
+constexpr int project_lds_doubles() {
+  return 4 * (BWD == 0 ? 10 : BWD == 1 ? 16 : 26);
+}
+
+// One item: sites sb S .. sb S + S - 1 of frame f, the k items of block pc of
+// n_pc; red holds project_lds_doubles<BWD>().
 template <int BWD, int S>
-__global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_pc, const double2* __restrict__ smm,
-                                                    size_t smm_stride, const double* __restrict__ Q,
-                                                    const double* __restrict__ mu, const double* __restrict__ theta,
-                                                    const double* __restrict__ qeff,
-                                                    const double2* __restrict__ qtab,
-                                                    const double2* __restrict__ sabc,
-                                                    const double* __restrict__ kw, int qmqm,
-                                                    double* __restrict__ qacc, double* __restrict__ det) {
-  const int f = blockIdx.z;
-  const FrameDev fr = get_frame(fa, f);
+DEV void project_qm_item(const Grid& g, const FrameDev& fr, int f, int sb, int pc, int n_pc,
+                         const double2* __restrict__ smm, size_t smm_stride, const double* __restrict__ Q,
+                         const double* __restrict__ mu, const double* __restrict__ theta,
+                         const double* __restrict__ qeff, const double2* __restrict__ qtab,
+                         const double2* __restrict__ sabc, const double* __restrict__ kw, int qmqm,
+                         double* __restrict__ qacc, double* __restrict__ det, double* red) {
   // S sites per block: the per-k data (weight, S_MM, A/B/C) is loaded once per
   // k and applied to each site; the sites' moments are block-uniform
-  const int j0 = blockIdx.x * S;
+  const int j0 = sb * S;
   if (j0 >= fr.nq) return;
   const int ns = min(S, fr.nq - j0);  // uniform
   // BWD: 0 forward (10 sums), 1 adjoint (16), 2 both (26, adjoint after the forward ones)
@@ -1116,7 +1155,7 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
   // thread item = (column, p = |nz|): k = (nx, ny, +p) and (nx, ny, -p) share e^{i(kx x + ky y)}
   const int NP = g.mz + 1;
   const int n_items = g.NCOL * NP;
-  for (int t = blockIdx.y * 256 + threadIdx.x; t < n_items; t += n_pc * 256) {
+  for (int t = pc * 256 + threadIdx.x; t < n_items; t += n_pc * 256) {
     const int col = t / NP, p = t - col * NP;
     const int nx = col / g.NY, iy = col - nx * g.NY;
     const int ny = iy - g.my;
@@ -1218,10 +1257,10 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
   for (int u = 0; u < S; u++) {
     if (u >= ns) break;  // uniform
     double tot[NV];
-    block_sum256<NV>(acc[u], tot);
+    block_sum256_lds<NV>(acc[u], tot, red);
     if (threadIdx.x == 0 && det) {
       // partial sums of this block, summed over the blocks in order afterwards
-      double* o = det + ((size_t)(fr.qoff + j0 + u) * n_pc + blockIdx.y) * 26;
+      double* o = det + ((size_t)(fr.qoff + j0 + u) * n_pc + pc) * 26;
       for (int t = 0; t < NV; t++) o[t] = tot[t];
     } else if (threadIdx.x == 0) {
       double* qa = qacc + (size_t)(fr.qoff + j0 + u) * QA_STRIDE;
@@ -1241,6 +1280,22 @@ __global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_p
       }
     }
   }
+}
+
+template <int BWD, int S>
+__global__ __launch_bounds__(256) void k_project_qm(Grid g, FrameArg fa, int n_pc, const double2* __restrict__ smm,
+                                                    size_t smm_stride, const double* __restrict__ Q,
+                                                    const double* __restrict__ mu, const double* __restrict__ theta,
+                                                    const double* __restrict__ qeff,
+                                                    const double2* __restrict__ qtab,
+                                                    const double2* __restrict__ sabc,
+                                                    const double* __restrict__ kw, int qmqm,
+                                                    double* __restrict__ qacc, double* __restrict__ det) {
+  __shared__ double red[project_lds_doubles<BWD>()];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  project_qm_item<BWD, S>(g, fr, f, blockIdx.x, blockIdx.y, n_pc, smm, smm_stride, Q, mu, theta, qeff, qtab, sabc,
+                          kw, qmqm, qacc, det, red);
 }
 
 hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int total_nq, const double2* smm,
@@ -1615,24 +1670,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
 // frame) consecutive logical blocks are placed on one XCD, so that the blocks
 // sharing an atom tile read its phase rows through one L2.
 
+// One adjoint work item: atom tile `tile` (16 WV atoms) and column chunk kc of
+// kc_n of frame f, all 64 WV threads of the block; eysh holds
+// eyl_lds_bytes(g, WV).  Returns (uniformly) for a tile past the frame's
+// atoms; waves past the last atom return after the staging barrier (no
+// barrier follows it).
 template <int NK, int WV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
-    Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const double2* __restrict__ tab,
-    const double* __restrict__ ztab, const double* __restrict__ wfrag, const double2* __restrict__ wk0,
-    double* __restrict__ fpart) {
-  extern __shared__ double2 eysh[];  // [NY][16 WV + 1]
-  constexpr int NA = 16 * WV;        // atoms per block
-  constexpr int ES = NA + 1;         // LDS row stride in entries
-  const int f = blockIdx.z;
-  const FrameDev fr = get_frame(fa, f);
+DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, int kc, int kc_n, int cap_mm,
+                           const double2* __restrict__ tab, const double* __restrict__ ztab,
+                           const double* __restrict__ wfrag, const double2* __restrict__ wk0,
+                           double* __restrict__ fpart, double2* eysh) {
+  constexpr int NA = 16 * WV;  // atoms per block
+  constexpr int ES = NA + 1;   // LDS row stride in entries
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
-  int bid = blockIdx.x;
-  if (xcd_remap) {
-    const int per = (int)gridDim.x / 8;
-    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
-  }
-  const int tile = bid / kc_n, kc = bid - tile * kc_n;
   const int ablk = tile * NA;
   if (ablk >= fr.nm) return;  // uniform over the block
   for (int e = threadIdx.x; e < NA * g.NY; e += 64 * WV) {
@@ -1765,6 +1816,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
   }
+}
+
+template <int NK, int WV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
+    Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const double2* __restrict__ tab,
+    const double* __restrict__ ztab, const double* __restrict__ wfrag, const double2* __restrict__ wk0,
+    double* __restrict__ fpart) {
+  extern __shared__ double2 eysh[];  // [NY][16 WV + 1]
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  int bid = blockIdx.x;
+  if (xcd_remap) {
+    const int per = (int)gridDim.x / 8;
+    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  }
+  const int tile = bid / kc_n, kc = bid - tile * kc_n;
+  force_mm_eyl_item<NK, WV>(g, fr, f, tile, kc, kc_n, cap_mm, tab, ztab, wfrag, wk0, fpart, eysh);
 }
 
 // Warp-specialised matrix-core adjoint: in a block of eight waves, waves 0-3
@@ -1993,16 +2061,15 @@ DEV void min_image(double& dx, double& dy, double& dz, const FrameDev& fr) {
 
 // QM side of the QM-MM real-space sum.  Forward: phi, grad phi, 1/2 grad grad phi.
 // Backward: dL/dR_qm with the effective moments.
+// One item: QM site j of frame fr against MM chunk ci (of nchunk, chunk atoms
+// each); red holds 4 x 13 doubles of LDS.
 template <typename T, int BWD>
-__global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk, const double* __restrict__ qm4,
-                                                 int cap_qm, const double* __restrict__ mm4, int cap_mm,
-                                                 const double* __restrict__ qeff, double* __restrict__ qacc,
-                                                 double* __restrict__ rpart, double* __restrict__ det) {
-  const int f = blockIdx.z;
-  const FrameDev fr = get_frame(fa, f);
-  const int j = blockIdx.x;
+DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchunk, int chunk,
+                      const double* __restrict__ qm4, int cap_qm, const double* __restrict__ mm4, int cap_mm,
+                      const double* __restrict__ qeff, double* __restrict__ qacc, double* __restrict__ rpart,
+                      double* __restrict__ det, double* red) {
   if (j >= fr.nq) return;
-  const int i0 = blockIdx.y * chunk;
+  const int i0 = ci * chunk;
   if (i0 >= fr.nm && !det) return;  // (with det every chunk writes its, possibly zero, partial sums)
   const int i1 = min(fr.nm, i0 + chunk);
   const int r = fr.qoff + j;
@@ -2078,9 +2145,9 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
     }
   }
   double tot[NV];
-  block_sum256<NV>(acc, tot);
+  block_sum256_lds<NV>(acc, tot, red);
   if (threadIdx.x == 0 && det) {
-    double* o = det + ((size_t)r * gridDim.y + blockIdx.y) * 13;
+    double* o = det + ((size_t)r * nchunk + ci) * 13;
     for (int t = 0; t < NV; t++) o[t] = tot[t];
   } else if (threadIdx.x == 0) {
     double* qa = qacc + (size_t)r * QA_STRIDE;
@@ -2092,6 +2159,18 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
     if (BWD != 0)
       for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], tot[OB + t]);
   }
+}
+
+template <typename T, int BWD>
+__global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk, const double* __restrict__ qm4,
+                                                 int cap_qm, const double* __restrict__ mm4, int cap_mm,
+                                                 const double* __restrict__ qeff, double* __restrict__ qacc,
+                                                 double* __restrict__ rpart, double* __restrict__ det) {
+  __shared__ double red[4 * 13];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  real_qm_item<T, BWD>(g, fr, blockIdx.x, blockIdx.y, gridDim.y, chunk, qm4, cap_qm, mm4, cap_mm, qeff, qacc, rpart,
+                       det, red);
 }
 
 static constexpr int kRealChunk = 2048;
@@ -2421,13 +2500,10 @@ hipError_t launch_real_cells(const Grid& g, const FrameArg& fa, int max_nq, int 
 // E = 1/2 sum_{a != b} P + sum_a self_a - (pi/(2 a^2 V)) Qtot^2.  One block per
 // site a; its threads take the partners b and the block sums the site's
 // energy share, position gradient and moment derivatives.
-__global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
-                                              const double* __restrict__ Q, const double* __restrict__ mu,
-                                              const double* __restrict__ theta, double* __restrict__ qacc,
-                                              double* __restrict__ facc, double* __restrict__ det) {
-  const int f = blockIdx.y;
-  const FrameDev fr = get_frame(fa, f);
-  const int a = blockIdx.x;
+// One item: QM site a of frame f; red holds 4 x 14 doubles of LDS.
+DEV void qmqm_item(const Grid& g, const FrameDev& fr, int f, int a, const double* __restrict__ qm4, int cap_qm,
+                   const double* __restrict__ Q, const double* __restrict__ mu, const double* __restrict__ theta,
+                   double* __restrict__ qacc, double* __restrict__ facc, double* __restrict__ det, double* red) {
   if (a >= fr.nq) return;
   const double al = g.alpha, rc2 = g.rcut * g.rcut;
   const double sp = 1.7724538509055160273;  // sqrt(pi)
@@ -2495,7 +2571,7 @@ __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double*
     }
   }
   double tot[14];
-  block_sum256<14>(v, tot);
+  block_sum256_lds<14>(v, tot, red);
   if (threadIdx.x == 0) {
     // self terms of site a
     const double a3 = 2.0 * al * al * al / (3.0 * sp);
@@ -2513,6 +2589,16 @@ __global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double*
     else
       atomicAdd(&facc[f * FA_COUNT + FA_E_QQ_SR], e);
   }
+}
+
+__global__ __launch_bounds__(256) void k_qmqm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
+                                              const double* __restrict__ Q, const double* __restrict__ mu,
+                                              const double* __restrict__ theta, double* __restrict__ qacc,
+                                              double* __restrict__ facc, double* __restrict__ det) {
+  __shared__ double red[4 * 14];
+  const int f = blockIdx.y;
+  const FrameDev fr = get_frame(fa, f);
+  qmqm_item(g, fr, f, blockIdx.x, qm4, cap_qm, Q, mu, theta, qacc, facc, det, red);
 }
 
 hipError_t launch_qmqm(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, const double* Q, const double* mu,
