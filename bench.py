@@ -101,9 +101,6 @@ def main():
             p.autotune(s.nm, cache)   # times candidate tilings once (untimed setup); later plans read the cache
         return p
 
-    # the timed plan brackets only the two hot loops with HIP events on their own streams
-    pplan = make_plan("hot")
-
     def tens(a, grad=True):
         return torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
 
@@ -116,27 +113,42 @@ def main():
         E.backward()
         return E
 
-    for _ in range(args.warmup):
-        step(pplan)
-    torch.cuda.synchronize()
-    pplan.profile_report()  # discard warm-up timings
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        E = step(pplan)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    hot_kern = pplan.profile_report()
-    assert np.isfinite(E.item())
+    def timed_steps(p, nsteps):
+        for _ in range(args.warmup):
+            step(p)
+        torch.cuda.synchronize()
+        if p.cfg.profile:
+            p.profile_report()  # discard warm-up timings
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            E = step(p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        assert np.isfinite(E.item())
+        return (t1 - t0) * 1e3 / nsteps
 
-    # roofline of the dominant hot kernel, from the events of the timed region.
-    # Algorithmic flops per (k, MM atom): 8 forward, 6 adjoint (the method's
-    # per-term work).  The matrix-core kernels fold +nz and -nz into one real
-    # contraction and execute 4 (forward) and 8 (adjoint) FP64 flops per term.
+    # headline: a plan without event brackets
+    tplan = make_plan(False)
+    ms = timed_steps(tplan, args.steps)
+    tplan.close()
+    # beside it, the same tiles with HIP events around the hot loops on their
+    # own streams: the per-launch durations of the roofline come from these
+    pplan = make_plan("hot")
+    ms_hot = timed_steps(pplan, args.steps)
+    hot_kern = pplan.profile_report()
+
+    # roofline of the dominant hot kernel, from the events of the bracketed run.
+    # Algorithmic flops per (k in the half space, MM atom): forward 4 (the
+    # folded method's minimal count: one real multiply-add of Re/Im of
+    # q e^{i(kx x + ky y)} with cos and with sin of p kz0 z per (column, |nz|)
+    # covers both k = (kx, ky, +-p kz0)), adjoint 6 (the forces: the imaginary
+    # part of the product with the QM structure factor and the k-weighted
+    # accumulation).  Executed by the matrix-core kernels: 4 and 8 (the adjoint
+    # also forms the potential, dE/dq, and the nz-weighted sums).
     per = {k: dict(count=v["count"], avg_us=1e3 * v["total_ms"] / max(v["count"], 1),
                    ms_per_step=v["total_ms"] / args.steps) for k, v in hot_kern.items()}
-    flops = {"sfac_mm": 8.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm}
-    executed = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 8.0 * nh * s.nm}
+    flops = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm, "hot_step": 10.0 * nh * s.nm}
+    executed = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 8.0 * nh * s.nm, "hot_step": 12.0 * nh * s.nm}
     hot = {k: per[k] for k in flops if k in per}
     dom = max(hot, key=lambda k: hot[k]["ms_per_step"])
     achieved = flops[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12
@@ -165,17 +177,20 @@ def main():
     roof["isolated_executed_frac_vs_measured"] = (None if iso is None or not unit_peak else
                                                   round(executed[dom] / (iso * 1e-6) / 1e12 / unit_peak, 4))
     hot_total_us = sum(per[k]["avg_us"] for k in hot)
-    path_flops = 14.0 * nh * s.nm
+    path_flops = 10.0 * nh * s.nm
+    path_exec = 12.0 * nh * s.nm
     extra = dict(
         hot_path=dict(kernels={k: dict(avg_us=round(per[k]["avg_us"], 2),
                                        algorithmic_frac=round(flops[k] / (per[k]["avg_us"] * 1e-6) / 1e12
                                                               / FP64_PEAK_TFLOPS, 4),
                                        executed_frac=round(executed[k] / (per[k]["avg_us"] * 1e-6) / 1e12
                                                            / FP64_PEAK_TFLOPS, 4)) for k in sorted(hot)},
-                      flops_per_step=path_flops, kernel_us=round(hot_total_us, 2),
-                      note="the two hot loops are launched on two streams; the adjoint's blocks take the GPU as the "
-                           "forward's drain, and each duration includes whatever overlap there was",
-                      step_frac_of_fp64_peak=round(path_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
+                      flops_per_step=path_flops, executed_flops_per_step=path_exec, kernel_us=round(hot_total_us, 2),
+                      ms_per_step_bracketed=round(ms_hot, 4),
+                      step_frac_of_fp64_peak=round(path_flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                      step_executed_frac_of_fp64_peak=round(path_exec / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)),
+        flop_model="per (k in the half space, MM atom): forward 4 (folded minimal count), adjoint 6 (forces); "
+                   "executed 4 + 8",
         kernel_source_hash=src_hash, plan=pplan.describe())
 
     # every launch timed separately (events perturb the step, so not in the timed region)
@@ -195,6 +210,8 @@ def main():
     if not args.no_extras:
         extra["scf_moments_update"] = _scf_update(make_plan(False), inputs, s, ms)
         extra["plain_path"] = _plain_path(s, dev, nh)
+        # the optimised step (forward + adjoint) against the plain forward-only path
+        extra["vs_plain_path"] = round(extra["plain_path"]["ms_per_frame_fwd"] / ms, 2)
         extra["batch_c4"] = _batch_c4(dev)
         extra["region_c3"] = _region_c3(make_plan(True), inputs, s)
         extra["fp32_recip"] = _fp32_recip(make_plan(False), s, inputs, cache, args.no_autotune)
@@ -295,9 +312,10 @@ def _isolated_us(cache, describe, kernel):
 
 
 def _per_config(dev, no_autotune, steps=5):
-    """Every configuration against the algorithmic model (14 flops per (k, MM
-    atom) forward + adjoint, 8 forward only): c1, c2 as single frames through
-    autograd, c5 as one batched call of its 16 replicas, and the plain forward
+    """Every configuration against the algorithmic model (10 flops per (k, MM
+    atom) forward + adjoint, 4 forward only): c1, c2 as single frames through
+    autograd, c5 as one batched call of its 16 replicas (FP64 and the mixed-
+    precision variants, with their deviation from FP64), and the plain forward
     path (one thread per k, sincos per term) on c1, c2, c3 and one c5 replica."""
     import numpy as np
     import torch
@@ -339,28 +357,13 @@ def _per_config(dev, no_autotune, steps=5):
         ob = plan.batch(desc, *xd)
         ms_g = timed(lambda: plan.batch(desc, *xd, out=ob), 4 * steps)
         out[f"c{cfg}"] = dict(n_mm=s.nm, n_kvec_half_space=nh, ms_per_frame_fwd_bwd=round(ms, 4),
-                              frames_per_s=round(1e3 / ms, 1), frac_of_fp64_peak=frac(14.0 * nh * s.nm, ms),
-                              graph_replay_ms=round(ms_g, 4), graph_replay_frac=frac(14.0 * nh * s.nm, ms_g))
+                              frames_per_s=round(1e3 / ms, 1), frac_of_fp64_peak=frac(10.0 * nh * s.nm, ms),
+                              graph_replay_ms=round(ms_g, 4), graph_replay_frac=frac(10.0 * nh * s.nm, ms_g))
         plan.close()
-    frames = [wl.make_config(5, f) for f in range(16)]
-    qoff = np.cumsum([0] + [f.nq for f in frames])
-    moff = np.cumsum([0] + [f.nm for f in frames])
-    desc = [dict(box=f.box, n_qm=f.nq, n_mm=f.nm, qm_offset=int(qoff[i]), mm_offset=int(moff[i]))
-            for i, f in enumerate(frames)]
-    cat = lambda k: torch.tensor(np.concatenate([getattr(f, k) for f in frames]), dtype=torch.float64,  # noqa: E731
-                                 device=dev)
-    xb = [cat("qm_pos"), cat("Q"), cat("mu"), cat("theta"), cat("mm_pos"), cat("q")]
-    f0 = frames[0]
-    nh5 = n_half_space(f0.kmax)
-    plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
-                            max_mm=int(moff[-1]), max_frames=16))
-    if not no_autotune:
-        plan.autotune(f0.nm)
-    ob = plan.batch(desc, *xb)
-    ms = timed(lambda: plan.batch(desc, *xb, out=ob), steps)
-    out["c5_batch"] = dict(frames=16, total_mm=int(moff[-1]), n_kvec_half_space=nh5, ms_per_batch=round(ms, 3),
-                           frames_per_s=round(16e3 / ms, 1), frac_of_fp64_peak=frac(14.0 * nh5 * float(moff[-1]), ms))
-    plan.close()
+    # c5: 16 replicas of 100 000 MM charges, FP64 and the mixed-precision variants
+    v = _batch_variants(dev, 5, 16, ("fp32_real", "fp32_recip", "fp32_all"), steps)
+    out["c5_batch"] = v["fp64"]
+    out["c5_batch"]["mixed_precision"] = {k: v[k] for k in ("fp32_real", "fp32_recip", "fp32_all")}
     plain = {}
     for cfg in (1, 2, 3, 5):
         s = wl.make_config(cfg)
@@ -369,7 +372,7 @@ def _per_config(dev, no_autotune, steps=5):
                                 plain=True))
         x = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
         ms = timed(lambda: plan.forward(*x), 2 if cfg == 5 else steps)
-        plain[f"c{cfg}"] = dict(ms_per_frame_fwd=round(ms, 3), frac_of_fp64_peak=frac(8.0 * nh * s.nm, ms))
+        plain[f"c{cfg}"] = dict(ms_per_frame_fwd=round(ms, 3), frac_of_fp64_peak=frac(4.0 * nh * s.nm, ms))
         plan.close()
     out["plain_forward"] = plain
     return out
@@ -479,20 +482,27 @@ def _plain_path(s, dev, nh, steps=5):
         plan.forward(*x)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    fl = 8.0 * nh * s.nm
+    fl = 4.0 * nh * s.nm
     plan.close()
     return dict(ms_per_frame_fwd=round(ms, 3), frames_per_s_fwd=round(1e3 / ms, 2),
                 frac_of_fp64_peak=round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4))
 
 
-def _batch_c4(dev, steps=5):
-    """64 independent frames of uneven size through one graph-replayed batch call."""
+def _rel_errs(got, ref):
+    """Normwise relative deviation per output array: max|a - b| / max|b|."""
+    return {k: float((got[k] - ref[k]).abs().max() / ref[k].abs().max()) for k in ref if ref[k].abs().max() > 0}
+
+
+def _batch_variants(dev, cfg, nframes, variants, steps):
+    """One batch of frames of configuration cfg through graph-replayed batch
+    calls, FP64 and the given precision variants (each against the FP64
+    outputs of the same call: normwise relative deviation per output)."""
     import numpy as np
     import torch
 
     from paper_2408_03273_amd import workloads as wl
     from paper_2408_03273_amd.ewald import EwaldConfig, Plan
-    frames = [wl.make_config(4, f) for f in range(64)]
+    frames = [wl.make_config(cfg, f) for f in range(nframes)]
     qoff = np.cumsum([0] + [f.nq for f in frames])
     moff = np.cumsum([0] + [f.nm for f in frames])
     desc = [dict(box=f.box, n_qm=f.nq, n_mm=f.nm, qm_offset=int(qoff[i]), mm_offset=int(moff[i]))
@@ -501,32 +511,90 @@ def _batch_c4(dev, steps=5):
                                  device=dev)
     x = [cat("qm_pos"), cat("Q"), cat("mu"), cat("theta"), cat("mm_pos"), cat("q")]
     f0 = frames[0]
-    plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
-                            max_mm=int(moff[-1]), max_frames=64))
-    out = plan.batch(desc, *x)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.batch(desc, *x, out=out)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
     nh = n_half_space(f0.kmax)
-    fl = 14.0 * nh * float(moff[-1])
-    plan.close()
-    return dict(frames=64, total_mm=int(moff[-1]), ms_per_batch=round(ms, 3), frames_per_s=round(64e3 / ms, 1),
-                frac_of_fp64_peak=round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    fl = 10.0 * nh * float(moff[-1])
+    out, ref = {}, None
+    for prec in ("fp64",) + tuple(variants):
+        plan = Plan(EwaldConfig(box=tuple(f0.box), alpha=f0.alpha, rcut=f0.rcut, kmax=f0.kmax, max_qm=int(qoff[-1]),
+                                max_mm=int(moff[-1]), max_frames=nframes, precision=prec))
+        if cfg == 5 or prec == "fp32_recip" or prec == "fp32_all":
+            plan.autotune(f0.nm)
+        o = plan.batch(desc, *x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.batch(desc, *x, out=o)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = dict(frames=nframes, total_mm=int(moff[-1]), ms_per_batch=round(ms, 3),
+                 frames_per_s=round(nframes * 1e3 / ms, 1),
+                 frac_of_fp64_peak=round(fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4), plan=plan.describe())
+        if ref is None:
+            ref = {k: v.clone() for k, v in o.items()}
+        else:
+            err = _rel_errs(o, ref)
+            r["rel_err_vs_fp64"] = {k: float(f"{v:.2e}") for k, v in err.items()}
+            r["max_rel_err"] = float(f"{max(err.values()):.2e}")
+        out[prec] = r
+        plan.close()
+    return out
+
+
+def _batch_c4(dev, steps=5):
+    """64 independent frames of uneven size through one graph-replayed batch
+    call, FP64 and with the real space in FP32 (FP64 accumulation)."""
+    v = _batch_variants(dev, 4, 64, ("fp32_real",), steps)
+    res = v["fp64"]
+    res["fp32_real"] = v["fp32_real"]
+    return res
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _cpu_baseline(s):
-    """The FP64 CPU oracle, as it stands, on one full c3 frame (forward and all gradients)."""
-    from oracle.oracle import num_threads, oracle_ewald
+    """The FP64 CPU oracle, as it stands, built for this host (gcc -O3
+    -march=native -fopenmp, in a temporary directory) and timed on one full c3
+    frame (forward and every gradient) with all OpenMP threads, and on a
+    sample of the frame (its first 5000 MM charges, scaled to a whole frame by
+    the MM count, which the oracle's time is linear in) with one thread."""
+    import tempfile
+
+    import numpy as np
+
+    from oracle import oracle as orc
+    lib = os.path.join(tempfile.mkdtemp(prefix="mpewald_oracle_"), "libewald_oracle_native.so")
+    orc.build(out=lib, extra_flags=("-O3", "-march=native"))
+    # the host share this process may use (the OpenMP setting where there is one)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    orc.set_num_threads(threads, lib_path=lib)
     t0 = time.perf_counter()
-    r = oracle_ewald(s.box, s.alpha, s.rcut, s.kmax, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)
+    r = orc.oracle_ewald(s.box, s.alpha, s.rcut, s.kmax, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q, lib_path=lib)
     dt = time.perf_counter() - t0
-    assert r.E == r.E
-    return dict(value=round(1.0 / dt, 5), unit="frames/s", cores=num_threads(), kind="oracle",
+    assert np.isfinite(r.E)
+    n1 = 5000
+    orc.set_num_threads(1, lib_path=lib)
+    t0 = time.perf_counter()
+    r1 = orc.oracle_ewald(s.box, s.alpha, s.rcut, s.kmax, s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos[:n1], s.q[:n1],
+                          lib_path=lib)
+    dt1 = time.perf_counter() - t0
+    assert np.isfinite(r1.E)
+    frame1 = dt1 * s.nm / n1
+    return dict(value=round(1.0 / dt, 5), unit="frames/s", cores=threads, kind="oracle",
                 sample="one full c3 frame (35000 MM, 40 QM, |n|<=24): energy, fields and every gradient",
-                seconds=round(dt, 2))
+                seconds=round(dt, 2), cpu_model=_cpu_model(), build="gcc -O3 -march=native -fopenmp",
+                single_thread=dict(value=round(1.0 / frame1, 5), unit="frames/s", cores=1,
+                                   sample=f"the c3 frame with its first {n1} MM charges, "
+                                          f"{dt1:.2f} s, scaled by {s.nm}/{n1}",
+                                   seconds_per_frame=round(frame1, 2)))
 
 
 if __name__ == "__main__":
