@@ -2061,13 +2061,32 @@ DEV void min_image(double& dx, double& dy, double& dz, const FrameDev& fr) {
 
 // QM side of the QM-MM real-space sum.  Forward: phi, grad phi, 1/2 grad grad phi.
 // Backward: dL/dR_qm with the effective moments.
+// Pairs within the cutoff are few among the (site, atom, image) triples a
+// block tests (a few percent at rc <= L/2), and a wave whose lanes test
+// different atoms would evaluate erfc and exp for a pair whenever any of its
+// lanes has one.  Each wave therefore appends its lanes' pairs, in lane order,
+// to a FIFO of its own in LDS and evaluates them 64 at a time, one pair per
+// lane (the order is fixed, so the sums are too).
+static constexpr int kPairFifo = 128;  // entries per wave (< 64 pending + up to 64 appended)
+
+template <typename T>
+constexpr int pair_fifo_bytes() {
+  return 4 * kPairFifo * (5 * (int)sizeof(T) + (int)sizeof(int));
+}
+
+// LDS between the lanes of one wave: stores complete before other lanes read
+DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // One item: QM site j of frame fr against MM chunk ci (of nchunk, chunk atoms
-// each); red holds 4 x 13 doubles of LDS.
+// each); red holds 4 x 13 doubles of LDS, fifo pair_fifo_bytes<T>() bytes.
 template <typename T, int BWD>
 DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchunk, int chunk,
                       const double* __restrict__ qm4, int cap_qm, const double* __restrict__ mm4, int cap_mm,
                       const double* __restrict__ qeff, double* __restrict__ qacc, double* __restrict__ rpart,
-                      double* __restrict__ det, double* red) {
+                      double* __restrict__ det, double* red, void* fifo) {
   if (j >= fr.nq) return;
   const int i0 = ci * chunk;
   if (i0 >= fr.nm && !det) return;  // (with det every chunk writes its, possibly zero, partial sums)
@@ -2093,57 +2112,117 @@ DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchu
   const double* my_ = mm4 + (size_t)cap_mm + fr.moff;
   const double* mz_ = mm4 + (size_t)2 * cap_mm + fr.moff;
   const double* mq_ = mm4 + (size_t)3 * cap_mm + fr.moff;
-  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-    double bx = X - mx_[i], by = Y - my_[i], bz = Zc - mz_[i];
-    min_image(bx, by, bz, fr);
-    const int n1_ = 2 * fr.nimg + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // this wave's FIFO: x, y, z, r^2, q (T) and the atom index
+  T* fx = reinterpret_cast<T*>(fifo) + wave * 5 * kPairFifo;
+  T* fy = fx + kPairFifo;
+  T* fz = fy + kPairFifo;
+  T* fr2 = fz + kPairFifo;
+  T* fq = fr2 + kPairFifo;
+  int* fi = reinterpret_cast<int*>(reinterpret_cast<T*>(fifo) + 4 * 5 * kPairFifo) + wave * kPairFifo;
+  // evaluate the first n (<= 64) pairs of the FIFO, one per lane
+  auto evaluate = [&](int n) {
+    if (lane >= n) return;
+    const T x = fx[lane], y = fy[lane], z = fz[lane], q = fq[lane];
+    const int i = fi[lane];
+    const Radial<T> R = radial<T>(fr2[lane], a);
+    if (BWD != 1) {
+      acc[0] += (double)(q * R.f1);
+      acc[1] += (double)(-q * x * R.f3);
+      acc[2] += (double)(-q * y * R.f3);
+      acc[3] += (double)(-q * z * R.f3);
+      const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
+      acc[4] += (double)(h5 * x * x - h3);
+      acc[5] += (double)(h5 * x * y);
+      acc[6] += (double)(h5 * x * z);
+      acc[7] += (double)(h5 * y * y - h3);
+      acc[8] += (double)(h5 * y * z);
+      acc[9] += (double)(h5 * z * z - h3);
+    }
+    if (BWD != 0) {
+      // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
+      const T md = m0 * x + m1 * y + m2 * z;
+      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+      const T dtd = x * thx + y * thy + z * thz;
+      const T tr = t0 + t3 + t5;
+      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+      const T s2 = -R.f3;
+      const T s3 = T(3) * R.f5;
+      const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
+                   gz = (double)(s1 * z + s2 * m2 + s3 * thz);
+      acc[OB + 0] += (double)q * gx;
+      acc[OB + 1] += (double)q * gy;
+      acc[OB + 2] += (double)q * gz;
+      if (rpart) {
+        // MM side: potential of the effective moments per unit charge, and -q g
+        double* o = rpart + (size_t)(fr.moff + i) * 4;
+        atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
+        atomicAdd(&o[1], -(double)q * gx);
+        atomicAdd(&o[2], -(double)q * gy);
+        atomicAdd(&o[3], -(double)q * gz);
+      }
+    }
+  };
+  int count = 0;  // pending pairs of this wave (wave-uniform)
+  const int n1_ = 2 * fr.nimg + 1;
+  for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
+    const int i = base + threadIdx.x;
+    const bool valid = i < i1;
+    double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
+    if (valid) {
+      bx = X - mx_[i];
+      by = Y - my_[i];
+      bz = Zc - mz_[i];
+      qd = mq_[i];
+      min_image(bx, by, bz, fr);
+    }
     for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
       // lattice images within the cutoff (only the minimum image when rc <= L/2)
       const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
       const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
       const double r2d = dx * dx + dy * dy + dz * dz;
-      if (!(r2d < rc2) || r2d == 0.0) continue;
-      const T x = (T)dx, y = (T)dy, z = (T)dz;
-      const Radial<T> R = radial<T>((T)r2d, a);
-      const T q = (T)mq_[i];
-      if (BWD != 1) {
-        acc[0] += (double)(q * R.f1);
-        acc[1] += (double)(-q * x * R.f3);
-        acc[2] += (double)(-q * y * R.f3);
-        acc[3] += (double)(-q * z * R.f3);
-        const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
-        acc[4] += (double)(h5 * x * x - h3);
-        acc[5] += (double)(h5 * x * y);
-        acc[6] += (double)(h5 * x * z);
-        acc[7] += (double)(h5 * y * y - h3);
-        acc[8] += (double)(h5 * y * z);
-        acc[9] += (double)(h5 * z * z - h3);
+      const bool hit = valid && r2d < rc2 && r2d != 0.0;
+      const unsigned long long mask = __ballot(hit);
+      if (hit) {
+        const int pos = count + (int)__popcll(mask & ((1ull << lane) - 1ull));
+        fx[pos] = (T)dx;
+        fy[pos] = (T)dy;
+        fz[pos] = (T)dz;
+        fr2[pos] = (T)r2d;
+        fq[pos] = (T)qd;
+        fi[pos] = i;
       }
-      if (BWD != 0) {
-        // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
-        const T md = m0 * x + m1 * y + m2 * z;
-        const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
-        const T dtd = x * thx + y * thy + z * thz;
-        const T tr = t0 + t3 + t5;
-        const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
-        const T s2 = -R.f3;
-        const T s3 = T(3) * R.f5;
-        const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
-                     gz = (double)(s1 * z + s2 * m2 + s3 * thz);
-        acc[OB + 0] += (double)q * gx;
-        acc[OB + 1] += (double)q * gy;
-        acc[OB + 2] += (double)q * gz;
-        if (rpart) {
-          // MM side: potential of the effective moments per unit charge, and -q g
-          double* o = rpart + (size_t)(fr.moff + i) * 4;
-          atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
-          atomicAdd(&o[1], -(double)q * gx);
-          atomicAdd(&o[2], -(double)q * gy);
-          atomicAdd(&o[3], -(double)q * gz);
+      count += (int)__popcll(mask);
+      if (count >= 64) {
+        wave_lds_sync();
+        evaluate(64);
+        // move the remaining count - 64 (< 64) pairs to the front
+        T sx = 0, sy = 0, sz = 0, s2 = 0, sq = 0;
+        int si = 0;
+        const bool mv = lane < count - 64;
+        if (mv) {
+          sx = fx[64 + lane];
+          sy = fy[64 + lane];
+          sz = fz[64 + lane];
+          s2 = fr2[64 + lane];
+          sq = fq[64 + lane];
+          si = fi[64 + lane];
         }
+        wave_lds_sync();
+        if (mv) {
+          fx[lane] = sx;
+          fy[lane] = sy;
+          fz[lane] = sz;
+          fr2[lane] = s2;
+          fq[lane] = sq;
+          fi[lane] = si;
+        }
+        count -= 64;
       }
     }
   }
+  wave_lds_sync();
+  evaluate(count);
   double tot[NV];
   block_sum256_lds<NV>(acc, tot, red);
   if (threadIdx.x == 0 && det) {
@@ -2167,10 +2246,11 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
                                                  const double* __restrict__ qeff, double* __restrict__ qacc,
                                                  double* __restrict__ rpart, double* __restrict__ det) {
   __shared__ double red[4 * 13];
+  __shared__ __align__(16) char fifo[pair_fifo_bytes<T>()];
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   real_qm_item<T, BWD>(g, fr, blockIdx.x, blockIdx.y, gridDim.y, chunk, qm4, cap_qm, mm4, cap_mm, qeff, qacc, rpart,
-                       det, red);
+                       det, red, fifo);
 }
 
 static constexpr int kRealChunk = 2048;
