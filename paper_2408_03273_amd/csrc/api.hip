@@ -293,6 +293,28 @@ bool assign_cells(const ewald_plan* pl, FrameDev* frames, int n) {
   return ok;
 }
 
+// How the all-pairs real space gets its MM-side adjoint terms.  With the
+// minimum image only, an MM atom meets few QM sites within the cutoff and the
+// QM-side kernel adds each pair's terms to the atom's row (returns 0).  When
+// the cutoff reaches beyond half a box length (lattice images, rc ~ L), every
+// (site, atom) pair has several images within it, and those per-pair adds to
+// one row serialise; the per-atom kernel then sums them, over enough site
+// groups to give about 2^19 threads (one group in deterministic plans).
+int real_mm_groups(const ewald_plan* pl, const FrameDev* frames, int n) {
+  bool images = false;
+  long atoms = 0;
+  int max_nq = 0;
+  for (int f = 0; f < n; f++) {
+    images = images || frames[f].nimg > 0;
+    atoms += frames[f].nm;
+    max_nq = std::max(max_nq, frames[f].nq);
+  }
+  if (!images || atoms == 0) return 0;
+  if (pl->p.flags & EWALD_DETERMINISTIC) return 1;
+  const long groups = ((1L << 19) + atoms - 1) / atoms;
+  return (int)std::max(1L, std::min<long>(groups, std::max(1, max_nq)));
+}
+
 // atoms per forward block so that the grid has about kTargetBlocks blocks
 // without exceeding the partial-sum slots.
 int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
@@ -402,6 +424,7 @@ struct Seq {
   int fp32;
   int qmqm;
   int cells;  // real space over the cell list
+  int mm_groups = 0;  // MM side of real space: 0 per pair, else site groups of the per-atom kernel
 };
 
 #define LCHK_P(pl_, s_, name, expr)                                                                 \
@@ -446,7 +469,7 @@ ewald_status_t seq_forward_tail(const Seq& q, const double* Q, const double* mu,
       LCHK(launch_real_cells(pl->g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, pl->w, q.s));
     else
       LCHK(launch_real_qm(pl->g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, mode, q.fp32, pl->w, q.s,
-                          with_adjoint ? pl->w.rpart : nullptr));
+                          with_adjoint ? pl->w.rpart : nullptr, q.mm_groups));
     if (q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(pl->g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, pl->w, q.s));
   }
   if (!finalize) return EWALD_OK;
@@ -467,9 +490,10 @@ ewald_status_t join_to(ewald_plan* pl, hipStream_t from, hipStream_t to) {
 }
 
 // Forward pass and the gradients of E (upstream gradient 1) in one sequence.
-// The reciprocal MM adjoint (matrix cores) runs on a second stream beside the
-// forward structure factor (vector units); both need only the phase tables
-// and the QM structure factors.
+// The reciprocal MM adjoint runs on a second stream beside the forward
+// structure factor (each hot loop on the matrix cores or the vector units as
+// the plan's tiles choose); both need only the phase tables and the QM
+// structure factors.
 ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, const double* Q, const double* mu,
                            const double* theta, const double* mm_xyz, const double* mm_q, double2* smm,
                            size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
@@ -529,7 +553,8 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
         // one pass: QM side per (site, MM chunk) block, the MM-side terms of
         // each pair into rpart (zeroed by prep; in deterministic mode the
         // launcher takes them from the per-atom kernel instead)
-        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart));
+        LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart,
+                            q.mm_groups));
       }
       if (!qq_first && q.qmqm && q.max_nq > 0)
         LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
@@ -786,6 +811,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
+  q.mm_groups = real_mm_groups(plan, &q.fa.f0, 1);
   if (ctx) plan->stale_ctx.erase(ctx);
   if (ctx && !q.plain) {
     plan->t.kc = choose_kc(plan, n_mm);
@@ -856,6 +882,7 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
   q.fa.f0 = make_frame(plan->p.box, n_qm, n_mm, 0, 0, 0, plan->p.rcut);
   q.fa.n_frames = 1;
   q.cells = assign_cells(plan, &q.fa.f0, 1) ? 1 : 0;
+  q.mm_groups = real_mm_groups(plan, &q.fa.f0, 1);
   CtxView cv = ctx_view(plan->g, (void*)ctx, n_qm, n_mm);
   Work& w = plan->w;
   if (!g_phi && !g_efield && !g_efgrad && !(plan->p.flags & EWALD_PLAIN) && !plan->stale_ctx.count(ctx)) {
@@ -896,7 +923,9 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
     STEP(launch_zero(w.rpart, (size_t)plan->cap_mm * 4, s));
     STEP(launch_real_cells(g, q.fa, n_qm, plan->cap_qm, plan->cap_mm, 1, q.fp32, w, s));
   } else {
-    STEP(launch_real_mm(g, q.fa, n_mm, plan->cap_qm, plan->cap_mm, q.fp32, w, s));
+    // several site groups add into rpart from zero; one group writes it
+    if (q.mm_groups > 1) STEP(launch_zero(w.rpart, (size_t)plan->cap_mm * 4, s));
+    STEP(launch_real_mm(g, q.fa, n_qm, n_mm, plan->cap_qm, plan->cap_mm, q.fp32, w, s, q.mm_groups));
   }
   STEP(launch_reduce_mm(g, plan->t, q.fa, n_mm, plan->cap_mm, g_mm_xyz, g_mm_q, w, s));
   STEP(launch_project_qm(g, q.fa, n_qm, n_qm, cv.smm, g.KF, Q, mu, theta, 1, q.qmqm, w, s));
@@ -912,7 +941,8 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
 
 namespace {
 
-ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int cells, int max_nq, int max_nm,
+ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int cells, int mm_groups, int max_nq,
+                             int max_nm,
                              int total_nq, int total_nm, const double* qm_xyz, const double* Q, const double* mu,
                              const double* theta, const double* mm_xyz, const double* mm_q, int mode, double* energy,
                              double* phi, double* efield, double* efgrad, double* g_qm_xyz, double* g_Q,
@@ -932,6 +962,7 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   q.fa.n_frames = n_frames;
   memset(&q.fa.f0, 0, sizeof(q.fa.f0));
   q.cells = cells;
+  q.mm_groups = mm_groups;
   Work& w = plan->w;
   const Grid& g = plan->g;
   if (mode == EWALD_FWD_BWD) {
@@ -1013,6 +1044,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     slot += (fr.n_mm + use.a_chunk - 1) / use.a_chunk;
   }
   const int cells = assign_cells(plan, hf.data(), n_frames) ? 1 : 0;
+  const int mm_groups = real_mm_groups(plan, hf.data(), n_frames);
   // graph key: frames, pointers, mode, stream, tiles
   std::vector<unsigned char> key;
   for (auto& f : hf) key_push(key, f);
@@ -1041,9 +1073,9 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     HIPCHK(hipStreamBeginCapture(plan->gstream, hipStreamCaptureModeThreadLocal));
     plan->capturing = true;
     // QM accumulators are indexed by packed row, so clear every row up to the last one used
-    st = enqueue_batch(plan, plan->gstream, n_frames, cells, max_nq, max_nm, (int)end_q, (int)total_nm, qm_xyz, Q, mu,
-                       theta, mm_xyz, mm_q, mode, energy, phi, efield, efgrad, g_qm_xyz, g_Q, g_mu, g_theta,
-                       g_mm_xyz, g_mm_q);
+    st = enqueue_batch(plan, plan->gstream, n_frames, cells, mm_groups, max_nq, max_nm, (int)end_q, (int)total_nm,
+                       qm_xyz, Q, mu, theta, mm_xyz, mm_q, mode, energy, phi, efield, efgrad, g_qm_xyz, g_Q, g_mu,
+                       g_theta, g_mm_xyz, g_mm_q);
     hipError_t ce = hipStreamEndCapture(plan->gstream, &graph);
     plan->capturing = false;
     plan->t = saved;

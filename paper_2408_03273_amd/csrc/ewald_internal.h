@@ -210,11 +210,16 @@ hipError_t launch_project_qm(const Grid& g, const FrameArg& fa, int max_nq, int 
 hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm, Work& w,
                            hipStream_t s);
 // backward: 0 forward sums, 1 QM-side adjoint, 2 both; rpart (zeroed, may be
-// null) also receives the MM-side adjoint terms
+// null) also receives the MM-side adjoint terms: from each pair of the
+// QM-side kernel (mm_groups 0), or from the per-atom kernel over mm_groups
+// site groups (deterministic plans: one group)
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
-                          int backward, int fp32, Work& w, hipStream_t s, double* rpart = nullptr);
-hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
-                          hipStream_t s);
+                          int backward, int fp32, Work& w, hipStream_t s, double* rpart = nullptr,
+                          int mm_groups = 0);
+// MM side of real space per MM atom into w.rpart: one site group writes each
+// atom's four values; several groups add to them (rpart zeroed beforehand)
+hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
+                          int fp32, Work& w, hipStream_t s, int groups = 1);
 // cell list (edge >= rcut) of the MM atoms and the real-space kernels that use it
 hipError_t launch_cells(const FrameArg& fa, int max_nm, int cap_mm, Work& w, hipStream_t s);
 hipError_t launch_real_cells(const Grid& g, const FrameArg& fa, int max_nq, int cap_qm, int cap_mm, int backward,

@@ -2255,11 +2255,8 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
 
 static constexpr int kRealChunk = 2048;
 
-hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
-                          hipStream_t s);
-
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
-                          int backward, int fp32, Work& w, hipStream_t s, double* rpart) {
+                          int backward, int fp32, Work& w, hipStream_t s, double* rpart, int mm_groups) {
   if (max_nq == 0 || max_nm == 0) return hipSuccess;
   int chunk = kRealChunk;
   double* det = w.det_real;
@@ -2268,7 +2265,10 @@ hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max
     // the per-atom kernel (fixed order over the sites) instead of atomics
     chunk = max(chunk, ((max_nm + kDetChunks - 1) / kDetChunks + 255) / 256 * 256);
   }
-  double* rp = det ? (double*)nullptr : rpart;
+  // MM-side terms: per pair into rpart from this kernel, or (deterministic
+  // mode, or mm_groups > 0) from the per-atom kernel afterwards
+  const bool per_atom = rpart && backward && (det || mm_groups > 0);
+  double* rp = per_atom ? (double*)nullptr : rpart;
   dim3 grid(max_nq, (max_nm + chunk - 1) / chunk, fa.n_frames);
 #define RQ(T, B)                                                                                              \
   hipLaunchKernelGGL((k_real_qm<T, B>), grid, dim3(256), 0, s, g, fa, chunk, w.qm4, cap_qm, w.mm4, cap_mm, \
@@ -2280,77 +2280,116 @@ hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max
   }
 #undef RQ
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !det) return e;
-  DetMap m{};
-  if (backward != 1) m = det_range(m, QA_PHI_SR, 10);
-  if (backward) m = det_range(m, QA_G_QMMM_SR, 3);
-  e = launch_det_reduce(fa, 1, max_nq, det, (int)grid.y, 13, m, w.qacc, QA_STRIDE, s);
-  if (e != hipSuccess || !rpart || !backward) return e;
-  return launch_real_mm(g, fa, max_nm, cap_qm, cap_mm, fp32, w, s);
+  if (e != hipSuccess) return e;
+  if (det) {
+    DetMap m{};
+    if (backward != 1) m = det_range(m, QA_PHI_SR, 10);
+    if (backward) m = det_range(m, QA_G_QMMM_SR, 3);
+    e = launch_det_reduce(fa, 1, max_nq, det, (int)grid.y, 13, m, w.qacc, QA_STRIDE, s);
+    if (e != hipSuccess) return e;
+  }
+  if (!per_atom) return hipSuccess;
+  // one site group writes each atom's terms in a fixed order (deterministic);
+  // several add into rpart, which prep zeroed
+  return launch_real_mm(g, fa, max_nq, max_nm, cap_qm, cap_mm, fp32, w, s, det ? 1 : mm_groups);
+}
+
+// Lattice images n along one axis that can put b + n L within rc (at most
+// nimg either side): a pair needs |b + n L| < rc on every axis.  A NaN offset
+// gives the full range (its distance tests then fail), an infinite one an
+// empty range; both ends stay within [-nimg - 1, nimg + 1] before conversion.
+DEV void image_range(double b, double L, double rc, int nimg, int& lo, int& hi) {
+  const double n = (double)nimg;
+  lo = (int)fmin(fmax(ceil((-rc - b) / L), -n), n + 1.0);
+  hi = (int)fmax(fmin(floor((rc - b) / L), n), -n - 1.0);
 }
 
 // MM side of the QM-MM real-space sum (backward): dL/dR_i and dL/dq_i with
-// the effective moments, one thread per MM atom looping over the QM sites.
+// the effective moments, one thread per MM atom looping over the QM sites of
+// its block's site group (blockIdx.y of gridDim.y groups), for each site over
+// the lattice images whose per-axis offsets can lie within the cutoff.  With
+// one group the thread writes its atom's four values; with several (the
+// paper's rc ~ L regime, where the per-atom work is large) it adds them to
+// rpart, which the caller has zeroed.
 template <typename T>
 __global__ __launch_bounds__(256) void k_real_mm(Grid g, FrameArg fa, const double* __restrict__ qm4, int cap_qm,
                                                  const double* __restrict__ mm4, int cap_mm,
-                                                 const double* __restrict__ qeff, double* __restrict__ rpart) {
-  const int f = blockIdx.y;
+                                                 const double* __restrict__ qeff, double* __restrict__ rpart,
+                                                 int sites_per_group) {
+  const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= fr.nm) return;
+  const int j0 = blockIdx.y * sites_per_group, j1 = min(fr.nq, j0 + sites_per_group);
+  if (j0 >= j1 && gridDim.y > 1) return;  // (one group: the atom's zero terms are still written)
   const int row = fr.moff + i;
   const double X = mm4[row], Y = mm4[(size_t)cap_mm + row], Zc = mm4[(size_t)2 * cap_mm + row];
   const double q = mm4[(size_t)3 * cap_mm + row];
   const T a = (T)g.alpha;
   const double rc2 = g.rcut * g.rcut;
   double aphi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-  for (int j = 0; j < fr.nq; j++) {
+  for (int j = j0; j < j1; j++) {
     const int r = fr.qoff + j;
     double bx = qm4[r] - X, by = qm4[(size_t)cap_qm + r] - Y, bz = qm4[(size_t)2 * cap_qm + r] - Zc;
     min_image(bx, by, bz, fr);
-    const int n1_ = 2 * fr.nimg + 1;
-    for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
-      // lattice images within the cutoff (only the minimum image when rc <= L/2)
-      const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
-      const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
-      const double r2d = dx * dx + dy * dy + dz * dz;
-      if (!(r2d < rc2) || r2d == 0.0) continue;
-      const T x = (T)dx, y = (T)dy, z = (T)dz;
-      const Radial<T> R = radial<T>((T)r2d, a);
-      const double* qe = qeff + 10 * (size_t)r;
-      const T Qe = (T)qe[0], m0 = (T)qe[1], m1 = (T)qe[2], m2 = (T)qe[3];
-      const T t0 = (T)qe[4], t1 = (T)qe[5], t2 = (T)qe[6], t3 = (T)qe[7], t4 = (T)qe[8], t5 = (T)qe[9];
-      const T md = m0 * x + m1 * y + m2 * z;
-      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
-      const T dtd = x * thx + y * thy + z * thz;
-      const T tr = t0 + t3 + t5;
-      // energy per unit MM charge: Q psi0 + mu.psi1 + theta:psi2
-      aphi += (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
-      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
-      const T s2 = -R.f3;
-      const T s3 = T(3) * R.f5;
-      // r depends on -R_mm
-      gx -= (double)(s1 * x + s2 * m0 + s3 * thx);
-      gy -= (double)(s1 * y + s2 * m1 + s3 * thy);
-      gz -= (double)(s1 * z + s2 * m2 + s3 * thz);
-    }
+    int lx, hx, ly, hy, lz, hz;
+    image_range(bx, fr.box[0], g.rcut, fr.nimg, lx, hx);
+    image_range(by, fr.box[1], g.rcut, fr.nimg, ly, hy);
+    image_range(bz, fr.box[2], g.rcut, fr.nimg, lz, hz);
+    for (int ix_ = lx; ix_ <= hx; ix_++)
+      for (int iy_ = ly; iy_ <= hy; iy_++)
+        for (int iz_ = lz; iz_ <= hz; iz_++) {
+          const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
+          const double r2d = dx * dx + dy * dy + dz * dz;
+          if (!(r2d < rc2) || r2d == 0.0) continue;
+          const T x = (T)dx, y = (T)dy, z = (T)dz;
+          const Radial<T> R = radial<T>((T)r2d, a);
+          const double* qe = qeff + 10 * (size_t)r;
+          const T Qe = (T)qe[0], m0 = (T)qe[1], m1 = (T)qe[2], m2 = (T)qe[3];
+          const T t0 = (T)qe[4], t1 = (T)qe[5], t2 = (T)qe[6], t3 = (T)qe[7], t4 = (T)qe[8], t5 = (T)qe[9];
+          const T md = m0 * x + m1 * y + m2 * z;
+          const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
+          const T dtd = x * thx + y * thy + z * thz;
+          const T tr = t0 + t3 + t5;
+          // energy per unit MM charge: Q psi0 + mu.psi1 + theta:psi2
+          aphi += (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
+          const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+          const T s2 = -R.f3;
+          const T s3 = T(3) * R.f5;
+          // r depends on -R_mm
+          gx -= (double)(s1 * x + s2 * m0 + s3 * thx);
+          gy -= (double)(s1 * y + s2 * m1 + s3 * thy);
+          gz -= (double)(s1 * z + s2 * m2 + s3 * thz);
+        }
   }
   double* o = rpart + (size_t)row * 4;
-  o[0] = aphi;
-  o[1] = q * gx;
-  o[2] = q * gy;
-  o[3] = q * gz;
+  if (gridDim.y == 1) {
+    o[0] = aphi;
+    o[1] = q * gx;
+    o[2] = q * gy;
+    o[3] = q * gz;
+  } else {
+    atomicAdd(&o[0], aphi);
+    atomicAdd(&o[1], q * gx);
+    atomicAdd(&o[2], q * gy);
+    atomicAdd(&o[3], q * gz);
+  }
 }
 
-hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nm, int cap_qm, int cap_mm, int fp32, Work& w,
-                          hipStream_t s) {
+hipError_t launch_real_mm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
+                          int fp32, Work& w, hipStream_t s, int groups) {
   if (max_nm == 0) return hipSuccess;
-  dim3 grid((max_nm + 255) / 256, fa.n_frames);
+  if (groups < 1 || max_nq <= 1) groups = 1;
+  if (groups > max_nq) groups = max_nq;
+  const int spg = (max_nq + groups - 1) / groups;
+  groups = (max_nq + spg - 1) / spg;
+  dim3 grid((max_nm + 255) / 256, groups, fa.n_frames);
   if (fp32)
-    hipLaunchKernelGGL(k_real_mm<float>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart);
+    hipLaunchKernelGGL(k_real_mm<float>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart,
+                       spg);
   else
-    hipLaunchKernelGGL(k_real_mm<double>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart);
+    hipLaunchKernelGGL(k_real_mm<double>, grid, dim3(256), 0, s, g, fa, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff, w.rpart,
+                       spg);
   return hipGetLastError();
 }
 
