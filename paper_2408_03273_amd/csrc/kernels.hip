@@ -10,6 +10,7 @@
 // Flat index k = col*NZ + (nz+mz), col = nx*NY + (ny+my).
 #include <math.h>
 
+#include <algorithm>
 #include <initializer_list>
 
 #include "ewald_internal.h"
@@ -2080,6 +2081,136 @@ DEV void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Lattice images n along one axis that can put b + n L within rc (at most
+// nimg either side): a pair needs |b + n L| < rc on every axis.  The range is
+// widened by 1e-9 L against rounding (a candidate too many only fails the
+// distance test; it also covers the product with 1/L in place of a
+// division).  A NaN offset gives the full range (its distance tests then
+// fail), an infinite one an empty range; both ends stay within
+// [-nimg - 1, nimg + 1] before conversion.
+DEV void image_range(double b, double L, double inv_L, double rc, int nimg, int& lo, int& hi) {
+  const double n = (double)nimg, w = rc + 1e-9 * L;
+  lo = (int)fmin(fmax(ceil((-w - b) * inv_L), -n), n + 1.0);
+  hi = (int)fmax(fmin(floor((w - b) * inv_L), n), -n - 1.0);
+}
+
+// Effective moments of one QM site as stored in qeff: Q, mu, theta (xx xy xz
+// yy yz zz).
+template <typename T>
+struct SiteMoments {
+  T Q, m0, m1, m2, t0, t1, t2, t3, t4, t5;
+};
+
+template <typename T>
+DEV SiteMoments<T> site_moments(const double* qe) {
+  return SiteMoments<T>{(T)qe[0], (T)qe[1], (T)qe[2], (T)qe[3], (T)qe[4],
+                        (T)qe[5], (T)qe[6], (T)qe[7], (T)qe[8], (T)qe[9]};
+}
+
+// Terms of one QM-MM pair within the cutoff: offset (x, y, z) = site - atom
+// (with its lattice image), r2 its squared length, q the MM charge.
+//   BWD != 1: the 10 forward sums into acc[0..9] (phi, grad phi and half the
+//             Hessian of phi at the site);
+//   BWD != 0: dL/dR_site with the effective moments M into acc[OB..OB+2], and
+//             with mm_side the MM atom's terms into mm[0..3]: the potential of
+//             M per unit charge, and -q g.
+template <typename T, int BWD>
+DEV void pair_terms(T x, T y, T z, T r2, T q, T a, const SiteMoments<T>& M, double* acc, bool mm_side,
+                    double (&mm)[4]) {
+  constexpr int OB = BWD == 2 ? 10 : 0;
+  const Radial<T> R = radial<T>(r2, a);
+  if (BWD != 1) {
+    acc[0] += (double)(q * R.f1);
+    acc[1] += (double)(-q * x * R.f3);
+    acc[2] += (double)(-q * y * R.f3);
+    acc[3] += (double)(-q * z * R.f3);
+    const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
+    acc[4] += (double)(h5 * x * x - h3);
+    acc[5] += (double)(h5 * x * y);
+    acc[6] += (double)(h5 * x * z);
+    acc[7] += (double)(h5 * y * y - h3);
+    acc[8] += (double)(h5 * y * z);
+    acc[9] += (double)(h5 * z * z - h3);
+  }
+  if (BWD != 0) {
+    // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
+    const T md = M.m0 * x + M.m1 * y + M.m2 * z;
+    const T thx = M.t0 * x + M.t1 * y + M.t2 * z, thy = M.t1 * x + M.t3 * y + M.t4 * z,
+            thz = M.t2 * x + M.t4 * y + M.t5 * z;
+    const T dtd = x * thx + y * thy + z * thz;
+    const T tr = M.t0 + M.t3 + M.t5;
+    const T s1 = -M.Q * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
+    const T s2 = -R.f3;
+    const T s3 = T(3) * R.f5;
+    const double gx = (double)(s1 * x + s2 * M.m0 + s3 * thx), gy = (double)(s1 * y + s2 * M.m1 + s3 * thy),
+                 gz = (double)(s1 * z + s2 * M.m2 + s3 * thz);
+    acc[OB + 0] += (double)q * gx;
+    acc[OB + 1] += (double)q * gy;
+    acc[OB + 2] += (double)q * gz;
+    if (mm_side) {
+      mm[0] = (double)(M.Q * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3);
+      mm[1] = -(double)q * gx;
+      mm[2] = -(double)q * gy;
+      mm[3] = -(double)q * gz;
+    }
+  }
+}
+
+// A wave's pair FIFO in LDS: x, y, z, r^2, q (T) and an atom index per entry.
+template <typename T>
+struct PairFifo {
+  T *x, *y, *z, *r2, *q;
+  int* idx;
+  DEV PairFifo(void* lds, int wave) {
+    x = reinterpret_cast<T*>(lds) + wave * 5 * kPairFifo;
+    y = x + kPairFifo;
+    z = y + kPairFifo;
+    r2 = z + kPairFifo;
+    q = r2 + kPairFifo;
+    idx = reinterpret_cast<int*>(reinterpret_cast<T*>(lds) + 4 * 5 * kPairFifo) + wave * kPairFifo;
+  }
+  // append the hits of the wave's lanes, in lane order, after the count
+  // pending entries; returns the new count (wave-uniform)
+  DEV int append(bool hit, int lane, int count, double dx, double dy, double dz, double r2d, double qd, int i) {
+    const unsigned long long mask = __ballot(hit);
+    if (hit) {
+      const int pos = count + (int)__popcll(mask & ((1ull << lane) - 1ull));
+      x[pos] = (T)dx;
+      y[pos] = (T)dy;
+      z[pos] = (T)dz;
+      r2[pos] = (T)r2d;
+      q[pos] = (T)qd;
+      idx[pos] = i;
+    }
+    return count + (int)__popcll(mask);
+  }
+  // after the first 64 entries were evaluated: move the remaining count - 64
+  // (< 64) to the front; returns the new count
+  DEV int drop64(int lane, int count) {
+    T sx = 0, sy = 0, sz = 0, s2 = 0, sq = 0;
+    int si = 0;
+    const bool mv = lane < count - 64;
+    if (mv) {
+      sx = x[64 + lane];
+      sy = y[64 + lane];
+      sz = z[64 + lane];
+      s2 = r2[64 + lane];
+      sq = q[64 + lane];
+      si = idx[64 + lane];
+    }
+    wave_lds_sync();
+    if (mv) {
+      x[lane] = sx;
+      y[lane] = sy;
+      z[lane] = sz;
+      r2[lane] = s2;
+      q[lane] = sq;
+      idx[lane] = si;
+    }
+    return count - 64;
+  }
+};
+
 // One item: QM site j of frame fr against MM chunk ci (of nchunk, chunk atoms
 // each); red holds 4 x 13 doubles of LDS, fifo pair_fifo_bytes<T>() bytes.
 template <typename T, int BWD>
@@ -2102,122 +2233,64 @@ DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchu
   double acc[NV];
 #pragma unroll
   for (int t = 0; t < NV; t++) acc[t] = 0.0;
-  T Qe = 0, m0 = 0, m1 = 0, m2 = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
-  if (BWD) {
-    const double* qe = qeff + 10 * (size_t)r;
-    Qe = (T)qe[0]; m0 = (T)qe[1]; m1 = (T)qe[2]; m2 = (T)qe[3];
-    t0 = (T)qe[4]; t1 = (T)qe[5]; t2 = (T)qe[6]; t3 = (T)qe[7]; t4 = (T)qe[8]; t5 = (T)qe[9];
-  }
+  const SiteMoments<T> M = BWD ? site_moments<T>(qeff + 10 * (size_t)r) : SiteMoments<T>{};
   const double* mx_ = mm4 + fr.moff;
   const double* my_ = mm4 + (size_t)cap_mm + fr.moff;
   const double* mz_ = mm4 + (size_t)2 * cap_mm + fr.moff;
   const double* mq_ = mm4 + (size_t)3 * cap_mm + fr.moff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // this wave's FIFO: x, y, z, r^2, q (T) and the atom index
-  T* fx = reinterpret_cast<T*>(fifo) + wave * 5 * kPairFifo;
-  T* fy = fx + kPairFifo;
-  T* fz = fy + kPairFifo;
-  T* fr2 = fz + kPairFifo;
-  T* fq = fr2 + kPairFifo;
-  int* fi = reinterpret_cast<int*>(reinterpret_cast<T*>(fifo) + 4 * 5 * kPairFifo) + wave * kPairFifo;
+  PairFifo<T> ff(fifo, wave);
   // evaluate the first n (<= 64) pairs of the FIFO, one per lane
   auto evaluate = [&](int n) {
     if (lane >= n) return;
-    const T x = fx[lane], y = fy[lane], z = fz[lane], q = fq[lane];
-    const int i = fi[lane];
-    const Radial<T> R = radial<T>(fr2[lane], a);
-    if (BWD != 1) {
-      acc[0] += (double)(q * R.f1);
-      acc[1] += (double)(-q * x * R.f3);
-      acc[2] += (double)(-q * y * R.f3);
-      acc[3] += (double)(-q * z * R.f3);
-      const T h5 = T(1.5) * q * R.f5, h3 = T(0.5) * q * R.f3;
-      acc[4] += (double)(h5 * x * x - h3);
-      acc[5] += (double)(h5 * x * y);
-      acc[6] += (double)(h5 * x * z);
-      acc[7] += (double)(h5 * y * y - h3);
-      acc[8] += (double)(h5 * y * z);
-      acc[9] += (double)(h5 * z * z - h3);
-    }
-    if (BWD != 0) {
-      // g = Q psi1 + 2 mu.psi2 + 3 theta:psi3 (theta full symmetric)
-      const T md = m0 * x + m1 * y + m2 * z;
-      const T thx = t0 * x + t1 * y + t2 * z, thy = t1 * x + t3 * y + t4 * z, thz = t2 * x + t4 * y + t5 * z;
-      const T dtd = x * thx + y * thy + z * thz;
-      const T tr = t0 + t3 + t5;
-      const T s1 = -Qe * R.f3 + T(3) * md * R.f5 + T(1.5) * tr * R.f5 - T(7.5) * dtd * R.f7;
-      const T s2 = -R.f3;
-      const T s3 = T(3) * R.f5;
-      const double gx = (double)(s1 * x + s2 * m0 + s3 * thx), gy = (double)(s1 * y + s2 * m1 + s3 * thy),
-                   gz = (double)(s1 * z + s2 * m2 + s3 * thz);
-      acc[OB + 0] += (double)q * gx;
-      acc[OB + 1] += (double)q * gy;
-      acc[OB + 2] += (double)q * gz;
-      if (rpart) {
-        // MM side: potential of the effective moments per unit charge, and -q g
-        double* o = rpart + (size_t)(fr.moff + i) * 4;
-        atomicAdd(&o[0], (double)(Qe * R.f1 - md * R.f3 + T(1.5) * dtd * R.f5 - T(0.5) * tr * R.f3));
-        atomicAdd(&o[1], -(double)q * gx);
-        atomicAdd(&o[2], -(double)q * gy);
-        atomicAdd(&o[3], -(double)q * gz);
-      }
+    double mm[4];
+    pair_terms<T, BWD>(ff.x[lane], ff.y[lane], ff.z[lane], ff.r2[lane], ff.q[lane], a, M, acc, rpart != nullptr, mm);
+    if (BWD != 0 && rpart) {
+      double* o = rpart + (size_t)(fr.moff + ff.idx[lane]) * 4;
+      for (int t = 0; t < 4; t++) atomicAdd(&o[t], mm[t]);
     }
   };
   int count = 0;  // pending pairs of this wave (wave-uniform)
-  const int n1_ = 2 * fr.nimg + 1;
   for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
     const int i = base + threadIdx.x;
-    const bool valid = i < i1;
     double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
-    if (valid) {
+    // this lane's candidate lattice images (per axis; with the minimum image
+    // only, one candidate or none when an axis offset already exceeds rc)
+    int lx = 0, hx = -1, ly = 0, hy = -1, lz = 0, hz = -1;
+    if (i < i1) {
       bx = X - mx_[i];
       by = Y - my_[i];
       bz = Zc - mz_[i];
       qd = mq_[i];
       min_image(bx, by, bz, fr);
+      image_range(bx, fr.box[0], fr.inv_box[0], g.rcut, fr.nimg, lx, hx);
+      image_range(by, fr.box[1], fr.inv_box[1], g.rcut, fr.nimg, ly, hy);
+      image_range(bz, fr.box[2], fr.inv_box[2], g.rcut, fr.nimg, lz, hz);
     }
-    for (int im_ = 0; im_ < n1_ * n1_ * n1_; im_++) {
-      // lattice images within the cutoff (only the minimum image when rc <= L/2)
-      const int ix_ = im_ / (n1_ * n1_) - fr.nimg, iy_ = (im_ / n1_) % n1_ - fr.nimg, iz_ = im_ % n1_ - fr.nimg;
-      const double dx = bx + ix_ * fr.box[0], dy = by + iy_ * fr.box[1], dz = bz + iz_ * fr.box[2];
-      const double r2d = dx * dx + dy * dy + dz * dz;
-      const bool hit = valid && r2d < rc2 && r2d != 0.0;
-      const unsigned long long mask = __ballot(hit);
-      if (hit) {
-        const int pos = count + (int)__popcll(mask & ((1ull << lane) - 1ull));
-        fx[pos] = (T)dx;
-        fy[pos] = (T)dy;
-        fz[pos] = (T)dz;
-        fr2[pos] = (T)r2d;
-        fq[pos] = (T)qd;
-        fi[pos] = i;
+    int ix_ = lx, iy_ = ly, iz_ = lz;
+    bool more = lx <= hx && ly <= hy && lz <= hz;
+    while (__ballot(more)) {  // wave-uniform: until every lane has tested its candidates
+      bool hit = false;
+      double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
+      if (more) {
+        dx = bx + ix_ * fr.box[0];
+        dy = by + iy_ * fr.box[1];
+        dz = bz + iz_ * fr.box[2];
+        r2d = dx * dx + dy * dy + dz * dz;
+        hit = r2d < rc2 && r2d != 0.0;
+        if (++iz_ > hz) {
+          iz_ = lz;
+          if (++iy_ > hy) {
+            iy_ = ly;
+            more = ++ix_ <= hx;
+          }
+        }
       }
-      count += (int)__popcll(mask);
+      count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i);
       if (count >= 64) {
         wave_lds_sync();
         evaluate(64);
-        // move the remaining count - 64 (< 64) pairs to the front
-        T sx = 0, sy = 0, sz = 0, s2 = 0, sq = 0;
-        int si = 0;
-        const bool mv = lane < count - 64;
-        if (mv) {
-          sx = fx[64 + lane];
-          sy = fy[64 + lane];
-          sz = fz[64 + lane];
-          s2 = fr2[64 + lane];
-          sq = fq[64 + lane];
-          si = fi[64 + lane];
-        }
-        wave_lds_sync();
-        if (mv) {
-          fx[lane] = sx;
-          fy[lane] = sy;
-          fz[lane] = sz;
-          fr2[lane] = s2;
-          fq[lane] = sq;
-          fi[lane] = si;
-        }
-        count -= 64;
+        count = ff.drop64(lane, count);
       }
     }
   }
@@ -2253,12 +2326,145 @@ __global__ __launch_bounds__(256) void k_real_qm(Grid g, FrameArg fa, int chunk,
                        det, red, fifo);
 }
 
+// Real space with lattice images (a cutoff beyond half a box length, where
+// every (site, atom) pair has several images within it), forward and adjoint
+// with both sides of each pair in one pass, so erfc and exp are evaluated once
+// per pair.  A block takes 256 MM atoms and 4 * spw QM sites, each wave spw of
+// them, site by site: the wave runs over the block's atoms 64 at a time,
+// compacts the pairs within the cutoff into its LDS FIFO and evaluates them 64
+// at a time, one per lane; at the end of a site it reduces the site's 13 sums
+// over its lanes and adds them to the site's accumulator row.  The MM-side
+// terms of each pair are added in LDS to the atom's four values, which go to
+// rpart (zeroed beforehand) once per block.  No block barrier inside the site
+// loop: waves with less work leave early.
+template <typename T>
+__global__ __launch_bounds__(256) void k_real_img(Grid g, FrameArg fa, int spw, const double* __restrict__ qm4,
+                                                  int cap_qm, const double* __restrict__ mm4, int cap_mm,
+                                                  const double* __restrict__ qeff, double* __restrict__ qacc,
+                                                  double* __restrict__ rpart) {
+  __shared__ double mmacc[4 * 256];  // [term][atom of the block]
+  __shared__ __align__(16) char fifo[pair_fifo_bytes<T>()];
+  const int f = blockIdx.z;
+  const FrameDev fr = get_frame(fa, f);
+  const int a0 = blockIdx.x * 256, a1 = min(fr.nm, a0 + 256);
+  if (a0 >= fr.nm || (int)blockIdx.y * 4 * spw >= fr.nq) return;  // block-uniform
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = 0; t < 4; t++) mmacc[t * 256 + tid] = 0.0;
+  __syncthreads();
+  const T a = (T)g.alpha;
+  const double rc2 = g.rcut * g.rcut;
+  const double* mx_ = mm4 + fr.moff;
+  const double* my_ = mm4 + (size_t)cap_mm + fr.moff;
+  const double* mz_ = mm4 + (size_t)2 * cap_mm + fr.moff;
+  const double* mq_ = mm4 + (size_t)3 * cap_mm + fr.moff;
+  PairFifo<T> ff(fifo, wave);
+  const int jw0 = ((int)blockIdx.y * 4 + wave) * spw, jw1 = min(fr.nq, jw0 + spw);
+  for (int j = jw0; j < jw1; j++) {  // wave-uniform
+    const int r = fr.qoff + j;
+    const double X = qm4[r], Y = qm4[(size_t)cap_qm + r], Zc = qm4[(size_t)2 * cap_qm + r];
+    const SiteMoments<T> M = site_moments<T>(qeff + 10 * (size_t)r);
+    double acc[13];
+#pragma unroll
+    for (int t = 0; t < 13; t++) acc[t] = 0.0;
+    auto evaluate = [&](int n) {
+      if (lane >= n) return;
+      double mm[4];
+      pair_terms<T, 2>(ff.x[lane], ff.y[lane], ff.z[lane], ff.r2[lane], ff.q[lane], a, M, acc, true, mm);
+      const int k = ff.idx[lane];
+      for (int t = 0; t < 4; t++) atomicAdd(&mmacc[t * 256 + k], mm[t]);
+    };
+    int count = 0;  // pending pairs of this wave (wave-uniform)
+    for (int base = a0; base < a1; base += 64) {  // wave-uniform
+      const int i = base + lane;
+      double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
+      int lx = 0, hx = -1, ly = 0, hy = -1, lz = 0, hz = -1;
+      if (i < a1) {
+        bx = X - mx_[i];
+        by = Y - my_[i];
+        bz = Zc - mz_[i];
+        qd = mq_[i];
+        min_image(bx, by, bz, fr);
+        image_range(bx, fr.box[0], fr.inv_box[0], g.rcut, fr.nimg, lx, hx);
+        image_range(by, fr.box[1], fr.inv_box[1], g.rcut, fr.nimg, ly, hy);
+        image_range(bz, fr.box[2], fr.inv_box[2], g.rcut, fr.nimg, lz, hz);
+      }
+      int ix_ = lx, iy_ = ly, iz_ = lz;
+      bool more = lx <= hx && ly <= hy && lz <= hz;
+      while (__ballot(more)) {  // wave-uniform: until every lane has tested its candidates
+        bool hit = false;
+        double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
+        if (more) {
+          dx = bx + ix_ * fr.box[0];
+          dy = by + iy_ * fr.box[1];
+          dz = bz + iz_ * fr.box[2];
+          r2d = dx * dx + dy * dy + dz * dz;
+          hit = r2d < rc2 && r2d != 0.0;
+          if (++iz_ > hz) {
+            iz_ = lz;
+            if (++iy_ > hy) {
+              iy_ = ly;
+              more = ++ix_ <= hx;
+            }
+          }
+        }
+        count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i - a0);
+        if (count >= 64) {
+          wave_lds_sync();
+          evaluate(64);
+          count = ff.drop64(lane, count);
+        }
+      }
+    }
+    wave_lds_sync();
+    evaluate(count);
+    wave_lds_sync();  // the FIFO is refilled from the front for the next site
+#pragma unroll
+    for (int t = 0; t < 13; t++) acc[t] = wave_sum(acc[t]);
+    if (lane == 0) {
+      double* qa = qacc + (size_t)r * QA_STRIDE;
+      atomicAdd(&qa[QA_PHI_SR], acc[0]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_DPHI_SR + t], acc[1 + t]);
+      for (int t = 0; t < 6; t++) atomicAdd(&qa[QA_H_SR + t], acc[4 + t]);
+      for (int t = 0; t < 3; t++) atomicAdd(&qa[QA_G_QMMM_SR + t], acc[10 + t]);
+    }
+  }
+  __syncthreads();  // every wave's LDS adds are done
+  if (a0 + tid < a1) {
+    double* o = rpart + (size_t)(fr.moff + a0 + tid) * 4;
+    for (int t = 0; t < 4; t++) atomicAdd(&o[t], mmacc[t * 256 + tid]);
+  }
+}
+
+// waves the lattice-image kernel aims for (sites per wave are sized to reach it)
+static constexpr long kImgWaves = 4096;
+
+hipError_t launch_real_img(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
+                           int fp32, Work& w, hipStream_t s) {
+  const int bx = (max_nm + 255) / 256;
+  const long site_waves = (long)bx * fa.n_frames * max_nq;  // waves at one site each
+  const int spw = (int)std::max(1L, site_waves / kImgWaves);
+  dim3 grid(bx, (max_nq + 4 * spw - 1) / (4 * spw), fa.n_frames);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_img<float>, grid, dim3(256), 0, s, g, fa, spw, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff,
+                       w.qacc, w.rpart);
+  else
+    hipLaunchKernelGGL(k_real_img<double>, grid, dim3(256), 0, s, g, fa, spw, w.qm4, cap_qm, w.mm4, cap_mm, w.qeff,
+                       w.qacc, w.rpart);
+  return hipGetLastError();
+}
+
 static constexpr int kRealChunk = 2048;
 
 hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max_nm, int cap_qm, int cap_mm,
                           int backward, int fp32, Work& w, hipStream_t s, double* rpart, int mm_groups) {
   if (max_nq == 0 || max_nm == 0) return hipSuccess;
-  int chunk = kRealChunk;
+  // lattice images, forward and adjoint with the MM side: one pass over each
+  // pair for both sides (deterministic plans keep the fixed-order kernels)
+  if (backward == 2 && rpart && mm_groups > 0 && !w.det_real)
+    return launch_real_img(g, fa, max_nq, max_nm, cap_qm, cap_mm, fp32, w, s);
+  // with lattice images (mm_groups > 0) a (site, atom) pair tests up to 8
+  // images: smaller chunks keep enough blocks in flight
+  int chunk = mm_groups > 0 ? kRealChunk / 4 : kRealChunk;
   double* det = w.det_real;
   if (det) {
     // at most kDetChunks partial rows per site; the MM-side terms come from
@@ -2294,16 +2500,6 @@ hipError_t launch_real_qm(const Grid& g, const FrameArg& fa, int max_nq, int max
   return launch_real_mm(g, fa, max_nq, max_nm, cap_qm, cap_mm, fp32, w, s, det ? 1 : mm_groups);
 }
 
-// Lattice images n along one axis that can put b + n L within rc (at most
-// nimg either side): a pair needs |b + n L| < rc on every axis.  A NaN offset
-// gives the full range (its distance tests then fail), an infinite one an
-// empty range; both ends stay within [-nimg - 1, nimg + 1] before conversion.
-DEV void image_range(double b, double L, double rc, int nimg, int& lo, int& hi) {
-  const double n = (double)nimg;
-  lo = (int)fmin(fmax(ceil((-rc - b) / L), -n), n + 1.0);
-  hi = (int)fmax(fmin(floor((rc - b) / L), n), -n - 1.0);
-}
-
 // MM side of the QM-MM real-space sum (backward): dL/dR_i and dL/dq_i with
 // the effective moments, one thread per MM atom looping over the QM sites of
 // its block's site group (blockIdx.y of gridDim.y groups), for each site over
@@ -2333,9 +2529,9 @@ __global__ __launch_bounds__(256) void k_real_mm(Grid g, FrameArg fa, const doub
     double bx = qm4[r] - X, by = qm4[(size_t)cap_qm + r] - Y, bz = qm4[(size_t)2 * cap_qm + r] - Zc;
     min_image(bx, by, bz, fr);
     int lx, hx, ly, hy, lz, hz;
-    image_range(bx, fr.box[0], g.rcut, fr.nimg, lx, hx);
-    image_range(by, fr.box[1], g.rcut, fr.nimg, ly, hy);
-    image_range(bz, fr.box[2], g.rcut, fr.nimg, lz, hz);
+    image_range(bx, fr.box[0], fr.inv_box[0], g.rcut, fr.nimg, lx, hx);
+    image_range(by, fr.box[1], fr.inv_box[1], g.rcut, fr.nimg, ly, hy);
+    image_range(bz, fr.box[2], fr.inv_box[2], g.rcut, fr.nimg, lz, hz);
     for (int ix_ = lx; ix_ <= hx; ix_++)
       for (int iy_ = ly; iy_ <= hy; iy_++)
         for (int iz_ = lz; iz_ <= hz; iz_++) {
