@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; FP64 matrix cores: the same
+FP32_PEAK_TFLOPS = 157.3  # FP32 vector (packed)
 HBM_PEAK_GBS = 8000.0
 METRIC = "QM/MM Ewald fwd+bwd frames/s at 35k MM charges; % FP64 roofline vs plain path"
 PROFILES = os.path.join(ROOT, "profiles")
@@ -66,6 +67,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-path and batched measurements")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles instead of timing candidates")
+    ap.add_argument("--f3-only", action="store_true",
+                    help="only the rc ~ L measurement of the c3 frame (its JSON object), e.g. under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device-to-device copy of 256 MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -83,6 +86,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.f3_only:
+        print(json.dumps(_f3(dev)), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -147,8 +153,8 @@ def main():
     # also forms the potential, dE/dq, and the nz-weighted sums).
     per = {k: dict(count=v["count"], avg_us=1e3 * v["total_ms"] / max(v["count"], 1),
                    ms_per_step=v["total_ms"] / args.steps) for k, v in hot_kern.items()}
-    flops = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm, "hot_step": 10.0 * nh * s.nm}
-    executed = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 8.0 * nh * s.nm, "hot_step": 12.0 * nh * s.nm}
+    flops = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 6.0 * nh * s.nm}
+    executed = {"sfac_mm": 4.0 * nh * s.nm, "force_mm": 8.0 * nh * s.nm}
     hot = {k: per[k] for k in flops if k in per}
     dom = max(hot, key=lambda k: hot[k]["ms_per_step"])
     achieved = flops[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12
@@ -216,6 +222,7 @@ def main():
         extra["region_c3"] = _region_c3(make_plan(True), inputs, s)
         extra["fp32_recip"] = _fp32_recip(make_plan(False), s, inputs, cache, args.no_autotune)
         extra["per_config"] = _per_config(dev, args.no_autotune)
+        extra["per_config"]["f3_c3_rc_near_L"] = _f3(dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -537,6 +544,115 @@ def _batch_variants(dev, cfg, nframes, variants, steps):
             r["max_rel_err"] = float(f"{max(err.values()):.2e}")
         out[prec] = r
         plan.close()
+    return out
+
+
+def real_flops_from_profiles(precision: str, src_hash: str):
+    """Executed FP64 and FP32 flops per real-space pair (both sides of the
+    pair) from the committed counter summary of the lattice-image kernel, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, "real_img_f3.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    return d.get("per_pair", {}).get(precision)
+
+
+def _f3(dev, steps=20):
+    """The paper's regime: the c3 frame with a real-space cutoff of 0.95 of the
+    smallest box edge and alpha, kmax from the parameter suggestion at 1e-8
+    (real space sums up to 8 lattice images per pair and dominates; the k-set
+    is small).  FP64 and FP32 real space (FP64 accumulation): the autograd
+    step, the same frame as a graph-replayed one-frame batch, the real-space
+    launch alone (HIP events), pairs within the cutoff per second, and the
+    real-space kernel against the VALU peak with its executed flops per pair
+    (hardware counters: FP64 against 78.6, FP32 against 157.3 TFLOP/s)."""
+    import numpy as np
+    import torch
+
+    from paper_2408_03273_amd import workloads as wl
+    from paper_2408_03273_amd.ewald import EwaldConfig, Plan, ewald, suggest_params
+
+    s = wl.make_config(3)
+    rc = 0.95 * float(np.min(s.box))
+    alpha, kmax = suggest_params(s.box, rc, 1e-8)
+    # pairs (site, atom, lattice image) within the cutoff
+    d = s.qm_pos[:, None, :] - s.mm_pos[None, :, :]
+    d -= s.box * np.round(d / s.box)
+    pairs = 0
+    for n in np.ndindex(3, 3, 3):
+        e = d + (np.array(n) - 1) * s.box
+        pairs += int(((e * e).sum(-1) < rc * rc).sum())
+    del d
+    src_hash = kernel_source_hash()
+    out = dict(workload=f"c3 frame, rc = 0.95 L = {rc:.1f} A, alpha {alpha:.4f}, kmax {list(kmax)} "
+                        "(parameters for 1e-8), fwd+bwd via autograd",
+               n_mm=s.nm, n_qm=s.nq, rcut=rc, alpha=round(alpha, 6), kmax=list(kmax),
+               n_kvec_half_space=n_half_space(kmax), real_space_pairs=pairs)
+    x = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)
+         for a in (s.qm_pos, s.Q, s.mu, s.theta, s.mm_pos, s.q)]
+    xd = [t.detach() for t in x]
+    desc = [dict(box=s.box, n_qm=s.nq, n_mm=s.nm, qm_offset=0, mm_offset=0)]
+    ref = None
+    for prec in ("fp64", "fp32_real"):
+        r = {}
+        for prof in (False, True):
+            plan = Plan(EwaldConfig(box=tuple(s.box), alpha=alpha, rcut=rc, kmax=kmax, max_qm=s.nq, max_mm=s.nm,
+                                    precision=prec, profile=prof))
+
+            def step():
+                for t in x:
+                    t.grad = None
+                ewald(plan, *x)[0].backward()
+
+            for _ in range(3):
+                step()
+            torch.cuda.synchronize()
+            if prof:
+                plan.profile_report()
+                for _ in range(steps):
+                    step()
+                torch.cuda.synchronize()
+                k = plan.profile_report()["real_qm"]
+                r["real_space_us"] = round(1e3 * k["total_ms"] / k["count"], 2)
+            else:
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    step()
+                torch.cuda.synchronize()
+                r["ms_per_frame_fwd_bwd"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+                ob = plan.batch(desc, *xd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    plan.batch(desc, *xd, out=ob)
+                torch.cuda.synchronize()
+                r["graph_replay_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+                if ref is None:
+                    ref = {k: v.clone() for k, v in ob.items()}
+                else:
+                    err = _rel_errs(ob, ref)
+                    r["max_rel_err_vs_fp64"] = float(f"{max(err.values()):.2e}")
+            plan.close()
+        t = r["real_space_us"] * 1e-6
+        r["pairs_per_s"] = float(f"{pairs / t:.4g}")
+        fl = real_flops_from_profiles(prec, src_hash)
+        if fl is not None:
+            f64, f32 = fl["fp64"] * pairs, fl["fp32"] * pairs
+            # share of the launch the VALU would need at peak for these flops
+            frac = (f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS) / 1e12 / t
+            r["roofline"] = dict(bound="alu", kernel="real space, lattice images (k_real_img)",
+                                 executed_fp64_flops_per_pair=fl["fp64"], executed_fp32_flops_per_pair=fl["fp32"],
+                                 achieved_fp64_tflops=round(f64 / t / 1e12, 3),
+                                 achieved_fp32_tflops=round(f32 / t / 1e12, 3),
+                                 peak_fp64_tflops=FP64_PEAK_TFLOPS, peak_fp32_tflops=FP32_PEAK_TFLOPS,
+                                 frac=round(frac, 4))
+        else:
+            r["roofline"] = None
+        out[prec] = r
     return out
 
 

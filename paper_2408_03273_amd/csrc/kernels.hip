@@ -2269,29 +2269,32 @@ DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchu
     }
     int ix_ = lx, iy_ = ly, iz_ = lz;
     bool more = lx <= hx && ly <= hy && lz <= hz;
-    while (__ballot(more)) {  // wave-uniform: until every lane has tested its candidates
-      bool hit = false;
-      double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
-      if (more) {
-        dx = bx + ix_ * fr.box[0];
-        dy = by + iy_ * fr.box[1];
-        dz = bz + iz_ * fr.box[2];
-        r2d = dx * dx + dy * dy + dz * dz;
-        hit = r2d < rc2 && r2d != 0.0;
-        if (++iz_ > hz) {
-          iz_ = lz;
-          if (++iy_ > hy) {
-            iy_ = ly;
-            more = ++ix_ <= hx;
+    for (;;) {  // wave-uniform
+      // test candidates until 64 pairs are pending or every lane is done
+      // (the accumulators stay out of this loop)
+      while (count < 64 && __ballot(more)) {
+        bool hit = false;
+        double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
+        if (more) {
+          dx = bx + ix_ * fr.box[0];
+          dy = by + iy_ * fr.box[1];
+          dz = bz + iz_ * fr.box[2];
+          r2d = dx * dx + dy * dy + dz * dz;
+          hit = r2d < rc2 && r2d != 0.0;
+          if (++iz_ > hz) {
+            iz_ = lz;
+            if (++iy_ > hy) {
+              iy_ = ly;
+              more = ++ix_ <= hx;
+            }
           }
         }
+        count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i);
       }
-      count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i);
-      if (count >= 64) {
-        wave_lds_sync();
-        evaluate(64);
-        count = ff.drop64(lane, count);
-      }
+      if (count < 64) break;
+      wave_lds_sync();
+      evaluate(64);
+      count = ff.drop64(lane, count);
     }
   }
   wave_lds_sync();
@@ -2390,29 +2393,32 @@ __global__ __launch_bounds__(256) void k_real_img(Grid g, FrameArg fa, int spw, 
       }
       int ix_ = lx, iy_ = ly, iz_ = lz;
       bool more = lx <= hx && ly <= hy && lz <= hz;
-      while (__ballot(more)) {  // wave-uniform: until every lane has tested its candidates
-        bool hit = false;
-        double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
-        if (more) {
-          dx = bx + ix_ * fr.box[0];
-          dy = by + iy_ * fr.box[1];
-          dz = bz + iz_ * fr.box[2];
-          r2d = dx * dx + dy * dy + dz * dz;
-          hit = r2d < rc2 && r2d != 0.0;
-          if (++iz_ > hz) {
-            iz_ = lz;
-            if (++iy_ > hy) {
-              iy_ = ly;
-              more = ++ix_ <= hx;
+      for (;;) {  // wave-uniform
+        // test candidates until 64 pairs are pending or every lane is done
+        // (the accumulators stay out of this loop)
+        while (count < 64 && __ballot(more)) {
+          bool hit = false;
+          double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
+          if (more) {
+            dx = bx + ix_ * fr.box[0];
+            dy = by + iy_ * fr.box[1];
+            dz = bz + iz_ * fr.box[2];
+            r2d = dx * dx + dy * dy + dz * dz;
+            hit = r2d < rc2 && r2d != 0.0;
+            if (++iz_ > hz) {
+              iz_ = lz;
+              if (++iy_ > hy) {
+                iy_ = ly;
+                more = ++ix_ <= hx;
+              }
             }
           }
+          count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i - a0);
         }
-        count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i - a0);
-        if (count >= 64) {
-          wave_lds_sync();
-          evaluate(64);
-          count = ff.drop64(lane, count);
-        }
+        if (count < 64) break;
+        wave_lds_sync();
+        evaluate(64);
+        count = ff.drop64(lane, count);
       }
     }
     wave_lds_sync();
