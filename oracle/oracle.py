@@ -25,7 +25,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ewald_oracle.c")
-_LIB = os.path.join(_HERE, "libewald_oracle.so")
+_DEFAULT_LIB = os.path.join(_HERE, "libewald_oracle.so")
+# MPEWALD_ORACLE_LIB names another build of the oracle (e.g. a sanitized one), used as it is
+_LIB = os.environ.get("MPEWALD_ORACLE_LIB") or _DEFAULT_LIB
 
 ENERGY_NAMES = ("total", "qmmm_sr", "qmmm_lr", "qmmm_bg", "qq_sr", "qq_lr", "qq_self", "qq_bg")
 
@@ -41,7 +43,7 @@ class _Params(ctypes.Structure):
     ]
 
 
-def build(src: str = _SRC, out: str = _LIB, extra_flags: tuple = ()) -> str:
+def build(src: str = _SRC, out: str = _DEFAULT_LIB, extra_flags: tuple = ()) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, generic x86-64)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-fno-fast-math",
            "-ffp-contract=off", *extra_flags, "-o", out + ".tmp", src, "-lm"]
@@ -56,8 +58,8 @@ _lib_cache: dict = {}
 def load(path: str = _LIB) -> ctypes.CDLL:
     if path in _lib_cache:
         return _lib_cache[path]
-    if not os.path.exists(path) or (path == _LIB and os.path.getmtime(path) < os.path.getmtime(_SRC)):
-        if path != _LIB:
+    if not os.path.exists(path) or (path == _DEFAULT_LIB and os.path.getmtime(path) < os.path.getmtime(_SRC)):
+        if path != _DEFAULT_LIB:
             raise FileNotFoundError(path)
         build()
     lib = ctypes.CDLL(path)

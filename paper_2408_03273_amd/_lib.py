@@ -5,7 +5,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmpewald.so")
+# MPEWALD_LIB names another build of the library (e.g. one with a sanitized host pass)
+LIB_PATH = os.environ.get("MPEWALD_LIB") or os.path.join(_HERE, "libmpewald.so")
 
 EWALD_OK = 0
 EWALD_ERR_ARG = -1

@@ -20,15 +20,18 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile every source to an object, then link the shared library."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 2, out: str = LIB, objdir: str | None = None,
+          extra_flags: tuple = ()) -> str:
+    """Compile every source to an object, then link the shared library (out).
+    extra_flags are added to every compile (e.g. host-pass-only options given
+    as "-Xarch_host", option pairs)."""
+    objdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     # MFMA accumulators in ordinary VGPRs (gfx950 allows either file): keeps
     # loop-carried accumulators from being copied between AGPRs and VGPRs
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form=1", "-Wall", "-Wno-unused-function",
-             "-Wno-unknown-pragmas"]
+             "-Wno-unknown-pragmas", *extra_flags]
     procs = []
     objs = []
     for src in SOURCES:
@@ -40,8 +43,8 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     errs = []
     for src, p in procs:
-        out, _ = p.communicate()
-        text = out.decode(errors="replace")
+        log, _ = p.communicate()
+        text = log.decode(errors="replace")
         # the host pass does not know the gfx feature flag; that warning is harmless
         lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln]
         if p.returncode != 0:
@@ -50,11 +53,11 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
             print("\n".join(lines))
     if errs:
         raise RuntimeError("HIP build failed:\n" + "\n".join(errs))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -59,10 +59,11 @@ struct ewald_plan {
   // batched graph state
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  // second stream for the adjoint chain that runs beside the forward chain
-  hipStream_t aux = nullptr, gaux = nullptr;
+  // second stream for the adjoint chain that runs beside the forward chain,
+  // third for a single frame's all-pairs real space (from the start)
+  hipStream_t aux = nullptr, gaux = nullptr, aux2 = nullptr, gaux2 = nullptr;
   int serial = 0;  // run the adjoint chain on the caller's stream (isolated kernel timings)
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   hipEvent_t ev_qside = nullptr, ev_mtab = nullptr;  // QM structure factors done; MM tables done
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
@@ -207,8 +208,11 @@ void free_plan(ewald_plan* pl) {
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   if (pl->aux) (void)hipStreamDestroy(pl->aux);
   if (pl->gaux) (void)hipStreamDestroy(pl->gaux);
+  if (pl->aux2) (void)hipStreamDestroy(pl->aux2);
+  if (pl->gaux2) (void)hipStreamDestroy(pl->gaux2);
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->ev_join2) (void)hipEventDestroy(pl->ev_join2);
   if (pl->ev_qside) (void)hipEventDestroy(pl->ev_qside);
   if (pl->ev_mtab) (void)hipEventDestroy(pl->ev_mtab);
   for (auto& r : pl->prof_pending) {
@@ -494,7 +498,7 @@ ewald_status_t join_to(ewald_plan* pl, hipStream_t from, hipStream_t to) {
 // structure factor (each hot loop on the matrix cores or the vector units as
 // the plan's tiles choose); both need only the phase tables and the QM
 // structure factors.
-ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, const double* Q, const double* mu,
+ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, hipStream_t aux2, const double* qm_xyz, const double* Q, const double* mu,
                            const double* theta, const double* mm_xyz, const double* mm_q, double2* smm,
                            size_t smm_stride, double* energy, double* phi, double* efield, double* efgrad,
                            double* site, double* g_qm_xyz, double* g_Q, double* g_mu, double* g_theta,
@@ -508,6 +512,24 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   if (st != EWALD_OK) return st;
   st = fork_to(pl, q.s, aux);
   if (st != EWALD_OK) return st;
+  // a single frame's all-pairs real space (forward, QM- and MM-side adjoint
+  // in one pass) needs only the staged positions and unit effective moments:
+  // on a third stream from here it fills the GPU while the phase tables and
+  // QM structure factors are built (the GPU is far from full then), instead
+  // of following the adjoint (FP64 vector work inside the hot-loop window
+  // delays the matrix-core issue)
+  const bool real_early = q.fa.n_frames == 1 && !q.cells;
+  if (real_early) {
+    Seq qr = q;
+    qr.s = aux2;
+    const Seq& q_ = qr;
+    {
+      const Seq& q = q_;
+      HIPCHK(hipStreamWaitEvent(q.s, pl->ev_fork, 0));
+      LCHK(launch_real_qm(g, q.fa, q.max_nq, q.max_nm, pl->cap_qm, pl->cap_mm, 2, q.fp32, w, q.s, w.rpart,
+                          q.mm_groups));
+    }
+  }
   {
     Seq qa = q;
     qa.s = aux;
@@ -549,7 +571,7 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
       if (q.cells) {
         LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 0, q.fp32, w, q.s));
         LCHK(launch_real_cells(g, q.fa, q.max_nq, pl->cap_qm, pl->cap_mm, 1, q.fp32, w, q.s));
-      } else {
+      } else if (!real_early) {
         // one pass: QM side per (site, MM chunk) block, the MM-side terms of
         // each pair into rpart (zeroed by prep; in deterministic mode the
         // launcher takes them from the per-atom kernel instead)
@@ -566,6 +588,10 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, const double* qm_xyz, 
   if (st != EWALD_OK) return st;
   st = join_to(pl, aux, q.s);
   if (st != EWALD_OK) return st;
+  if (real_early && aux2 != q.s) {
+    HIPCHK(hipEventRecord(pl->ev_join2, aux2));
+    HIPCHK(hipStreamWaitEvent(q.s, pl->ev_join2, 0));
+  }
   LCHK(launch_finish_fused(g, pl->t, q.fa, q.max_nm, pl->cap_mm, Q, mu, theta, q.qmqm, energy, phi, efield, efgrad,
                            site, g_mm_xyz, g_mm_q, g_qm_xyz, g_Q, g_mu, g_theta, w, q.s));
   return EWALD_OK;
@@ -749,8 +775,10 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     return fail(EWALD_ERR_HIP, "hipMemcpy failed");
   }
   if (hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&pl->aux2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_qside, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&pl->ev_mtab, hipEventDisableTiming) != hipSuccess) {
     free_plan(pl);
@@ -816,7 +844,7 @@ ewald_status_t ewald_forward(ewald_plan* plan, int n_qm, const double* qm_xyz, c
   if (ctx && !q.plain) {
     plan->t.kc = choose_kc(plan, n_mm);
     CtxView cv = ctx_view(plan->g, ctx, n_qm, n_mm);
-    st = seq_fwd_bwd(q, plan->serial ? s : plan->aux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, cv.smm, plan->g.KF, energy, phi, efield,
+    st = seq_fwd_bwd(q, plan->serial ? s : plan->aux, plan->serial ? s : plan->aux2, qm_xyz, Q, mu, theta, mm_xyz, mm_q, cv.smm, plan->g.KF, energy, phi, efield,
                      efgrad, cv.site, cv.gq, cv.gQ, cv.gmu, cv.gth, cv.gm, cv.gmq);
     plan->t = saved;
     return st;
@@ -966,7 +994,7 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   Work& w = plan->w;
   const Grid& g = plan->g;
   if (mode == EWALD_FWD_BWD) {
-    return seq_fwd_bwd(q, plan->serial ? s : plan->gaux, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
+    return seq_fwd_bwd(q, plan->serial ? s : plan->gaux, plan->serial ? s : plan->gaux2, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
                        w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
   }
   ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 0);
@@ -1057,6 +1085,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
   if (!plan->gstream) {
     HIPCHK(hipStreamCreateWithFlags(&plan->gstream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&plan->gaux, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&plan->gaux2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&plan->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&plan->ev_out, hipEventDisableTiming));
   }
