@@ -913,8 +913,15 @@ DEV void sfac_mm_mfma_item(const Grid& g, const FrameDev& fr, int gc, int ac, in
   }
   __syncthreads();
   double2* __restrict__ out = spart + (size_t)(fr.slot_base + ac) * g.NZP * g.NCOL;
-  for (int e = threadIdx.x; e < NCL * g.NZ; e += 256) {
-    const int c = e / g.NZ, iz = e - c * g.NZ;
+  // entry e = c NZ + iz; (c, iz) advance by the block size without a division
+  // per entry (c grows with e, so the first column past the grid ends the loop)
+  const int dc = 256 / g.NZ, diz = 256 - dc * g.NZ;
+  int c = threadIdx.x / g.NZ, iz = threadIdx.x - c * g.NZ;
+  for (int e = threadIdx.x; e < NCL * g.NZ; e += 256, c += dc, iz += diz) {
+    if (iz >= g.NZ) {
+      iz -= g.NZ;
+      c++;
+    }
     const int col = gc * NCL + c;
     if (col >= g.NCOL) break;
     const int nz = iz - g.mz;
@@ -1687,9 +1694,23 @@ DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, i
   const int wave = uniform_int(threadIdx.x >> 6);
   const int ablk = tile * NA;
   if (ablk >= fr.nm) return;  // uniform over the block
-  for (int e = threadIdx.x; e < NA * g.NY; e += 64 * WV) {
-    const int a = e / g.NY, c = e - a * g.NY;
-    eysh[c * ES + a] = tab[(size_t)(fr.moff + min(ablk + a, fr.nm - 1)) * g.NXY + g.NX + c];
+  {
+    // entry e = a NY + c of the tile; (a, c) advance by the block size
+    // without a division per entry (VALU instructions here delay the
+    // matrix-core issue of the other waves on the SIMD)
+    constexpr int NT = 64 * WV;
+    const int da = NT / g.NY, dc = NT - da * g.NY;
+    int a = threadIdx.x / g.NY, c = threadIdx.x - a * g.NY;
+    const double2* __restrict__ src = tab + (size_t)fr.moff * g.NXY + g.NX;
+    for (int e = threadIdx.x; e < NA * g.NY; e += NT) {
+      eysh[c * ES + a] = src[(size_t)min(ablk + a, fr.nm - 1) * g.NXY + c];
+      a += da;
+      c += dc;
+      if (c >= g.NY) {
+        c -= g.NY;
+        a++;
+      }
+    }
   }
   __syncthreads();
   const int a0 = ablk + wave * 16;
