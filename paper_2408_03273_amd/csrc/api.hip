@@ -63,6 +63,8 @@ struct ewald_plan {
   // third for a single frame's all-pairs real space (from the start)
   hipStream_t aux = nullptr, gaux = nullptr, aux2 = nullptr, gaux2 = nullptr;
   int serial = 0;  // run the adjoint chain on the caller's stream (isolated kernel timings)
+  int batch_serial = -1;  // batches on one stream: 1 always, 0 never, -1 by the adjoint's weight size
+  int batch_target = 16384;  // matrix-core forward of a batch: blocks its atom chunking aims for
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   hipEvent_t ev_qside = nullptr, ev_mtab = nullptr;  // QM structure factors done; MM tables done
   hipGraphExec_t gexec = nullptr;
@@ -332,11 +334,14 @@ int choose_a_chunk(const ewald_plan* pl, const std::vector<int>& nms) {
     const long nac = std::max<long>(1, pl->t.fwd_target / kb);
     ac = (total + nac - 1) / nac;
   } else {
-    ac = (kb * total + pl->t.fwd_target - 1) / pl->t.fwd_target;
+    // many frames: more, smaller chunks than one frame would take, so that
+    // the XCD-aware order over (frame, chunk) units balances the XCDs
+    const long tgt = pl->t.fwd_mode == 1 ? pl->batch_target : pl->t.fwd_target;
+    ac = (kb * total + tgt - 1) / tgt;
   }
   ac = ((ac + 63) / 64) * 64;
   if (ac < 64) ac = 64;
-  if (pl->t.a_chunk > 0) ac = pl->t.a_chunk;  // tuned value
+  if (pl->t.a_chunk > 0 && nms.size() == 1) ac = pl->t.a_chunk;  // tuned value (single-frame shapes)
   for (;;) {
     long slots = 0;
     for (int n : nms) slots += (n + ac - 1) / ac;
@@ -655,7 +660,9 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
   // tile overrides for experiments and tests: MPEWALD_BWD = 1|2 (VALU Horner,
   // atoms per lane), 3|4 (matrix cores, 16|32 atoms per wave), 5 (matrix cores
   // with separate epilogue waves) or 6 (matrix cores, y phases in LDS);
-  // MPEWALD_SERIAL = 1 runs the adjoint chain on the caller's stream; MPEWALD_FWD =
+  // MPEWALD_SERIAL = 1 runs the adjoint chain on the caller's stream;
+  // MPEWALD_BATCH_SERIAL = 0|1 overrides the batches' choice of one stream;
+  // MPEWALD_BATCH_TARGET = a batch's forward block count target; MPEWALD_FWD =
   // 0|1 (VALU | matrix cores); MPEWALD_FWD_CT = 1|2|4 (matrix-core column
   // tiles per wave); MPEWALD_FWD_PF = 0|1 (VALU prefetch); MPEWALD_FWD_TARGET =
   // forward block count target; MPEWALD_FWD_XCD, MPEWALD_BWD_XCD = 0|1
@@ -673,6 +680,11 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     }
   }
   if (const char* e = getenv("MPEWALD_SERIAL")) pl->serial = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_BATCH_SERIAL")) pl->batch_serial = atoi(e) ? 1 : 0;
+  if (const char* e = getenv("MPEWALD_BATCH_TARGET")) {
+    const int v = atoi(e);
+    if (v >= 64 && v <= 65536) pl->batch_target = v;
+  }
   if (const char* e = getenv("MPEWALD_FWD_XCD")) pl->t.fwd_xcd = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_BWD_XCD")) pl->t.bwd_xcd = atoi(e) ? 1 : 0;
   if (const char* e = getenv("MPEWALD_KC")) pl->t.kc = std::max(0, atoi(e));
@@ -969,6 +981,20 @@ ewald_status_t ewald_backward(ewald_plan* plan, const void* ctx, int n_qm, const
 
 namespace {
 
+// Whether a batch runs its forward+backward chain on one stream.  With many
+// frames each hot loop fills the GPU by itself, so running them side by side
+// gains little; and the matrix-core adjoint reads one frame's folded weights
+// from L2 in every block of the frame, which the forward's stream of phase
+// rows evicts once the weights pass about half an XCD's 4 MB L2 (measured:
+// 64 frames at kmax 20, 1.1 MB of weights, are 1% faster on two streams; 16
+// frames at kmax 32, 4.4 MB, 2.5% faster on one).
+bool batch_one_stream(const ewald_plan* pl) {
+  if (pl->batch_serial >= 0) return pl->batch_serial != 0;
+  if (pl->t.bwd_ilp < 3) return false;
+  const size_t weights = (size_t)pl->g.NG * pl->g.NK2 * 256 * sizeof(double);
+  return weights > (size_t)2 << 20;
+}
+
 ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int cells, int mm_groups, int max_nq,
                              int max_nm,
                              int total_nq, int total_nm, const double* qm_xyz, const double* Q, const double* mu,
@@ -994,8 +1020,9 @@ ewald_status_t enqueue_batch(ewald_plan* plan, hipStream_t s, int n_frames, int 
   Work& w = plan->w;
   const Grid& g = plan->g;
   if (mode == EWALD_FWD_BWD) {
-    return seq_fwd_bwd(q, plan->serial ? s : plan->gaux, plan->serial ? s : plan->gaux2, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm, g.KF, energy, phi, efield, efgrad,
-                       w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
+    const bool one = plan->serial || batch_one_stream(plan);
+    return seq_fwd_bwd(q, one ? s : plan->gaux, one ? s : plan->gaux2, qm_xyz, Q, mu, theta, mm_xyz, mm_q, w.smm,
+                       g.KF, energy, phi, efield, efgrad, w.site, g_qm_xyz, g_Q, g_mu, g_theta, g_mm_xyz, g_mm_q);
   }
   ewald_status_t st = seq_begin(q, qm_xyz, Q, mu, theta, mm_xyz, mm_q, mm_tables_for(pl), 0);
   if (st != EWALD_OK) return st;
@@ -1071,6 +1098,7 @@ extern "C" ewald_status_t ewald_batch(ewald_plan* plan, int n_frames, const ewal
     hf[i].orig = order[i];
     slot += (fr.n_mm + use.a_chunk - 1) / use.a_chunk;
   }
+  use.fwd_units = n_frames > 1 ? slot : 0;
   const int cells = assign_cells(plan, hf.data(), n_frames) ? 1 : 0;
   const int mm_groups = real_mm_groups(plan, hf.data(), n_frames);
   // graph key: frames, pointers, mode, stream, tiles

@@ -152,7 +152,8 @@ struct Tuning {
   int fwd_target; // forward blocks the atom chunking aims for
   int fwd_mode;   // 0 VALU forward, 1 matrix-core forward
   int fwd_ct;     // matrix-core forward: 16-column tiles per wave
-  int fwd_xcd;    // matrix-core forward: XCD-aware block order (single-frame calls)
+  int fwd_xcd;    // matrix-core forward: XCD-aware block order
+  int fwd_units;  // batched calls: partial-sum slots of the forward (its XCD-aware units)
   int bwd_xcd;    // LDS-y adjoint: XCD-aware block order (single-frame calls)
   int fp32r;      // both hot loops on the FP32 matrix cores (mixed-precision variant)
 };

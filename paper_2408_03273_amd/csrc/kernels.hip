@@ -943,16 +943,39 @@ DEV void sfac_mm_mfma_item(const Grid& g, const FrameDev& fr, int gc, int ac, in
 
 template <int CT, int NT>
 __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
-                                                      int xcd_remap, const double* __restrict__ mm4, int cap_mm,
-                                                      const double2* __restrict__ tab,
+                                                      int xcd_remap, int units, const double* __restrict__ mm4,
+                                                      int cap_mm, const double2* __restrict__ tab,
                                                       const double* __restrict__ ztab,
                                                       double2* __restrict__ spart) {
   __shared__ double lds[sfac_lds_doubles<CT, NT>()];
+  // Consecutive workgroups go to the 8 XCDs in turn.
+  if (units > 0) {
+    // Many frames, one-dimensional grid: the ngc blocks of one (frame, atom
+    // chunk) unit (= its partial-sum slot) run on one XCD, whose L2 then
+    // serves their common atom rows; units are dealt to the XCDs in a snake
+    // order (largest frames first, so each XCD gets a similar share).
+    const int x = blockIdx.x & 7, p = blockIdx.x >> 3;
+    const int j = p / ngc, gc = p - j * ngc;
+    const int u = 8 * j + ((j & 1) ? 7 - x : x);
+    if (u >= units) return;
+    // the frame owning slot u: the last one whose first slot is <= u (frames
+    // without atoms own no slot and share the next frame's first slot)
+    int lo = 0, hi = fa.n_frames - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (fa.frames[mid].slot_base <= u) lo = mid; else hi = mid - 1;
+    }
+    const FrameDev fr = get_frame(fa, lo);
+    const int ac = u - fr.slot_base;
+    if (ac < 0 || ac * a_chunk >= fr.nm) return;
+    sfac_mm_mfma_item<CT, NT>(g, fr, gc, ac, a_chunk, mm4, cap_mm, tab, ztab, spart, lds);
+    return;
+  }
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
-  // Consecutive workgroups go to the 8 XCDs in turn.  With xcd_remap (single
-  // frame) the blocks that share an atom chunk (consecutive logical ids) are
-  // placed on one XCD, so that its L2 serves their common atom rows.
+  // With xcd_remap (single frame) the blocks that share an atom chunk
+  // (consecutive logical ids) are placed on one XCD, so that its L2 serves
+  // their common atom rows.
   int bid = blockIdx.x;
   if (xcd_remap) {
     const int per = (int)gridDim.x / 8;
@@ -965,9 +988,9 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
 
 template <int CT, int NT>
 static void launch_sfac_mm_mfma_t(dim3 grid, hipStream_t s, const Grid& g, const FrameArg& fa, int a_chunk, int ngc,
-                                  int nac, int xcd, int cap_mm, Work& w) {
-  hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, xcd, w.mm4, cap_mm,
-                     w.mm_xy, w.mm_ztab, w.spart);
+                                  int nac, int xcd, int units, int cap_mm, Work& w) {
+  hipLaunchKernelGGL((k_sfac_mm_mfma<CT, NT>), grid, dim3(256), 0, s, g, fa, a_chunk, ngc, nac, xcd, units, w.mm4,
+                     cap_mm, w.mm_xy, w.mm_ztab, w.spart);
 }
 
 static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const FrameArg& fa, int max_nm, int cap_mm,
@@ -977,10 +1000,13 @@ static hipError_t launch_sfac_mm_mfma(const Grid& g, const Tuning& t, const Fram
   if (nac == 0) return hipSuccess;
   dim3 grid(ngc * nac, 1, fa.n_frames);
   const int xcd = (t.fwd_xcd && fa.n_frames == 1) ? 1 : 0;
-#define SF(C, N)                                                                      \
-  if (t.fwd_ct == C && g.NT == N) {                                                   \
-    launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, xcd, cap_mm, w); \
-    return hipGetLastError();                                                         \
+  // many frames: one-dimensional grid over the partial-sum slots (units)
+  const int units = (t.fwd_xcd && fa.frames && fa.n_frames > 1) ? t.fwd_units : 0;
+  if (units > 0) grid = dim3(8 * ngc * ((units + 7) / 8), 1, 1);
+#define SF(C, N)                                                                             \
+  if (t.fwd_ct == C && g.NT == N) {                                                          \
+    launch_sfac_mm_mfma_t<C, N>(grid, s, g, fa, t.a_chunk, ngc, nac, xcd, units, cap_mm, w); \
+    return hipGetLastError();                                                                \
   }
   SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(4, 2) SF(1, 3) SF(2, 3) SF(1, 4) SF(2, 4)
 #undef SF
