@@ -236,6 +236,7 @@ static constexpr int kTabRun = 7;
 static constexpr int kTabAtoms = 16;
 static constexpr int kTabMaxR = 192;    // complex entries per row held in LDS
 static constexpr int kTabMaxZ = 64;     // real z entries per row held in LDS
+static constexpr int kTabBlocks = 4096;  // blocks of a table pass (several frames share them)
 
 __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_side, int with_ez,
                                                   const double* __restrict__ pos4, int cap, double2* __restrict__ tab,
@@ -249,94 +250,97 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
   const FrameDev fr = get_frame(fa, f);
   const int n_atoms = qm_side ? fr.nq : fr.nm;
   const int off = qm_side ? fr.qoff : fr.moff;
-  const int a0 = blockIdx.x * kTabAtoms;
-  if (a0 >= n_atoms) return;  // uniform over the block
-  const int na = min(kTabAtoms, n_atoms - a0);
   const int nc = g.NX + g.NY + (with_ez ? g.NZP : 0);  // complex entries built per row
   const int rs = nc + 1;
   auto rows = [&](int a, int c) -> double2& { return rowbuf[a * rs + c]; };
   const int rx = (g.NX + kTabRun - 1) / kTabRun, ry = (g.NY + kTabRun - 1) / kTabRun,
             rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
   const int runs = rx + ry + rz + rr;
-  if (threadIdx.x < na * 3) {
-    const int a = threadIdx.x / 3, ax = threadIdx.x - 3 * a;
-    const double x = pos4[(size_t)ax * cap + off + a0 + a] / fr.box[ax];
-    double sn, cs;
-    sincospi(2.0 * x, &sn, &cs);
-    base[a][ax] = make_double2(cs, sn);
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < na * runs; t += 256) {
-    const int a = t / runs, u = t - a * runs;
-    int axis, first, count, n0, limit;
-    if (u < rx) {
-      axis = 0;
-      first = u * kTabRun;
-      count = min(kTabRun, g.NX - first);
-      n0 = first;
-      limit = count;
-    } else if (u < rx + ry) {
-      axis = 1;
-      first = (u - rx) * kTabRun;
-      count = min(kTabRun, g.NY - first);
-      n0 = first - g.my;
-      first += g.NX;
-      limit = count;
-    } else if (u < rx + ry + rz) {
-      axis = 2;
-      first = (u - rx - ry) * kTabRun;
-      count = min(kTabRun, g.NZP - first);
-      n0 = first - g.mz;
-      limit = g.NZ - first;  // z entries past NZ are padding
-      first += g.NX + g.NY;
-    } else {
-      axis = 3;  // real z row, p = first+1 ..
-      first = (u - rx - ry - rz) * kTabRun;
-      count = min(kTabRun, g.mz - first);
-      n0 = first + 1;
-      limit = count;
+  // The block takes groups of kTabAtoms atoms in turn: the stores of one
+  // group drain while the next is built (the barrier after the powers of u
+  // also orders the previous group's LDS reads before the new rows).
+  for (int a0 = blockIdx.x * kTabAtoms; a0 < n_atoms; a0 += gridDim.x * kTabAtoms) {  // uniform over the block
+    const int na = min(kTabAtoms, n_atoms - a0);
+    if (threadIdx.x < na * 3) {
+      const int a = threadIdx.x / 3, ax = threadIdx.x - 3 * a;
+      const double x = pos4[(size_t)ax * cap + off + a0 + a] / fr.box[ax];
+      double sn, cs;
+      sincospi(2.0 * x, &sn, &cs);
+      base[a][ax] = make_double2(cs, sn);
     }
-    const int ax = axis == 3 ? 2 : axis;
-    const double2 step = base[a][ax];
-    // v = step^n0
-    double2 v = make_double2(1.0, 0.0), pw = step;
-    for (int m = n0 < 0 ? -n0 : n0; m; m >>= 1) {
-      if (m & 1) v = cmul(v, pw);
-      pw = cmul(pw, pw);
-    }
-    if (n0 < 0) v = cconj(v);
-    for (int e = 0; e < count; e++) {
-      if (axis == 3) {
-        zrows[a][first + e] = v.x;
-        zrows[a][g.mz + first + e] = v.y;
+    __syncthreads();
+    for (int t = threadIdx.x; t < na * runs; t += 256) {
+      const int a = t / runs, u = t - a * runs;
+      int axis, first, count, n0, limit;
+      if (u < rx) {
+        axis = 0;
+        first = u * kTabRun;
+        count = min(kTabRun, g.NX - first);
+        n0 = first;
+        limit = count;
+      } else if (u < rx + ry) {
+        axis = 1;
+        first = (u - rx) * kTabRun;
+        count = min(kTabRun, g.NY - first);
+        n0 = first - g.my;
+        first += g.NX;
+        limit = count;
+      } else if (u < rx + ry + rz) {
+        axis = 2;
+        first = (u - rx - ry) * kTabRun;
+        count = min(kTabRun, g.NZP - first);
+        n0 = first - g.mz;
+        limit = g.NZ - first;  // z entries past NZ are padding
+        first += g.NX + g.NY;
       } else {
-        rows(a, first + e) = e < limit ? v : make_double2(0.0, 0.0);
+        axis = 3;  // real z row, p = first+1 ..
+        first = (u - rx - ry - rz) * kTabRun;
+        count = min(kTabRun, g.mz - first);
+        n0 = first + 1;
+        limit = count;
       }
-      v = cmul(v, step);
+      const int ax = axis == 3 ? 2 : axis;
+      const double2 step = base[a][ax];
+      // v = step^n0
+      double2 v = make_double2(1.0, 0.0), pw = step;
+      for (int m = n0 < 0 ? -n0 : n0; m; m >>= 1) {
+        if (m & 1) v = cmul(v, pw);
+        pw = cmul(pw, pw);
+      }
+      if (n0 < 0) v = cconj(v);
+      for (int e = 0; e < count; e++) {
+        if (axis == 3) {
+          zrows[a][first + e] = v.x;
+          zrows[a][g.mz + first + e] = v.y;
+        } else {
+          rows(a, first + e) = e < limit ? v : make_double2(0.0, 0.0);
+        }
+        v = cmul(v, step);
+      }
     }
-  }
-  __syncthreads();
-  if (with_ez) {
-    // whole rows: one contiguous run of na * R entries
-    double2* __restrict__ o = tab + (size_t)(off + a0) * g.R;
-    for (int e = threadIdx.x; e < na * g.R; e += 256) {
-      const int a = e / g.R, c = e - a * g.R;
-      o[e] = rows(a, c);
+    __syncthreads();
+    if (with_ez) {
+      // whole rows: one contiguous run of na * R entries
+      double2* __restrict__ o = tab + (size_t)(off + a0) * g.R;
+      for (int e = threadIdx.x; e < na * g.R; e += 256) {
+        const int a = e / g.R, c = e - a * g.R;
+        o[e] = rows(a, c);
+      }
     }
-  }
-  if (xy) {
-    // compact x/y rows (stride NX + NY): one contiguous run of na * NXY entries
-    double2* __restrict__ o = xy + (size_t)(off + a0) * g.NXY;
-    for (int e = threadIdx.x; e < na * g.NXY; e += 256) {
-      const int a = e / g.NXY, c = e - a * g.NXY;
-      o[e] = rows(a, c);
+    if (xy) {
+      // compact x/y rows (stride NX + NY): one contiguous run of na * NXY entries
+      double2* __restrict__ o = xy + (size_t)(off + a0) * g.NXY;
+      for (int e = threadIdx.x; e < na * g.NXY; e += 256) {
+        const int a = e / g.NXY, c = e - a * g.NXY;
+        o[e] = rows(a, c);
+      }
     }
-  }
-  if (ztab) {
-    const int zw = 2 * g.mz;
-    for (int e = threadIdx.x; e < na * zw; e += 256) {
-      const int a = e / zw, c = e - a * zw;
-      ztab[(size_t)(off + a0 + a) * g.ZKP + c] = zrows[a][c];
+    if (ztab) {
+      const int zw = 2 * g.mz;
+      for (int e = threadIdx.x; e < na * zw; e += 256) {
+        const int a = e / zw, c = e - a * zw;
+        ztab[(size_t)(off + a0 + a) * g.ZKP + c] = zrows[a][c];
+      }
     }
   }
 }
@@ -392,7 +396,9 @@ __global__ __launch_bounds__(256) void k_prep_tab_direct(Grid g, FrameArg fa, in
 static void launch_tab(const Grid& g, const FrameArg& fa, int qm_side, int with_ez, int max_n, const double* pos4,
                        int cap, double2* tab, double* ztab, double2* xy, hipStream_t s) {
   if (g.R <= kTabMaxR && 2 * g.mz <= kTabMaxZ) {
-    dim3 grid((max_n + kTabAtoms - 1) / kTabAtoms, fa.n_frames);
+    // about kTabBlocks blocks in all, each looping over its frame's groups
+    const int groups = (max_n + kTabAtoms - 1) / kTabAtoms;
+    dim3 grid(std::max(1, std::min(groups, kTabBlocks / std::max(fa.n_frames, 1))), fa.n_frames);
     const size_t lds = (size_t)kTabAtoms * (g.NX + g.NY + (with_ez ? g.NZP : 0) + 1) * sizeof(double2);
     hipLaunchKernelGGL(k_prep_tab, grid, dim3(256), lds, s, g, fa, qm_side, with_ez, pos4, cap, tab, ztab, xy);
   } else {
