@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles instead of timing candidates")
     ap.add_argument("--f3-only", action="store_true",
                     help="only the rc ~ L measurement of the c3 frame (its JSON object), e.g. under a profiler")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the FP64 batches (64 c4 frames, 16 c5 replicas; their JSON objects), e.g. under a profiler")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device-to-device copy of 256 MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -90,6 +92,10 @@ def main():
     torch.cuda.set_device(dev)
     if args.f3_only:
         print(json.dumps(_f3(dev)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch_c4": _batch_variants(dev, 4, 64, (), 10)["fp64"],
+                          "c5_batch": _batch_variants(dev, 5, 16, (), 5)["fp64"]}), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -661,7 +667,7 @@ def _f3(dev, steps=20):
     return out
 
 
-def _batch_c4(dev, steps=5):
+def _batch_c4(dev, steps=10):
     """64 independent frames of uneven size through one graph-replayed batch
     call, FP64 and with the real space in FP32 (FP64 accumulation)."""
     v = _batch_variants(dev, 4, 64, ("fp32_real",), steps)
