@@ -72,6 +72,33 @@ def test_batch_matches_unbatched_and_oracle():
             assert max(errs.values()) <= 1e-10, (i, errs)
 
 
+@pytest.mark.parametrize("fwd_xcd,target,one_stream", [("0", "64", "0"), ("1", "64", "1"), ("1", "65536", "0"),
+                                                        ("0", "65536", "1")])
+def test_batch_schedules_agree(monkeypatch, fwd_xcd, target, one_stream):
+    """The batch's forward block orders (frame-major grid, or the XCD-aware
+    one-dimensional grid over (frame, atom chunk) units), its chunk sizes (896
+    atoms, a few per frame with ragged last ones, or 64, which divide the
+    2048-atom frame exactly; the frame without MM atoms owns none) and its one-
+    or two-stream schedule give the single-frame results of every frame."""
+    monkeypatch.setenv("MPEWALD_FWD_XCD", fwd_xcd)
+    monkeypatch.setenv("MPEWALD_BATCH_TARGET", target)
+    monkeypatch.setenv("MPEWALD_BATCH_SERIAL", one_stream)
+    frames = _frames(FRAMES)
+    desc, x, qoff, moff = _pack(frames)
+    plan = _batch_plan(frames)
+    print(f"[batch schedule] fwd_xcd={fwd_xcd} target={target} one_stream={one_stream}", flush=True)
+    out = plan.batch(desc, *x)
+    torch.cuda.synchronize()
+    monkeypatch.delenv("MPEWALD_FWD_XCD")
+    monkeypatch.delenv("MPEWALD_BATCH_TARGET")
+    monkeypatch.delenv("MPEWALD_BATCH_SERIAL")
+    for i, f in enumerate(frames):
+        got = _per_frame(frames, out, qoff, moff, i)
+        single = H.gpu_outputs(f)
+        errs = H.compare(got, single, H.FWD_KEYS + H.BWD_KEYS)
+        assert max(errs.values()) <= 1e-12, (i, errs)
+
+
 def test_batch_frame_order_irrelevant():
     frames = _frames(FRAMES[:4])
     desc, x, qoff, moff = _pack(frames)
