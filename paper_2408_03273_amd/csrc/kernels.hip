@@ -2336,6 +2336,30 @@ DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchu
     }
   };
   int count = 0;  // pending pairs of this wave (wave-uniform)
+  if (fr.nimg == 0) {
+    // rc <= L/2 on every axis: the minimum image is a pair's only candidate
+    // (the FIFO receives the same pairs in the same order as below)
+    for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
+      const int i = base + threadIdx.x;
+      double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0, r2d = 0.0;
+      bool hit = false;
+      if (i < i1) {
+        bx = X - mx_[i];
+        by = Y - my_[i];
+        bz = Zc - mz_[i];
+        qd = mq_[i];
+        min_image(bx, by, bz, fr);
+        r2d = bx * bx + by * by + bz * bz;
+        hit = r2d < rc2 && r2d != 0.0;
+      }
+      count = ff.append(hit, lane, count, bx, by, bz, r2d, qd, i);
+      if (count >= 64) {
+        wave_lds_sync();
+        evaluate(64);
+        count = ff.drop64(lane, count);
+      }
+    }
+  } else
   for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
     const int i = base + threadIdx.x;
     double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
