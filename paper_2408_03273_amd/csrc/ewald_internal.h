@@ -168,6 +168,29 @@ inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && eyl_lds_by
 inline int eyl_waves(const Grid& g) { return eyl_lds_bytes(g, 4) <= 65536 ? 4 : 2; }
 // the matrix-core hot loops address one frame's x/y phase table with 32-bit
 // buffer offsets
+// Batched matrix-core forward, one-dimensional grid over the (frame, atom
+// chunk) units (= partial-sum slots): the ngc column-group blocks of a unit are
+// consecutive on one XCD (workgroups go to the 8 XCDs in turn) and the units
+// are dealt to the XCDs in snake order.  Returns false for a block without a
+// unit; else the frame index (the last frame whose first slot is <= the unit:
+// frames without atoms own no slot and share the next frame's first slot),
+// column group and chunk.
+__device__ inline bool fwd_unit(const FrameArg& fa, int units, int ngc, int& f, int& gc, int& ac) {
+  const int x = blockIdx.x & 7, p = blockIdx.x >> 3;
+  const int j = p / ngc;
+  gc = p - j * ngc;
+  const int u = 8 * j + ((j & 1) ? 7 - x : x);
+  if (u >= units) return false;
+  int lo = 0, hi = fa.n_frames - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fa.frames[mid].slot_base <= u) lo = mid; else hi = mid - 1;
+  }
+  f = lo;
+  ac = u - fa.frames[lo].slot_base;
+  return true;
+}
+
 inline bool tab32_ok(const Grid& g, long nm) { return (size_t)nm * g.NXY * 16 < (size_t(1) << 31); }
 // the forward tiles per wave are limited by the LDS of the block reduction
 // (64 KB of FP64 partial tiles at CT NT = 8; gfx950 gives a block up to 160 KB)

@@ -954,25 +954,14 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma(Grid g, FrameArg fa, int a
                                                       const double* __restrict__ ztab,
                                                       double2* __restrict__ spart) {
   __shared__ double lds[sfac_lds_doubles<CT, NT>()];
-  // Consecutive workgroups go to the 8 XCDs in turn.
+  // Consecutive workgroups go to the 8 XCDs in turn.  Many frames: the
+  // XCD-aware order over (frame, atom chunk) units, whose blocks then share
+  // their atom rows in one XCD's L2 (largest frames first, so that the snake
+  // order gives each XCD a similar share).
   if (units > 0) {
-    // Many frames, one-dimensional grid: the ngc blocks of one (frame, atom
-    // chunk) unit (= its partial-sum slot) run on one XCD, whose L2 then
-    // serves their common atom rows; units are dealt to the XCDs in a snake
-    // order (largest frames first, so each XCD gets a similar share).
-    const int x = blockIdx.x & 7, p = blockIdx.x >> 3;
-    const int j = p / ngc, gc = p - j * ngc;
-    const int u = 8 * j + ((j & 1) ? 7 - x : x);
-    if (u >= units) return;
-    // the frame owning slot u: the last one whose first slot is <= u (frames
-    // without atoms own no slot and share the next frame's first slot)
-    int lo = 0, hi = fa.n_frames - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (fa.frames[mid].slot_base <= u) lo = mid; else hi = mid - 1;
-    }
-    const FrameDev fr = get_frame(fa, lo);
-    const int ac = u - fr.slot_base;
+    int f, gc, ac;
+    if (!fwd_unit(fa, units, ngc, f, gc, ac)) return;
+    const FrameDev fr = get_frame(fa, f);
     if (ac < 0 || ac * a_chunk >= fr.nm) return;
     sfac_mm_mfma_item<CT, NT>(g, fr, gc, ac, a_chunk, mm4, cap_mm, tab, ztab, spart, lds);
     return;

@@ -124,7 +124,8 @@ hipError_t launch_wfrag32(const Grid& g, const FrameArg& fa, Work& w, hipStream_
 // partial S(k) in FP64.
 template <int CT, int NT>
 __global__ __launch_bounds__(256) void k_sfac_mm_mfma32(Grid g, FrameArg fa, int a_chunk, int ngc, int nac,
-                                                        int xcd_remap, const double* __restrict__ mm4, int cap_mm,
+                                                        int xcd_remap, int units, const double* __restrict__ mm4,
+                                                        int cap_mm,
                                                         const float2* __restrict__ tab,
                                                         const float* __restrict__ ztab,
                                                         double2* __restrict__ spart) {
@@ -132,15 +133,22 @@ __global__ __launch_bounds__(256) void k_sfac_mm_mfma32(Grid g, FrameArg fa, int
   constexpr int NACC = CT * NT * 8;  // accumulator floats per lane
   __shared__ float red[2][NACC * 64];
   __shared__ float s0red[4][CT][2][16];
-  const int f = blockIdx.z;
-  const FrameDev fr = frame32(fa, f);
-  int bid = blockIdx.x;
-  if (xcd_remap) {
-    const int per = (int)gridDim.x / 8;
-    if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+  // block order as the FP64 kernel's: many frames over (frame, atom chunk)
+  // units, one frame with the blocks of an atom chunk on one XCD
+  int f = blockIdx.z, gc, ac;
+  if (units > 0) {
+    if (!fwd_unit(fa, units, ngc, f, gc, ac)) return;
+  } else {
+    int bid = blockIdx.x;
+    if (xcd_remap) {
+      const int per = (int)gridDim.x / 8;
+      if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
+    }
+    gc = bid % ngc;
+    ac = bid / ngc;
+    if (ac >= nac) return;
   }
-  const int gc = bid % ngc, ac = bid / ngc;
-  if (ac >= nac) return;
+  const FrameDev fr = frame32(fa, f);
   const int a0 = ac * a_chunk;
   if (a0 >= fr.nm) return;  // uniform over the block
   const int a1 = min(fr.nm, a0 + a_chunk);
@@ -319,10 +327,12 @@ hipError_t launch_sfac_mm32(const Grid& g, const Tuning& t, const FrameArg& fa, 
   if (nac == 0) return hipSuccess;
   dim3 grid(ngc * nac, 1, fa.n_frames);
   const int xcd = (t.fwd_xcd && fa.n_frames == 1) ? 1 : 0;
+  const int units = (t.fwd_xcd && fa.frames && fa.n_frames > 1) ? t.fwd_units : 0;
+  if (units > 0) grid = dim3(8 * ngc * ((units + 7) / 8), 1, 1);
 #define SF(C, N)                                                                                                   \
   if (t.fwd_ct == C && g.NT == N) {                                                                                \
-    hipLaunchKernelGGL((k_sfac_mm_mfma32<C, N>), grid, dim3(256), 0, s, g, fa, t.a_chunk, ngc, nac, xcd, w.mm4, \
-                       cap_mm, w.mm_xy32, w.mm_ztab32, w.spart);                                                   \
+    hipLaunchKernelGGL((k_sfac_mm_mfma32<C, N>), grid, dim3(256), 0, s, g, fa, t.a_chunk, ngc, nac, xcd, units, \
+                       w.mm4, cap_mm, w.mm_xy32, w.mm_ztab32, w.spart);                                            \
     return hipGetLastError();                                                                                      \
   }
   SF(1, 1) SF(2, 1) SF(4, 1) SF(1, 2) SF(2, 2) SF(4, 2) SF(1, 3) SF(2, 3) SF(4, 3) SF(1, 4) SF(2, 4)
