@@ -535,9 +535,13 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, hipStream_t aux2, cons
                           q.mm_groups));
     }
   }
+  // many frames: the QM side first on the caller stream, ahead of the MM
+  // tables (beside the table pass's blocks the QM structure factors took
+  // ~4x their time alone), and both hot loops after both
+  const bool qside_first = q.fa.n_frames > 1;
   {
     Seq qa = q;
-    qa.s = aux;
+    qa.s = qside_first ? q.s : aux;
     const Seq& q_ = qa;
     {
       const Seq& q = q_;
@@ -560,10 +564,9 @@ ewald_status_t seq_fwd_bwd(const Seq& q, hipStream_t aux, hipStream_t aux2, cons
                    tables, 1, PREP_MM_TAB));
   HIPCHK(hipEventRecord(pl->ev_mtab, q.s));
   if (qq_first && q.qmqm && q.max_nq > 0) LCHK(launch_qmqm(g, q.fa, q.max_nq, pl->cap_qm, Q, mu, theta, w, q.s));
-  // caller stream: the forward hot loop.  With many frames its grid would take
-  // the GPU from the QM structure factors that the adjoint waits for, so that
-  // the adjoint would start long after the forward: it waits for them too.
-  if (q.fa.n_frames > 1 && aux != q.s) HIPCHK(hipStreamWaitEvent(q.s, pl->ev_qside, 0));
+  // caller stream: the forward hot loop (with many frames after the QM side,
+  // whose structure factors the adjoint needs: a forward grid beside them
+  // would starve them and the adjoint would start long after the forward)
   LCHK(launch_sfac_mm(g, pl->t, q.fa, q.max_nm, pl->cap_mm, w, q.s));
   {
     Seq qa = q;
