@@ -166,6 +166,13 @@ inline bool mfma_bwd_ok(const Grid& g) { return g.NK2 >= 2 && g.NK2 <= 16; }
 inline size_t eyl_lds_bytes(const Grid& g, int wv) { return (size_t)(16 * wv + 1) * g.NY * 16; }
 inline bool mfma_bwd_eyl_ok(const Grid& g) { return mfma_bwd_ok(g) && eyl_lds_bytes(g, 2) <= 65536; }
 inline int eyl_waves(const Grid& g) { return eyl_lds_bytes(g, 4) <= 65536 ? 4 : 2; }
+// Large y grids: only the rows ny >= 0 in LDS (a row ny < 0 is the conjugate
+// of row -ny) when the full 64-atom tile would leave fewer than three blocks
+// per CU (160 KB of LDS), i.e. fewer waves per SIMD than the registers allow
+inline size_t eyl_half_lds_bytes(const Grid& g) { return (size_t)(16 * 4 + 1) * (g.my + 1) * 16; }
+inline bool eyl_half_y(const Grid& g) {
+  return eyl_lds_bytes(g, 4) * 3 > 160 * 1024 && eyl_half_lds_bytes(g) <= 65536;
+}
 // the matrix-core hot loops address one frame's x/y phase table with 32-bit
 // buffer offsets
 // Batched matrix-core forward, one-dimensional grid over the (frame, atom

@@ -1702,10 +1702,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
 
 // One adjoint work item: atom tile `tile` (16 WV atoms) and column chunk kc of
 // kc_n of frame f, all 64 WV threads of the block; eysh holds
-// eyl_lds_bytes(g, WV).  Returns (uniformly) for a tile past the frame's
-// atoms; waves past the last atom return after the staging barrier (no
-// barrier follows it).
-template <int NK, int WV>
+// eyl_lds_bytes(g, WV), or with HY (half y) eyl_half_lds_bytes(g): only the
+// rows ny >= 0, a column with ny < 0 taking the conjugate of row -ny.
+// Returns (uniformly) for a tile past the frame's atoms; waves past the last
+// atom return after the staging barrier (no barrier follows it).
+template <int NK, int WV, bool HY>
 DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, int kc, int kc_n, int cap_mm,
                            const double2* __restrict__ tab, const double* __restrict__ ztab,
                            const double* __restrict__ wfrag, const double2* __restrict__ wk0,
@@ -1721,15 +1722,16 @@ DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, i
     // without a division per entry (VALU instructions here delay the
     // matrix-core issue of the other waves on the SIMD)
     constexpr int NT = 64 * WV;
-    const int da = NT / g.NY, dc = NT - da * g.NY;
-    int a = threadIdx.x / g.NY, c = threadIdx.x - a * g.NY;
-    const double2* __restrict__ src = tab + (size_t)fr.moff * g.NXY + g.NX;
-    for (int e = threadIdx.x; e < NA * g.NY; e += NT) {
+    const int rows = HY ? g.my + 1 : g.NY;  // LDS row c holds iy = c (HY: iy = my + c, ny = c)
+    const int da = NT / rows, dc = NT - da * rows;
+    int a = threadIdx.x / rows, c = threadIdx.x - a * rows;
+    const double2* __restrict__ src = tab + (size_t)fr.moff * g.NXY + g.NX + (HY ? g.my : 0);
+    for (int e = threadIdx.x; e < NA * rows; e += NT) {
       eysh[c * ES + a] = src[(size_t)min(ablk + a, fr.nm - 1) * g.NXY + c];
       a += da;
       c += dc;
-      if (c >= g.NY) {
-        c -= g.NY;
+      if (c >= rows) {
+        c -= rows;
         a++;
       }
     }
@@ -1811,11 +1813,15 @@ DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, i
     // columns past NCOL (in the last group) have zero weights: their terms
     // vanish without a branch
     const double fnx = (double)nx, fny = (double)(iy - g.my);
-    const double2* __restrict__ ey = eysh + iy * ES + erow;
+    // HY: row |ny|, conjugated for ny < 0
+    const int yrow = HY ? (iy < g.my ? g.my - iy : iy - g.my) : iy;
+    const double sy = (HY && iy < g.my) ? -1.0 : 1.0;
+    const double2* __restrict__ ey = eysh + yrow * ES + erow;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       // c = e^{-i(kx x + ky y)} = conj(e^{i kx x} e^{i ky y}) = cr - i s
-      const double2 e = ey[4 * r];
+      double2 e = ey[4 * r];
+      if (HY) e.y *= sy;
       const double pr = Pr[r] + w0.x, pi = Pi[r] + w0.y;
       const double cr = fma(ex[r].x, e.x, -ex[r].y * e.y);
       const double s = fma(ex[r].x, e.y, ex[r].y * e.x);
@@ -1862,7 +1868,7 @@ DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, i
   }
 }
 
-template <int NK, int WV>
+template <int NK, int WV, bool HY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_force_mm_eyl(
     Grid g, FrameArg fa, int kc_n, int xcd_remap, int cap_mm, const double2* __restrict__ tab,
     const double* __restrict__ ztab, const double* __restrict__ wfrag, const double2* __restrict__ wk0,
@@ -1876,7 +1882,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (bid < 8 * per) bid = (bid % 8) * per + bid / 8;
   }
   const int tile = bid / kc_n, kc = bid - tile * kc_n;
-  force_mm_eyl_item<NK, WV>(g, fr, f, tile, kc, kc_n, cap_mm, tab, ztab, wfrag, wk0, fpart, eysh);
+  force_mm_eyl_item<NK, WV, HY>(g, fr, f, tile, kc, kc_n, cap_mm, tab, ztab, wfrag, wk0, fpart, eysh);
 }
 
 // Warp-specialised matrix-core adjoint: in a block of eight waves, waves 0-3
@@ -2009,18 +2015,22 @@ hipError_t launch_force_mm(const Grid& g, const Tuning& t, const FrameArg& fa, i
   if (t.fp32r) return launch_force_mm32(g, t, fa, max_nm, cap_mm, w, s);
   if (t.bwd_ilp == 6 && mfma_bwd_eyl_ok(g)) {  // y phases in LDS: 64 (or 32) atoms per block
     if (!tab32_ok(g, max_nm)) return hipErrorInvalidValue;  // the API rejects such frames first
-    const int wv = eyl_waves(g);
+    const bool hy = eyl_half_y(g);
+    const int wv = hy ? 4 : eyl_waves(g);
     dim3 grid(((max_nm + 16 * wv - 1) / (16 * wv)) * t.kc, 1, fa.n_frames);
-    const size_t lds = eyl_lds_bytes(g, wv);
+    const size_t lds = hy ? eyl_half_lds_bytes(g) : eyl_lds_bytes(g, wv);
     const int xcd = (t.bwd_xcd && fa.n_frames == 1) ? 1 : 0;
-#define FE(N)                                                                                                  \
-  case N:                                                                                                      \
-    if (wv == 4)                                                                                               \
-      hipLaunchKernelGGL((k_force_mm_eyl<N, 4>), grid, dim3(256), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy,  \
-                         w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_force_mm_eyl<N, 2>), grid, dim3(128), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy,  \
-                         w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                  \
+#define FE(N)                                                                                                       \
+  case N:                                                                                                           \
+    if (hy)                                                                                                         \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 4, true>), grid, dim3(256), lds, s, g, fa, t.kc, xcd, cap_mm, w.mm_xy, \
+                         w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                                       \
+    else if (wv == 4)                                                                                               \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 4, false>), grid, dim3(256), lds, s, g, fa, t.kc, xcd, cap_mm,         \
+                         w.mm_xy, w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                              \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_force_mm_eyl<N, 2, false>), grid, dim3(128), lds, s, g, fa, t.kc, xcd, cap_mm,         \
+                         w.mm_xy, w.mm_ztab, w.wfrag, w.wk0, w.fpart);                                              \
     break;
     switch (g.NK2) { FE(2) FE(4) FE(6) FE(8) FE(10) FE(12) FE(14) FE(16) default: return hipErrorInvalidValue; }
 #undef FE

@@ -131,6 +131,18 @@ def test_forward_kernel_variants(mode, ct, xcd, monkeypatch):
            keys=H.FWD_KEYS)
 
 
+@pytest.mark.parametrize("kc", ["1", "3"])
+def test_adjoint_half_y_rows(kc, monkeypatch):
+    """Large y grids (|ny| <= 26 and <= 30: the full 64-atom y tile would leave
+    fewer than three blocks per CU) keep only the rows ny >= 0 in LDS and
+    conjugate them for ny < 0; ragged atom counts, one or three column
+    chunks."""
+    monkeypatch.setenv("MPEWALD_BWD", "6")
+    monkeypatch.setenv("MPEWALD_KC", kc)
+    _check(wl.random_system(50, 6, 1501, box=(18.0, 20.0, 22.0), alpha=0.35, rcut=8.0, kmax=(5, 30, 9)))
+    _check(wl.random_system(51, 3, 877, box=(17.0, 19.0, 16.0), alpha=0.4, rcut=7.5, kmax=(4, 26, 6)))
+
+
 def test_large_kgrid_valu_kernels_and_direct_tables():
     """kmax beyond the matrix-core instances (mz > 32) selects the VALU hot
     loops, and table rows longer than the LDS tile use the per-entry table
