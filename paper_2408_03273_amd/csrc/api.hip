@@ -993,7 +993,8 @@ namespace {
 // from L2 in every block of the frame, which the forward's stream of phase
 // rows evicts once the weights pass about half an XCD's 4 MB L2 (measured:
 // 64 frames at kmax 20, 1.1 MB of weights, are 1% faster on two streams; 16
-// frames at kmax 32, 4.4 MB, 2.5% faster on one).
+// frames at kmax 32, 4.4 MB, 4-5% faster on one, in FP64 and with the FP32
+// reciprocal kernels).
 bool batch_one_stream(const ewald_plan* pl) {
   if (pl->batch_serial >= 0) return pl->batch_serial != 0;
   if (pl->t.bwd_ilp < 3) return false;
