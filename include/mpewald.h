@@ -73,7 +73,7 @@ enum {
                               and MM gradients) on FP32 matrix cores: phase tables and
                               folded weights rounded to FP32, FP32 accumulation inside
                               a block, FP64 sums across blocks and everything after;
-                              needs kmax[2] <= 32 and kmax[1] <= 31.  The error against
+                              needs kmax[2] <= 32 and kmax[1] <= 61.  The error against
                               FP64 is of the order of 1e-6 relative (mixed precision) */
 };
 

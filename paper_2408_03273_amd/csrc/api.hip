@@ -703,7 +703,7 @@ ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan) {
     // both hot loops on the FP32 matrix cores: matrix-core forward, LDS-y adjoint
     if (!fp32r_ok(pl->g)) {
       delete pl;
-      return fail(EWALD_ERR_ARG, "EWALD_FP32_RECIP needs kmax[2] <= 32 and kmax[1] <= 31");
+      return fail(EWALD_ERR_ARG, "EWALD_FP32_RECIP needs kmax[2] <= 32 and kmax[1] <= 61");
     }
     pl->t.fp32r = 1;
     pl->t.fwd_mode = 1;
