@@ -58,7 +58,7 @@ def test_fp32_recip_c3_against_oracle():
 
 @pytest.mark.parametrize("case", [(81, 17, 3000, (21.0, 22.0, 23.0), 0.33, 9.0, (8, 9, 10)),
                                   (82, 5, 700, (17.0, 17.0, 17.0), 0.4, 8.0, (5, 5, 3)),
-                                  # |ny| <= 33: a large y grid (38 KB of y rows per 64-atom block)
+                                  # |ny| <= 33: a large y grid (35 KB of FP32 y rows per 64-atom block)
                                   (83, 6, 1501, (18.0, 20.0, 22.0), 0.35, 8.0, (5, 33, 9))])
 def test_fp32_recip_small_against_oracle(case):
     seed, nq, nm, box, alpha, rcut, kmax = case
