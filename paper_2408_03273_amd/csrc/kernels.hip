@@ -257,8 +257,9 @@ __global__ __launch_bounds__(256) void k_prep_tab(Grid g, FrameArg fa, int qm_si
             rz = with_ez ? (g.NZP + kTabRun - 1) / kTabRun : 0, rr = ztab ? (g.mz + kTabRun - 1) / kTabRun : 0;
   const int runs = rx + ry + rz + rr;
   // The block takes groups of kTabAtoms atoms in turn: the stores of one
-  // group drain while the next is built (the barrier after the powers of u
-  // also orders the previous group's LDS reads before the new rows).
+  // group drain while the next is built (the barrier after a group's u per
+  // atom and axis also orders the previous group's reads of the LDS rows
+  // before the new rows are written).
   for (int a0 = blockIdx.x * kTabAtoms; a0 < n_atoms; a0 += gridDim.x * kTabAtoms) {  // uniform over the block
     const int na = min(kTabAtoms, n_atoms - a0);
     if (threadIdx.x < na * 3) {
@@ -2358,51 +2359,52 @@ DEV void real_qm_item(const Grid& g, const FrameDev& fr, int j, int ci, int nchu
         count = ff.drop64(lane, count);
       }
     }
-  } else
-  for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
-    const int i = base + threadIdx.x;
-    double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
-    // this lane's candidate lattice images (per axis; with the minimum image
-    // only, one candidate or none when an axis offset already exceeds rc)
-    int lx = 0, hx = -1, ly = 0, hy = -1, lz = 0, hz = -1;
-    if (i < i1) {
-      bx = X - mx_[i];
-      by = Y - my_[i];
-      bz = Zc - mz_[i];
-      qd = mq_[i];
-      min_image(bx, by, bz, fr);
-      image_range(bx, fr.box[0], fr.inv_box[0], g.rcut, fr.nimg, lx, hx);
-      image_range(by, fr.box[1], fr.inv_box[1], g.rcut, fr.nimg, ly, hy);
-      image_range(bz, fr.box[2], fr.inv_box[2], g.rcut, fr.nimg, lz, hz);
-    }
-    int ix_ = lx, iy_ = ly, iz_ = lz;
-    bool more = lx <= hx && ly <= hy && lz <= hz;
-    for (;;) {  // wave-uniform
-      // test candidates until 64 pairs are pending or every lane is done
-      // (the accumulators stay out of this loop)
-      while (count < 64 && __ballot(more)) {
-        bool hit = false;
-        double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
-        if (more) {
-          dx = bx + ix_ * fr.box[0];
-          dy = by + iy_ * fr.box[1];
-          dz = bz + iz_ * fr.box[2];
-          r2d = dx * dx + dy * dy + dz * dz;
-          hit = r2d < rc2 && r2d != 0.0;
-          if (++iz_ > hz) {
-            iz_ = lz;
-            if (++iy_ > hy) {
-              iy_ = ly;
-              more = ++ix_ <= hx;
+  } else {
+    for (int base = i0; base < i1; base += 256) {  // rounds are uniform over the block
+      const int i = base + threadIdx.x;
+      double bx = 0.0, by = 0.0, bz = 0.0, qd = 0.0;
+      // this lane's candidate lattice images: per axis, the image offsets
+      // whose distance along that axis can be within rc
+      int lx = 0, hx = -1, ly = 0, hy = -1, lz = 0, hz = -1;
+      if (i < i1) {
+        bx = X - mx_[i];
+        by = Y - my_[i];
+        bz = Zc - mz_[i];
+        qd = mq_[i];
+        min_image(bx, by, bz, fr);
+        image_range(bx, fr.box[0], fr.inv_box[0], g.rcut, fr.nimg, lx, hx);
+        image_range(by, fr.box[1], fr.inv_box[1], g.rcut, fr.nimg, ly, hy);
+        image_range(bz, fr.box[2], fr.inv_box[2], g.rcut, fr.nimg, lz, hz);
+      }
+      int ix_ = lx, iy_ = ly, iz_ = lz;
+      bool more = lx <= hx && ly <= hy && lz <= hz;
+      for (;;) {  // wave-uniform
+        // test candidates until 64 pairs are pending or every lane is done
+        // (the accumulators stay out of this loop)
+        while (count < 64 && __ballot(more)) {
+          bool hit = false;
+          double dx = 0.0, dy = 0.0, dz = 0.0, r2d = 0.0;
+          if (more) {
+            dx = bx + ix_ * fr.box[0];
+            dy = by + iy_ * fr.box[1];
+            dz = bz + iz_ * fr.box[2];
+            r2d = dx * dx + dy * dy + dz * dz;
+            hit = r2d < rc2 && r2d != 0.0;
+            if (++iz_ > hz) {
+              iz_ = lz;
+              if (++iy_ > hy) {
+                iy_ = ly;
+                more = ++ix_ <= hx;
+              }
             }
           }
+          count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i);
         }
-        count = ff.append(hit, lane, count, dx, dy, dz, r2d, qd, i);
+        if (count < 64) break;
+        wave_lds_sync();
+        evaluate(64);
+        count = ff.drop64(lane, count);
       }
-      if (count < 64) break;
-      wave_lds_sync();
-      evaluate(64);
-      count = ff.drop64(lane, count);
     }
   }
   wave_lds_sync();
