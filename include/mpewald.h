@@ -123,18 +123,23 @@ typedef struct {
 } ewald_frame_t;
 
 /* Create a plan on the current HIP device and allocate its workspace for
- * the given capacities.  The plan keeps a copy of *params. */
+ * the given capacities.  The plan keeps a copy of *params: the Ewald
+ * splitting parameter, real-space cutoff and k-space range of the multipolar
+ * Ewald sums (paper: SI, Multipolar Ewald; Computational Details, Common
+ * Setup, for the choice of the cutoff). */
 ewald_status_t ewald_setup(const ewald_params_t* params, ewald_plan** plan);
 
-/* Release the workspace; null is accepted. */
+/* Release the workspace of a plan made by ewald_setup; null is accepted. */
 ewald_status_t ewald_destroy(ewald_plan* plan);
 
-/* Change the box of a plan (validated like ewald_setup); affects later calls. */
+/* Change the box of a plan (validated like ewald_setup); affects later calls
+ * (paper: Implementation, where the MD driver sends the box with every step). */
 ewald_status_t ewald_set_box(ewald_plan* plan, const double box[3]);
 
 /* Bytes of the caller-allocated context that ewald_forward fills and
  * ewald_backward reads (saved reciprocal structure factor of the MM charges
- * and the MM potential data at the QM sites). */
+ * and the MM potential data at the QM sites: the MM field that the SCF
+ * iterations and the gradient reuse, paper: Electronic Mean-Field Theory). */
 size_t ewald_ctx_bytes(const ewald_plan* plan, int n_qm, int n_mm);
 
 /* Forward pass (paper: periodic multipole energy; SI multipolar Ewald).
@@ -274,7 +279,9 @@ ewald_status_t ewald_octupole_error_noalloc(const double box[3], int n_qm, const
                                             double* r_cut, void* stream);
 
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
- * and kmax and per-frame boxes.  frames: host array of n_frames descriptors.
+ * and kmax and per-frame boxes: per frame the computation of ewald_forward
+ * and, with EWALD_FWD_BWD, of ewald_backward (paper: SI, Multipolar Ewald;
+ * Results, Timings, for per-step costs across system sizes).  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or
  * EWALD_FWD_BWD.  Outputs: energy (n_frames), phi/efield/efgrad per QM row;
  * with EWALD_FWD_BWD also dE/dx for every input (gE = 1): g_qm_xyz, g_Q,
@@ -308,7 +315,8 @@ ewald_status_t ewald_profile_report(ewald_plan* plan, char* buf, size_t len);
  * columns per block, etc., as a short text. */
 const char* ewald_plan_describe(const ewald_plan* plan);
 
-/* Message of the calling thread's last error ("" if none). */
+/* Message of the calling thread's last error ("" if none); every entry point
+ * that returns a status other than EWALD_OK sets it. */
 const char* ewald_last_error(void);
 
 /* Library version string. */
