@@ -281,7 +281,8 @@ ewald_status_t ewald_octupole_error_noalloc(const double box[3], int n_qm, const
 /* Batched evaluation of many independent frames with the plan's alpha, rcut
  * and kmax and per-frame boxes: per frame the computation of ewald_forward
  * and, with EWALD_FWD_BWD, of ewald_backward (paper: SI, Multipolar Ewald;
- * Results, Timings, for per-step costs across system sizes).  frames: host array of n_frames descriptors.
+ * Results and Discussion, Timings, where the cost is the wall time per MD
+ * step).  frames: host array of n_frames descriptors.
  * Packed inputs hold each frame's rows at its offsets.  mode: EWALD_FWD or
  * EWALD_FWD_BWD.  Outputs: energy (n_frames), phi/efield/efgrad per QM row;
  * with EWALD_FWD_BWD also dE/dx for every input (gE = 1): g_qm_xyz, g_Q,
