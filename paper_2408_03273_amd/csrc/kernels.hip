@@ -514,20 +514,23 @@ __global__ __launch_bounds__(256) void k_sfac_qm(Grid g, FrameArg fa, const doub
       const double2 Ap = make_double2(W[0].x + W[1].x, W[0].y + W[1].y);
       const double2 Am = make_double2(W[0].x - W[1].x, W[0].y - W[1].y);
       const double fp = (double)p;
-      double* base = wfrag + ((size_t)f * g.NG + (col >> 4)) * g.NK2 * 256 + (col & 15);
       // K row p-1 multiplies cos(p kz0 z), K row mz+p-1 multiplies sin(p kz0 z);
-      // the four B matrices give Re P, Im P, Re Pz, Im Pz
-      double* o = base + (size_t)((p - 1) >> 2) * 256 + 16 * ((p - 1) & 3);
+      // the four B matrices k = 0..3 give Re P, Im P, Re Pz, Im Pz.  A K step
+      // holds 256 entries: entry 128 (k >> 1) + 2 lane + (k & 1) for lane =
+      // column + 16 (K row & 3), so that a lane reads the B values of
+      // matrices 0, 1 and of 2, 3 as two 16-byte loads
+      double* base = wfrag + ((size_t)f * g.NG + (col >> 4)) * g.NK2 * 256 + 2 * (col & 15);
+      double* o = base + (size_t)((p - 1) >> 2) * 256 + 32 * ((p - 1) & 3);
       o[0] = Ap.x;
-      o[64] = Ap.y;
+      o[1] = Ap.y;
       o[128] = fp * Am.x;
-      o[192] = fp * Am.y;
+      o[129] = fp * Am.y;
       const int js = g.mz + p - 1;
-      o = base + (size_t)(js >> 2) * 256 + 16 * (js & 3);
+      o = base + (size_t)(js >> 2) * 256 + 32 * (js & 3);
       o[0] = Am.y;
-      o[64] = -Am.x;
+      o[1] = -Am.x;
       o[128] = fp * Ap.y;
-      o[192] = -fp * Ap.x;
+      o[129] = -fp * Ap.x;
     }
   }
 }
@@ -1536,7 +1539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
                                                        const double* __restrict__ ztab,
                                                        const double* __restrict__ wfrag,
                                                        const double2* __restrict__ wk0, double* __restrict__ fpart) {
-  __shared__ double bsh[2][NK * 256];
+  __shared__ __align__(16) double bsh[2][NK * 256];
   const int f = blockIdx.z;
   const FrameDev fr = get_frame(fa, f);
   const int lane = threadIdx.x & 63;
@@ -1597,7 +1600,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
         ey[t][r] = row[g.NX + iy];
       }
     const double2 w0 = wk0[(size_t)f * g.NG * 16 + grp * 16 + li];
-    const double* __restrict__ wg = bsh[cur] + lane;
+    const double* __restrict__ wg = bsh[cur] + 2 * lane;  // B values of a K step: 2 lane + {0, 1, 128, 129}
     v4d Pr[AT], Pi[AT], Zr[AT], Zi[AT];
 #pragma unroll
     for (int t = 0; t < AT; t++) {
@@ -1608,7 +1611,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AT == 1 ? 3
     }
 #pragma unroll
     for (int st = 0; st < NK; st++) {
-      const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
+      const double2 u = *reinterpret_cast<const double2*>(wg + st * 256);
+      const double2 v = *reinterpret_cast<const double2*>(wg + st * 256 + 128);
+      const double b0 = u.x, b1 = u.y, b2 = v.x, b3 = v.y;
 #pragma unroll
       for (int t = 0; t < AT; t++) {
         Pr[t] = mfma4(za[t][st], b0, Pr[t]);
@@ -1774,9 +1779,14 @@ DEV void force_mm_eyl_item(const Grid& g, const FrameDev& fr, int f, int tile, i
   static_assert(NK % BD == 0, "ring depth must divide the K steps");
   double bq[BD][4];
   auto wrsrc = [&](int grp) { return buf_rsrc(wff + (size_t)grp * NK * 256, NK * 256 * 8); };
+  // a lane's B values of K step st: matrices 0, 1 and 2, 3 as two 16-byte loads
   auto load_b = [&](__amdgpu_buffer_rsrc_t wr, int st, double (&b)[4]) {
-#pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = buf_load_f64(wr, lane * 8, st * 2048 + k * 512);
+    const double2 u = buf_load_c64(wr, lane * 16, st * 2048);
+    const double2 v = buf_load_c64(wr, lane * 16, st * 2048 + 1024);
+    b[0] = u.x;
+    b[1] = u.y;
+    b[2] = v.x;
+    b[3] = v.y;
   };
   int col = gbeg * 16 + li;
   int nx = col / g.NY, iy = col - nx * g.NY;
@@ -1935,10 +1945,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const double2 w0 = wk0[(size_t)f * g.NG * 16 + it * 16 + li];
         v4d Pr = v4d{w0.x, w0.x, w0.x, w0.x}, Pi = v4d{w0.y, w0.y, w0.y, w0.y};
         v4d Zr = v4d{0.0, 0.0, 0.0, 0.0}, Zi = v4d{0.0, 0.0, 0.0, 0.0};
-        const double* __restrict__ wg = wfrag + ((size_t)f * g.NG + it) * NK * 256 + lane;
+        const double* __restrict__ wg = wfrag + ((size_t)f * g.NG + it) * NK * 256 + 2 * lane;
 #pragma unroll
         for (int st = 0; st < NK; st++) {
-          const double b0 = wg[st * 256], b1 = wg[st * 256 + 64], b2 = wg[st * 256 + 128], b3 = wg[st * 256 + 192];
+          const double2 u = *reinterpret_cast<const double2*>(wg + st * 256);
+          const double2 v = *reinterpret_cast<const double2*>(wg + st * 256 + 128);
+          const double b0 = u.x, b1 = u.y, b2 = v.x, b3 = v.y;
           Pr = mfma4(za[st], b0, Pr);
           Pi = mfma4(za[st], b1, Pi);
           Zr = mfma4(za[st], b2, Zr);

@@ -97,14 +97,15 @@ hipError_t launch_tab32(const Grid& g, const FrameArg& fa, int max_nm, int cap_m
 }
 
 // folded adjoint weights of every frame (padding entries are zero in both).
-// A 256-entry K step holds the four B fragments (Re P, Im P, Re Pz, Im Pz) of
-// 64 lanes; the FP64 layout is fragment-major (entry 64 k + lane), the FP32
-// copy lane-major (entry 4 lane + k), so that a lane reads its four values of
-// a K step as one 16-byte load.
+// A 256-entry K step holds the four B fragments k = 0..3 (Re P, Im P, Re Pz,
+// Im Pz) of 64 lanes; the FP64 layout pairs them (entry 128 (k >> 1) + 2 lane
+// + (k & 1): two 16-byte loads per lane), the FP32 copy is lane-major (entry
+// 4 lane + k), so that a lane reads its four values of a K step as one
+// 16-byte load.
 __global__ __launch_bounds__(256) void k_wfrag32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const size_t blk = i >> 8;
-    const int rem = (int)(i & 255), k = rem >> 6, lane = rem & 63;
+    const int rem = (int)(i & 255), lane = (rem & 127) >> 1, k = 2 * (rem >> 7) + (rem & 1);
     dst[(blk << 8) + 4 * lane + k] = (float)src[i];
   }
 }
